@@ -1,0 +1,128 @@
+"""Gate-by-gate FP64 state-vector simulator (oracle side).
+
+psi(theta) = U(theta) psi_ref (eq. 6), with U a product of gates applied one
+at a time to 2^n complex128 amplitudes; memory 2^(n+4) bytes (Sec. I).
+No fusion, no reordering.
+
+Conventions (the paper, whose ansatz is built from S/D excitation gate sets
+(eq. 5), does not fix the matrices of the hardware-efficient ansatz used here):
+  qubit j = bit j of the basis index;
+  RY(t) = exp(-i t Y/2) = [[c, -s], [s, c]],  c = cos(t/2), s = sin(t/2);
+  RZ(t) = exp(-i t Z/2) = diag(e^{-it/2}, e^{+it/2});
+  RX(t) = exp(-i t X/2) = [[c, -is], [-is, c]];
+  CNOT(c -> t) maps |b> to |b xor (b_c << t)>;  CZ(a, b) = (-1)^{b_a b_b}.
+A circuit is a list of gates (kind, q0, q1, param_index, angle); a gate with
+param_index >= 0 takes its angle from the parameter vector, else ``angle``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+RY, RZ, RX, H, X, CNOT, CZ = "RY", "RZ", "RX", "H", "X", "CNOT", "CZ"
+ROTATIONS = (RY, RZ, RX)
+
+
+def basis_state(n, b=0):
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[b] = 1.0
+    return psi
+
+
+def gate_matrix(kind, angle=0.0):
+    c, s = math.cos(angle / 2.0), math.sin(angle / 2.0)
+    if kind == RY:
+        return np.array([[c, -s], [s, c]], dtype=np.complex128)
+    if kind == RZ:
+        return np.array([[complex(c, -s), 0], [0, complex(c, s)]], dtype=np.complex128)
+    if kind == RX:
+        return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
+    if kind == H:
+        r = 1.0 / math.sqrt(2.0)
+        return np.array([[r, r], [r, -r]], dtype=np.complex128)
+    if kind == X:
+        return np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    raise ValueError(kind)
+
+
+def generator(kind):
+    """G with R(t) = exp(-i t G / 2)."""
+    if kind == RY:
+        return np.array([[0, -1j], [1j, 0]])
+    if kind == RZ:
+        return np.array([[1, 0], [0, -1]], dtype=np.complex128)
+    if kind == RX:
+        return np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    raise ValueError(kind)
+
+
+def apply_1q(psi, n, q, U):
+    """Apply a 2x2 matrix U to qubit q; psi viewed as (2^(n-q-1), 2, 2^q)."""
+    v = psi.reshape(1 << (n - q - 1), 2, 1 << q)
+    a = v[:, 0, :].copy()
+    b = v[:, 1, :].copy()
+    v[:, 0, :] = U[0, 0] * a + U[0, 1] * b
+    v[:, 1, :] = U[1, 0] * a + U[1, 1] * b
+    return psi
+
+
+def apply_cnot(psi, n, c, t):
+    """Swap the target pairs inside the control = 1 slice."""
+    idx = np.arange(1 << n, dtype=np.int64)
+    sel = ((idx >> c) & 1 == 1) & ((idx >> t) & 1 == 0)
+    i0 = idx[sel]
+    i1 = i0 | (1 << t)
+    tmp = psi[i0].copy()
+    psi[i0] = psi[i1]
+    psi[i1] = tmp
+    return psi
+
+
+def apply_cz(psi, n, a, b):
+    idx = np.arange(1 << n, dtype=np.int64)
+    sel = ((idx >> a) & 1 == 1) & ((idx >> b) & 1 == 1)
+    psi[sel] *= -1.0
+    return psi
+
+
+def gate_angle(g, params):
+    kind, q0, q1, pidx, angle = g
+    return params[pidx] if pidx >= 0 else angle
+
+
+def apply_gate(psi, n, g, params, inverse=False):
+    kind, q0, q1, pidx, angle = g
+    if kind == CNOT:
+        return apply_cnot(psi, n, q0, q1)
+    if kind == CZ:
+        return apply_cz(psi, n, q0, q1)
+    U = gate_matrix(kind, gate_angle(g, params))
+    if inverse:
+        U = U.conj().T
+    return apply_1q(psi, n, q0, U)
+
+
+def run(n, gates, params, psi=None):
+    """psi = G_m ... G_1 psi_ref, one gate at a time (default psi_ref = |0...0>)."""
+    psi = basis_state(n) if psi is None else psi.copy()
+    for g in gates:
+        apply_gate(psi, n, g, params)
+    return psi
+
+
+def layered_ansatz(n, layers):
+    """L layers of [RY on every qubit; RZ on every qubit; CNOT q -> q+1 ladder].
+
+    Layer l uses theta[l*2n + q] for RY on qubit q and theta[l*2n + n + q] for
+    RZ on qubit q; the ladder runs q = 0 .. n-2 in ascending order.
+    """
+    gates = []
+    for l in range(layers):
+        for q in range(n):
+            gates.append((RY, q, -1, l * 2 * n + q, 0.0))
+        for q in range(n):
+            gates.append((RZ, q, -1, l * 2 * n + n + q, 0.0))
+        for q in range(n - 1):
+            gates.append((CNOT, q, q + 1, -1, 0.0))
+    return gates

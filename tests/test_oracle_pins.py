@@ -1,0 +1,306 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a worked closed form, a textbook
+result, an invariant of the mathematics, or brute force.  A mistake anywhere in
+the oracle (a dropped term, a wrong sign, a swapped index, a transposed
+operand) should fail at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import closed_forms as cf
+from oracle import ed, expect, grad, hamiltonian as ham, slim
+from oracle import statevector as sv
+
+
+# ------------------------------------------------------------------ Hamiltonians
+def test_jw_two_site_hubbard_worked_form():
+    """2-site Hubbard (4 qubits) written out by hand (Sec. II-B, eqs. 1-4):
+    I: U/2; Z_j: -U/4; Z0Z1, Z2Z3: +U/4; X0Z1X2, Y0Z1Y2, X1Z2X3, Y1Z2Y3: -t/2."""
+    t, U = 1.3, 4.7
+    H = ham.hubbard(2, [(0, 1)], t, U)
+    want = {
+        "IIII": U / 2, "ZIII": -U / 4, "IZII": -U / 4, "IIZI": -U / 4, "IIIZ": -U / 4,
+        "ZZII": U / 4, "IIZZ": U / 4,
+        "XZXI": -t / 2, "YZYI": -t / 2, "IXZX": -t / 2, "IYZY": -t / 2,
+    }
+    got = {"".join(k): v for k, v in H.items()}
+    assert set(got) == set(want)
+    for k in want:
+        assert abs(got[k] - want[k]) < 1e-14, k
+
+
+@pytest.mark.parametrize("name,terms,groups", [
+    ("hubbard1d_6", 39, 11), ("hubbard2x7", 127, 43), ("hubbard4x4", 145, 49)])
+def test_hubbard_counts_closed_form(name, terms, groups):
+    """Terms = 4E + 3N + 1 and X-groups = 2E + 1 for E bonds and N sites."""
+    lat = synth.WORKLOADS[name].lattice
+    E, N = len(lat.bonds), lat.n_sites
+    assert (4 * E + 3 * N + 1, 2 * E + 1) == (terms, groups)
+    H = ham.hubbard(lat.n_sites, list(lat.bonds), lat.t, lat.U)
+    x, z, w = ham.to_masks(H)
+    assert len(w) == terms
+    assert len(set(x.tolist())) == groups
+
+
+def test_two_site_hubbard_ed_closed_forms():
+    """Global ground energy -t at U=4 (one electron); -2t at U=0 (free fermions);
+    half-filling singlet (U - sqrt(U^2+16t^2))/2 is an eigenvalue."""
+    H4 = ham.hubbard(2, [(0, 1)], 1.0, 4.0)
+    ev = np.linalg.eigvalsh(ed.dense(H4, 4))
+    assert abs(ev[0] - (-1.0)) < 1e-12
+    assert np.min(np.abs(ev - (4 - math.sqrt(32)) / 2)) < 1e-12
+    H0 = ham.hubbard(2, [(0, 1)], 1.0, 0.0)
+    assert abs(ed.ground_energy(H0, 4) - (-2.0)) < 1e-12
+
+
+@pytest.mark.parametrize("sites,bonds", [
+    (4, synth.chain_bonds(4)), (6, synth.chain_bonds(6)), (6, synth.snake_bonds(2, 3, False))])
+def test_free_fermion_energy_matches_ed(sites, bonds):
+    """At U = 0, ED over the full Fock space equals twice the sum of the negative
+    single-particle hopping levels."""
+    H = ham.hubbard(sites, bonds, 1.0, 0.0)
+    n = 2 * sites
+    assert abs(ed.ground_energy(H, n) - ed.free_fermion_energy(sites, bonds, 1.0)) < 1e-9
+
+
+def test_dense_and_sparse_matrices_agree():
+    """Kronecker-built dense H equals the signed-permutation sparse H."""
+    H = ham.hubbard(3, synth.chain_bonds(3), 1.0, 2.5)
+    D = ed.dense(H, 6)
+    S = ed.sparse(H, 6).toarray()
+    assert np.max(np.abs(D - S)) < 1e-13
+    assert np.max(np.abs(D - D.conj().T)) < 1e-13
+
+
+def test_molecule_one_orbital_spectrum():
+    """One spatial orbital: H = h (n_up + n_dn) + g n_up n_dn, spectrum {0, h, h, 2h+g}."""
+    h = np.array([[0.7]])
+    g = np.full((1, 1, 1, 1), 0.3)
+    H = ham.molecule(h, g)
+    ev = np.sort(np.linalg.eigvalsh(ed.dense(H, 2)))
+    assert np.allclose(ev, np.sort([0.0, 0.7, 0.7, 2 * 0.7 + 0.3]), atol=1e-13)
+
+
+def test_molecule_symmetries():
+    """Molecule-shaped H is Hermitian and conserves particle number and S_z."""
+    h, g = synth.molecule_integrals(3, seed=5)
+    H = ham.molecule(h, g)
+    n = 6
+    D = ed.dense(H, n)
+    assert np.max(np.abs(D - D.conj().T)) < 1e-13
+    b = np.arange(1 << n)
+    occ = np.array([[(bb >> j) & 1 for j in range(n)] for bb in b])
+    Nop = np.diag(occ.sum(1)).astype(float)
+    Sz = np.diag(occ[:, 0::2].sum(1) - occ[:, 1::2].sum(1)).astype(float)
+    assert np.max(np.abs(D @ Nop - Nop @ D)) < 1e-12
+    assert np.max(np.abs(D @ Sz - Sz @ D)) < 1e-12
+
+
+def test_molecule_matches_one_body_diagonal():
+    """With g = 0, H = sum_pq h_pq a+_p a_q: its single-particle block is h (per spin)."""
+    h, _ = synth.molecule_integrals(3, seed=2)
+    H = ham.molecule(h, np.zeros((3, 3, 3, 3)))
+    D = ed.dense(H, 6)
+    one = [1 << j for j in range(0, 6, 2)]           # one up electron in orbital p
+    block = D[np.ix_(one, one)]
+    assert np.max(np.abs(block - h)) < 1e-13
+
+
+def test_mask_round_trip():
+    H = ham.hubbard(3, synth.chain_bonds(3), 1.0, 3.0)
+    x, z, w = ham.to_masks(H)
+    back = ham.from_masks(6, x, z, w)
+    assert back == H
+
+
+# ------------------------------------------------------------------ simulator
+@pytest.mark.parametrize("t,p", [(0.3, -1.1), (2.9, 0.4), (-1.7, 2.2)])
+def test_single_qubit_bloch(t, p):
+    """RZ(p) RY(t)|0> has Bloch vector (sin t cos p, sin t sin p, cos t)."""
+    psi = sv.run(1, [("RY", 0, -1, 0, 0.0), ("RZ", 0, -1, 1, 0.0)], [t, p])
+    vals = [expect.expect_term_masks(psi, 1, x, z).real for (x, z) in ((1, 0), (1, 1), (0, 1))]
+    assert np.allclose(vals, cf.bloch_ry_rz(t, p), atol=1e-14)
+
+
+def test_cnot_truth_table():
+    """CNOT(0 -> 1): |00>->|00>, |01>->|11>, |10>->|10>, |11>->|01> (bit 0 = control)."""
+    for b, want in ((0, 0), (1, 3), (2, 2), (3, 1)):
+        psi = sv.apply_cnot(sv.basis_state(2, b), 2, 0, 1)
+        assert psi[want] == 1.0
+
+
+@pytest.mark.parametrize("n", [3, 7, 11])
+def test_ladder_prefix_xor(n):
+    """The ascending CNOT ladder maps |b> to |M b>, (M b)_j = b_0 ^ ... ^ b_j."""
+    gates = [("CNOT", q, q + 1, -1, 0.0) for q in range(n - 1)]
+    rng = np.random.default_rng(n)
+    for b in rng.integers(0, 1 << n, size=8):
+        psi = sv.run(n, gates, [], psi=sv.basis_state(n, int(b)))
+        assert psi[cf.ladder_map(int(b), n)] == 1.0
+
+
+@pytest.mark.parametrize("n", [4, 9])
+def test_one_layer_closed_form(n):
+    """One ansatz layer: <P> from Clifford conjugation of P through the ladder and
+    the per-qubit Bloch vectors equals the simulated value."""
+    rng = np.random.default_rng(7 + n)
+    th = rng.uniform(-math.pi, math.pi, size=2 * n)
+    psi = sv.run(n, sv.layered_ansatz(n, 1), th)
+    for _ in range(25):
+        x, z = int(rng.integers(0, 1 << n)), int(rng.integers(0, 1 << n))
+        want = cf.one_layer_expectation(n, th[:n], th[n:], x, z)
+        got = expect.expect_term_masks(psi, n, x, z).real
+        assert abs(got - want) < 1e-12
+
+
+@pytest.mark.parametrize("n,layers", [(5, 6), (8, 4)])
+def test_clifford_tableau_matches_simulation(n, layers):
+    """Angles in {0, +-pi/2, pi}: stabiliser-tableau <P> equals the simulated value."""
+    rng = np.random.default_rng(n * 10 + layers)
+    th = rng.choice([0.0, math.pi / 2, -math.pi / 2, math.pi], size=2 * n * layers)
+    gates = sv.layered_ansatz(n, layers)
+    psi = sv.run(n, gates, th)
+    terms = [(int(rng.integers(0, 1 << n)), int(rng.integers(0, 1 << n))) for _ in range(40)]
+    terms += [(0, 1 << q) for q in range(n)]
+    want = cf.clifford_expectations(n, gates, th, terms)
+    for (x, z), w in zip(terms, want):
+        assert abs(expect.expect_term_masks(psi, n, x, z).real - w) < 1e-12
+
+
+def test_norm_and_inverse():
+    """Unitary gates preserve the norm; applying U then U^dag returns |0...0>."""
+    n = 8
+    gates = sv.layered_ansatz(n, 3)
+    th = synth.theta(3, 2 * n * 3)
+    psi = sv.run(n, gates, th)
+    assert abs(np.vdot(psi, psi).real - 1.0) < 1e-12
+    for g in reversed(gates):
+        sv.apply_gate(psi, n, g, th, inverse=True)
+    assert abs(psi[0] - 1.0) < 1e-12
+    assert np.max(np.abs(psi[1:])) < 1e-12
+
+
+def test_theta_zero_energy():
+    """At theta = 0 the state stays |0...0>: E = sum of w over the x = 0 terms."""
+    lat = synth.WORKLOADS["hubbard1d_6"].lattice
+    H = ham.hubbard(lat.n_sites, list(lat.bonds), lat.t, lat.U)
+    n = 12
+    psi = sv.run(n, sv.layered_ansatz(n, 2), np.zeros(4 * n))
+    E, _ = expect.energy(psi, n, H)
+    x, z, w = ham.to_masks(H)
+    assert abs(E - math.fsum(w[x == 0])) < 1e-12
+
+
+def test_expectation_routes_agree():
+    """Per-qubit sigma route and the vectorised b^x route give the same <P>."""
+    n = 7
+    psi = sv.run(n, sv.layered_ansatz(n, 2), synth.theta(11, 4 * n))
+    rng = np.random.default_rng(0)
+    for _ in range(30):
+        s = tuple(rng.choice(list("IXYZ"), size=n))
+        x, z = expect.string_masks(s)
+        a = expect.expect_term_gates(psi, n, s)
+        b = expect.expect_term_masks(psi, n, x, z)
+        assert abs(a - b) < 1e-13
+
+
+def test_variational_bound_config0():
+    """E(theta) >= E_0 (ED) for the 12-qubit 6-site chain at random angles."""
+    wl = synth.WORKLOADS["hubbard1d_6"]
+    lat = wl.lattice
+    H = ham.hubbard(lat.n_sites, list(lat.bonds), lat.t, lat.U)
+    E0 = ed.ground_energy(H, 12)
+    assert E0 >= ed.free_fermion_energy(lat.n_sites, list(lat.bonds), lat.t) - 1e-9
+    for s in range(3):
+        th = synth.theta(s, wl.n_params)
+        E, norm = expect.energy(sv.run(12, sv.layered_ansatz(12, wl.layers), th), 12, H)
+        assert E >= E0 - 1e-10
+        assert abs(norm - 1) < 1e-12
+
+
+# ------------------------------------------------------------------ gradients
+def test_gradients_three_ways():
+    """Parameter shift (exact), central differences and the adjoint sweep agree."""
+    n, layers = 6, 2
+    H = ham.hubbard(3, synth.chain_bonds(3), 1.0, 4.0)
+    gates = sv.layered_ansatz(n, layers)
+    th = synth.theta(4, 2 * n * layers)
+    E, g_adj = grad.adjoint(n, gates, th, H)
+    ps = grad.param_shift(n, gates, th, H)
+    fd = grad.finite_diff(n, gates, th, H, indices=range(0, 24, 5))
+    g_ps = np.array([ps[k] for k in range(len(th))])
+    assert np.max(np.abs(g_adj - g_ps)) < 1e-12
+    for k, v in fd.items():
+        assert abs(v - g_ps[k]) < 1e-7
+    assert abs(E - expect.energy(sv.run(n, gates, th), n, H)[0]) < 1e-13
+
+
+def test_parameter_shift_single_rotation_closed_form():
+    """E = <Z> after RY(t): cos t, derivative -sin t."""
+    H = {("Z",): 1.0}
+    for t in (0.3, -2.0):
+        g = grad.param_shift(1, [("RY", 0, -1, 0, 0.0)], [t], H)[0]
+        assert abs(g + math.sin(t)) < 1e-14
+
+
+# ------------------------------------------------------------------ slimming
+def _rand_terms(seed, n_terms=200, ties=False):
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, 1 << 10, size=n_terms).astype(np.uint64)
+    z = rng.integers(0, 1 << 10, size=n_terms).astype(np.uint64)
+    w = rng.normal(size=n_terms) * 10.0 ** rng.uniform(-6, 0, size=n_terms)
+    if ties:
+        w = np.round(w * 4) / 4 + 0.0
+        w[w == 0] = 0.25
+    x[0] = z[0] = 0
+    return x, z, w
+
+
+@pytest.mark.parametrize("seed,ties", [(0, False), (1, True), (2, True)])
+def test_slim_threshold_bruteforce(seed, ties):
+    """Keep iff |w| >= Th, identity always kept; dropped sum bounds |dE| (Sec. II-D)."""
+    x, z, w = _rand_terms(seed, ties=ties)
+    for th in (0.0, 1e-4, 0.25, float(np.abs(w[5]))):
+        keep, dropped = slim.threshold(x, z, w, th)
+        want = np.array([1 if (i == 0 or abs(w[i]) >= th) else 0 for i in range(len(w))])
+        assert np.array_equal(keep, want)
+        assert abs(dropped - math.fsum(abs(v) for v in w[want == 0])) < 1e-12
+    keep0, d0 = slim.threshold(x, z, w, 0.0)
+    assert keep0.all() and d0 == 0.0
+
+
+@pytest.mark.parametrize("seed,ties", [(3, False), (4, True)])
+def test_slim_remove_percent_and_budget(seed, ties):
+    x, z, w = _rand_terms(seed, ties=ties)
+    N = len(w) - 1
+    for pct in (0, 10, 33, 70, 100):
+        keep, dropped = slim.remove_percent(x, z, w, pct)
+        assert int((keep == 0).sum()) == (N * pct) // 100
+        if 0 < pct < 100:       # every dropped |w| <= every kept non-identity |w|
+            assert np.abs(w[keep == 0]).max() <= np.abs(w[1:][keep[1:] == 1]).min()
+    for lim in (0.0, 1e-3, 0.5, 1e9):
+        keep, s = slim.budget(x, z, w, lim)
+        assert s <= lim
+        assert keep[0] == 1
+        kept = np.abs(w[1:][keep[1:] == 1])
+        if len(kept):
+            assert s + kept.min() > lim     # the next term would exceed the budget
+
+
+def test_slim_energy_bound():
+    """|E_full - E_slim| <= sum of dropped |w| for a normalised state (Sec. II-D)."""
+    h, g = synth.molecule_integrals(3, seed=1)
+    H = ham.molecule(h, g)
+    x, z, w = ham.to_masks(H)
+    n = 6
+    psi = sv.run(n, sv.layered_ansatz(n, 3), synth.theta(9, 36))
+    E_full, _ = expect.energy_masks(psi, n, x, z, w)
+    for th in (1e-4, 1e-3, 1e-2, 1e-1):
+        keep, dropped = slim.threshold(x, z, w, th)
+        k = keep == 1
+        E_slim, _ = expect.energy_masks(psi, n, x[k], z[k], w[k])
+        assert slim.dropped_bound_check(E_full, E_slim, dropped)
