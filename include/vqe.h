@@ -1,0 +1,223 @@
+/*
+ * vqe.h -- C ABI of the MI355X (gfx950) VQE state-vector library.
+ *
+ * The library evaluates the variational quantum eigensolver objective of
+ * Morita et al., "Simulator Demonstration of Large Scale Variational Quantum
+ * Algorithm on HPC Cluster" (arXiv 2402.11878):
+ *   psi(theta) = U(theta) psi_ref                          (Sec. II-B, eq. 6)
+ *   E(theta)   = <psi|H|psi> / <psi|psi>                   (Sec. II-B, eq. 7)
+ *   H          = sum_i w_i P_i,  P_i = (x) sigma_k, sigma in {I,X,Y,Z}  (eqs. 2-4)
+ * with the Hamiltonian optionally slimmed by dropping terms of small |w|
+ * (Sec. II-D, Sec. III-D), the drop being bounded by |<psi|wP|psi>| <= |w|.
+ *
+ * Conventions used by every entry point
+ *   - Qubit j is bit j (value 2^j) of the basis index.  A state of n qubits is
+ *     2^n contiguous interleaved complex amplitudes (re, im), index = basis
+ *     integer: complex64 (2 x float) or complex128 (2 x double).
+ *   - A Pauli string is a pair of bit masks (x, z): (x_j, z_j) = (0,0) I,
+ *     (1,0) X, (0,1) Z, (1,1) Y, i.e. P(x,z) = i^popcount(x&z) X^x Z^z.
+ *   - RY(t) = exp(-i t Y/2), RZ(t) = exp(-i t Z/2), RX(t) = exp(-i t X/2);
+ *     CNOT(c -> t) maps |b> to |b xor (b_c << t)>.
+ *   - All device work of a call is enqueued on the stream of the state handle
+ *     (a hipStream_t given at allocation; NULL = the null stream).  Calls that
+ *     return host scalars synchronise that stream before returning.
+ *
+ * Errors
+ *   Every function returns VQE_OK (0) or a negative status.  No C++ exception
+ *   crosses the ABI.  On error the outputs are left untouched and
+ *   vqe_last_error() returns a message (thread-local, valid until the next
+ *   call on the same thread).
+ *
+ * Ownership
+ *   The caller owns every host array passed in; the library copies what it
+ *   keeps.  Handles own their device tables and are released by the matching
+ *   *_free call.  A handle may not be used from two threads at once.
+ */
+#ifndef VQE_H_
+#define VQE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define VQE_OK               0
+#define VQE_ERR_ARG         -1  /* invalid argument (null, size, range, mismatch) */
+#define VQE_ERR_OOM         -2  /* device or host allocation failed */
+#define VQE_ERR_DEVICE      -3  /* HIP runtime error or no usable device */
+#define VQE_ERR_UNSUPPORTED -4  /* valid request the library does not implement */
+#define VQE_ERR_STATE       -5  /* handle in the wrong state for this call */
+
+/* ---- amplitude types ---- */
+#define VQE_C64   1   /* complex64: float re, float im (8 bytes per amplitude)   */
+#define VQE_C128  2   /* complex128: double re, double im (16 bytes per amplitude) */
+
+/* ---- gate kinds ---- */
+#define VQE_GATE_RY    0
+#define VQE_GATE_RZ    1
+#define VQE_GATE_RX    2
+#define VQE_GATE_H     3
+#define VQE_GATE_X     4
+#define VQE_GATE_CNOT  5   /* q0 = control, q1 = target */
+#define VQE_GATE_CZ    6
+
+/* ---- expectation modes ---- */
+#define VQE_EXPECT_GROUPED   0  /* one sweep per X-mask group serves every Z pattern */
+#define VQE_EXPECT_PER_TERM  1  /* one sweep per Pauli term (Sec. III-D evaluation order) */
+
+/* ---- gradient methods ---- */
+#define VQE_GRAD_ADJOINT      0  /* reverse sweep un-applying one gate at a time */
+#define VQE_GRAD_PARAM_SHIFT  1  /* [E(t + pi/2 e_k) - E(t - pi/2 e_k)] / 2 per parameter */
+
+/* ---- slimming modes (Sec. II-D, III-D) ---- */
+#define VQE_SLIM_THRESHOLD       0  /* keep iff |w| >= value */
+#define VQE_SLIM_REMOVE_PERCENT  1  /* remove floor(N * value / 100) smallest terms */
+#define VQE_SLIM_BUDGET          2  /* remove smallest terms while sum |w| <= value */
+
+typedef struct vqe_state vqe_state;
+typedef struct vqe_circuit vqe_circuit;
+typedef struct vqe_hamiltonian vqe_hamiltonian;
+
+/* One gate.  A gate with param_index >= 0 takes its angle from the parameter
+ * vector passed at evaluation time, else from `angle`.  Only RY, RZ and RX
+ * may be parameterised.  q1 is used by CNOT and CZ only. */
+typedef struct vqe_gate {
+    uint8_t kind;
+    uint8_t q0;
+    uint8_t q1;
+    uint8_t reserved;
+    int32_t param_index;
+    double angle;
+} vqe_gate;
+
+/* Options of vqe_energy_grad. */
+typedef struct vqe_grad_opts {
+    int32_t method;        /* VQE_GRAD_ADJOINT or VQE_GRAD_PARAM_SHIFT */
+    int32_t expect_mode;   /* energy evaluation used by PARAM_SHIFT: VQE_EXPECT_* */
+    int32_t n_ckpt;        /* number of checkpoint states in ckpt (ADJOINT only; may be 0) */
+    int32_t reserved;
+    vqe_state* const* ckpt;/* n_ckpt states of the same n and dtype as psi; their
+                              contents are overwritten */
+} vqe_grad_opts;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* vqe_last_error(void);
+
+/* Library version, e.g. "1.0.0". */
+const char* vqe_version(void);
+
+/* Number of HIP devices visible (0 when none); never fails. */
+int vqe_device_count(void);
+
+/* ------------------------------------------------------------------ states
+ * A state holds 2^n amplitudes (memory 2^(n+3) or 2^(n+4) bytes, Sec. I).
+ *   n_qubits   1 .. 40
+ *   dtype      VQE_C64 or VQE_C128
+ *   device_buf device memory of at least buf_bytes >= 2^n * amplitude size,
+ *              BORROWED (it must outlive the handle), or NULL: the library
+ *              allocates and owns the memory.
+ *   hip_stream hipStream_t on which all work of this state is enqueued.
+ * The new state is |0...0>. */
+int vqe_state_alloc(int n_qubits, int dtype, void* device_buf, size_t buf_bytes,
+                    void* hip_stream, vqe_state** out);
+int vqe_state_free(vqe_state* s);
+
+/* psi = |b>, the basis state with index b < 2^n (eq. 6 with psi_ref = |b>). */
+int vqe_state_set_basis(vqe_state* s, uint64_t basis_index);
+
+/* Device pointer, qubit count and dtype of a state. */
+int vqe_state_info(const vqe_state* s, void** device_ptr, int* n_qubits, int* dtype);
+
+/* Copy `count` amplitudes starting at `offset` to / from host memory
+ * (interleaved re, im of the state's dtype).  Synchronous. */
+int vqe_state_read(const vqe_state* s, uint64_t offset, uint64_t count, void* host_dst);
+int vqe_state_write(vqe_state* s, uint64_t offset, uint64_t count, const void* host_src);
+
+/* ------------------------------------------------------------------ circuits
+ * U(theta) as an ordered gate list (applied first to last).  Creating a
+ * circuit plans its fused passes: gates are grouped into windows of at most
+ * 5 qubits, one HBM read and write of the state per window, respecting the
+ * order of every gate pair that shares a qubit. */
+int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_circuit** out);
+int vqe_circuit_free(vqe_circuit* c);
+
+/* n_params = 1 + the largest param_index used (0 if none); n_passes = fused
+ * state sweeps per application. */
+int vqe_circuit_info(const vqe_circuit* c, size_t* n_params, size_t* n_passes);
+
+/* Inspection of the fused plan used for states of `dtype`: pass `pass` has a
+ * window of *window qubits (listed ascending in qubits[0..*window-1], at most
+ * 5 entries) and applies *n_gates gates whose indices into the circuit's
+ * gate list, in execution order, are written to gate_index (capacity
+ * entries; may be NULL to query the count).  Host only. */
+int vqe_circuit_pass(const vqe_circuit* c, int dtype, size_t pass, int* window, int* qubits,
+                     size_t* n_gates, int32_t* gate_index, size_t capacity);
+
+/* psi <- U(params) psi  (eq. 6).  params has n_params doubles (host). */
+int vqe_apply_circuit(vqe_state* s, const vqe_circuit* c, const double* params, size_t n_params);
+
+/* ------------------------------------------------------------------ Hamiltonians
+ * H = sum_i w_i P(x_i, z_i)  (eqs. 2-4).  Masks must have no bit >= n and the
+ * weights must be finite.  Repeated (x, z) pairs are summed.  The terms are
+ * grouped by x mask and the phase i^popcount(x&z) is folded into signed real
+ * or imaginary coefficients; the tables are uploaded to the current device. */
+int vqe_hamiltonian_create(int n_qubits, const uint64_t* x, const uint64_t* z, const double* w,
+                           size_t n_terms, vqe_hamiltonian** out);
+int vqe_hamiltonian_free(vqe_hamiltonian* h);
+
+/* Number of distinct terms, of X-mask groups (the identity counted with the
+ * diagonal group), and the identity coefficient. */
+int vqe_hamiltonian_info(const vqe_hamiltonian* h, size_t* n_terms, size_t* n_groups,
+                         double* identity_weight);
+
+/* energy = <psi|H|psi> / <psi|psi>  (eq. 7); norm (nullable) = <psi|psi>.
+ * mode VQE_EXPECT_GROUPED sweeps the state once per X-mask group,
+ * VQE_EXPECT_PER_TERM once per term.  Reductions across blocks are FP64 in a
+ * fixed order, so repeated calls give identical bits. */
+int vqe_expect_pauli(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy, double* norm);
+
+/* lam <- H psi (out of place) and energy = Re<psi|lam>/<psi|psi>. */
+int vqe_apply_hamiltonian(vqe_state* psi, vqe_state* lam, const vqe_hamiltonian* h,
+                          double* energy, double* norm);
+
+/* Energy of psi(theta) = U(theta)|0...0> and its gradient dE/dtheta_k for all
+ * k (grad has n_params doubles).
+ *   ADJOINT: forward sweep, lam = H psi, then one reverse sweep un-applying
+ *     one gate at a time from psi and lam, with dE/dtheta_k = Im<lam|G_k|psi>
+ *     / <psi|psi> just after gate k, R_k = exp(-i theta_k G_k / 2).  lam must
+ *     be a distinct state of the same n and dtype.  With n_ckpt > 0 forward
+ *     states are kept at evenly spaced pass boundaries and restored during the
+ *     reverse sweep, which bounds the drift of the un-applied psi.
+ *   PARAM_SHIFT: 2 n_params + 1 circuit runs (the independent circuit runs of
+ *     Sec. II-C), energies by opts->expect_mode; lam is unused (may be NULL).
+ * psi is overwritten; on return it holds U(theta)|0> for PARAM_SHIFT and the
+ * reference |0...0> (up to rounding) for ADJOINT. */
+int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,
+                    const double* params, size_t n_params, const vqe_hamiltonian* h,
+                    const vqe_grad_opts* opts, double* energy, double* grad);
+
+/* ------------------------------------------------------------------ slimming
+ * Hamiltonian cutoff (Sec. II-D; terms sorted by |w|, small ones dropped).
+ * Host only.  The identity term (x = z = 0) is always kept.  The order of
+ * importance is (|w| descending, x ascending, z ascending).
+ *   THRESHOLD:       keep iff |w| >= value (value >= 0).
+ *   REMOVE_PERCENT:  value = integer percentage p in [0, 100]; drop the last
+ *                    floor(N p / 100) non-identity terms of that order.
+ *   BUDGET:          walk that order from its end adding |w| into an FP64
+ *                    running sum; drop while the sum stays <= value.
+ * keep[i] (out, n_terms bytes) = 1 to keep term i, else 0; n_kept (nullable)
+ * = number kept; dropped_abs_sum (nullable) = sum of the dropped |w|, added in
+ * ascending order of importance: a bound on |E_full - E_slim| for any
+ * normalised state (Sec. II-D). */
+int vqe_slim_hamiltonian(const uint64_t* x, const uint64_t* z, const double* w, size_t n_terms,
+                         int mode, double value, uint8_t* keep, size_t* n_kept,
+                         double* dropped_abs_sum);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VQE_H_ */

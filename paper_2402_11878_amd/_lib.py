@@ -1,0 +1,225 @@
+"""ctypes binding of libvqe.so: one Python function per C entry point.
+
+Argument marshalling only; every step of the computation runs in the
+library.  Importing this module loads the in-tree libvqe.so and raises if it
+is missing (build it with ``python -m paper_2402_11878_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvqe.so")
+
+VQE_OK, VQE_ERR_ARG, VQE_ERR_OOM, VQE_ERR_DEVICE, VQE_ERR_UNSUPPORTED, VQE_ERR_STATE = 0, -1, -2, -3, -4, -5
+VQE_C64, VQE_C128 = 1, 2
+GATE_RY, GATE_RZ, GATE_RX, GATE_H, GATE_X, GATE_CNOT, GATE_CZ = range(7)
+EXPECT_GROUPED, EXPECT_PER_TERM = 0, 1
+GRAD_ADJOINT, GRAD_PARAM_SHIFT = 0, 1
+SLIM_THRESHOLD, SLIM_REMOVE_PERCENT, SLIM_BUDGET = 0, 1, 2
+
+
+class VqeError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+class vqe_gate(C.Structure):
+    _fields_ = [("kind", C.c_uint8), ("q0", C.c_uint8), ("q1", C.c_uint8), ("reserved", C.c_uint8),
+                ("param_index", C.c_int32), ("angle", C.c_double)]
+
+
+class vqe_grad_opts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("expect_mode", C.c_int32), ("n_ckpt", C.c_int32),
+                ("reserved", C.c_int32), ("ckpt", C.POINTER(C.c_void_p))]
+
+
+GATE_DTYPE = np.dtype([("kind", "u1"), ("q0", "u1"), ("q1", "u1"), ("reserved", "u1"),
+                       ("param_index", "<i4"), ("angle", "<f8")], align=True)
+assert GATE_DTYPE.itemsize == C.sizeof(vqe_gate) == 16
+
+_P = C.c_void_p
+_SZ = C.c_size_t
+_SIGS = {
+    "vqe_last_error": (C.c_char_p, []),
+    "vqe_version": (C.c_char_p, []),
+    "vqe_device_count": (C.c_int, []),
+    "vqe_state_alloc": (C.c_int, [C.c_int, C.c_int, _P, _SZ, _P, C.POINTER(_P)]),
+    "vqe_state_free": (C.c_int, [_P]),
+    "vqe_state_set_basis": (C.c_int, [_P, C.c_uint64]),
+    "vqe_state_info": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "vqe_state_read": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P]),
+    "vqe_state_write": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P]),
+    "vqe_circuit_create": (C.c_int, [C.c_int, _P, _SZ, C.POINTER(_P)]),
+    "vqe_circuit_free": (C.c_int, [_P]),
+    "vqe_circuit_info": (C.c_int, [_P, C.POINTER(_SZ), C.POINTER(_SZ)]),
+    "vqe_circuit_pass": (C.c_int, [_P, C.c_int, _SZ, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.POINTER(_SZ), C.POINTER(C.c_int32), _SZ]),
+    "vqe_apply_circuit": (C.c_int, [_P, _P, C.POINTER(C.c_double), _SZ]),
+    "vqe_hamiltonian_create": (C.c_int, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                         C.POINTER(C.c_double), _SZ, C.POINTER(_P)]),
+    "vqe_hamiltonian_free": (C.c_int, [_P]),
+    "vqe_hamiltonian_info": (C.c_int, [_P, C.POINTER(_SZ), C.POINTER(_SZ), C.POINTER(C.c_double)]),
+    "vqe_expect_pauli": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vqe_apply_hamiltonian": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vqe_energy_grad": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double), _SZ, _P, C.POINTER(vqe_grad_opts),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vqe_slim_hamiltonian": (C.c_int, [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_double),
+                                       _SZ, C.c_int, C.c_double, C.POINTER(C.c_uint8), C.POINTER(_SZ),
+                                       C.POINTER(C.c_double)]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if libvqe.so has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_11878_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def check(fn, rc):
+    if rc != VQE_OK:
+        raise VqeError(fn, rc, lib().vqe_last_error().decode(errors="replace"))
+    return rc
+
+
+def _arr(a, dtype, ctype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.POINTER(ctype))
+
+
+# ----------------------------------------------------------------- thin wrappers
+def vqe_version():
+    return lib().vqe_version().decode()
+
+
+def vqe_device_count():
+    return lib().vqe_device_count()
+
+
+def vqe_state_alloc(n_qubits, dtype, device_buf=None, buf_bytes=0, hip_stream=None):
+    out = _P()
+    check("vqe_state_alloc", lib().vqe_state_alloc(n_qubits, dtype, device_buf, buf_bytes, hip_stream, C.byref(out)))
+    return out.value
+
+
+def vqe_state_free(s):
+    check("vqe_state_free", lib().vqe_state_free(s))
+
+
+def vqe_state_set_basis(s, b):
+    check("vqe_state_set_basis", lib().vqe_state_set_basis(s, b))
+
+
+def vqe_state_read(s, offset, count, dtype):
+    out = np.empty(count, dtype=np.complex64 if dtype == VQE_C64 else np.complex128)
+    check("vqe_state_read", lib().vqe_state_read(s, offset, count, out.ctypes.data))
+    return out
+
+
+def vqe_state_write(s, offset, values, dtype):
+    v = np.ascontiguousarray(values, dtype=np.complex64 if dtype == VQE_C64 else np.complex128)
+    check("vqe_state_write", lib().vqe_state_write(s, offset, len(v), v.ctypes.data))
+
+
+def vqe_circuit_create(n_qubits, gates):
+    g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+    out = _P()
+    check("vqe_circuit_create", lib().vqe_circuit_create(n_qubits, g.ctypes.data, len(g), C.byref(out)))
+    return out.value
+
+
+def vqe_circuit_free(c):
+    check("vqe_circuit_free", lib().vqe_circuit_free(c))
+
+
+def vqe_circuit_info(c):
+    npar, npass = _SZ(), _SZ()
+    check("vqe_circuit_info", lib().vqe_circuit_info(c, C.byref(npar), C.byref(npass)))
+    return npar.value, npass.value
+
+
+def vqe_circuit_pass(c, dtype, p):
+    K = C.c_int()
+    q = (C.c_int * 5)()
+    ng = _SZ()
+    check("vqe_circuit_pass", lib().vqe_circuit_pass(c, dtype, p, C.byref(K), q, C.byref(ng), None, 0))
+    idx = (C.c_int32 * max(ng.value, 1))()
+    check("vqe_circuit_pass", lib().vqe_circuit_pass(c, dtype, p, None, None, None, idx, ng.value))
+    return list(q)[: K.value], list(idx)[: ng.value]
+
+
+def vqe_apply_circuit(s, c, params):
+    p, pp = _arr(params, np.float64, C.c_double)
+    check("vqe_apply_circuit", lib().vqe_apply_circuit(s, c, pp, len(p)))
+
+
+def vqe_hamiltonian_create(n_qubits, x, z, w):
+    x, xp = _arr(x, np.uint64, C.c_uint64)
+    z, zp = _arr(z, np.uint64, C.c_uint64)
+    w, wp = _arr(w, np.float64, C.c_double)
+    out = _P()
+    check("vqe_hamiltonian_create", lib().vqe_hamiltonian_create(n_qubits, xp, zp, wp, len(w), C.byref(out)))
+    return out.value
+
+
+def vqe_hamiltonian_free(h):
+    check("vqe_hamiltonian_free", lib().vqe_hamiltonian_free(h))
+
+
+def vqe_hamiltonian_info(h):
+    nt, ng, idw = _SZ(), _SZ(), C.c_double()
+    check("vqe_hamiltonian_info", lib().vqe_hamiltonian_info(h, C.byref(nt), C.byref(ng), C.byref(idw)))
+    return nt.value, ng.value, idw.value
+
+
+def vqe_expect_pauli(s, h, mode=EXPECT_GROUPED):
+    e, n = C.c_double(), C.c_double()
+    check("vqe_expect_pauli", lib().vqe_expect_pauli(s, h, mode, C.byref(e), C.byref(n)))
+    return e.value, n.value
+
+
+def vqe_apply_hamiltonian(psi, lam, h):
+    e, n = C.c_double(), C.c_double()
+    check("vqe_apply_hamiltonian", lib().vqe_apply_hamiltonian(psi, lam, h, C.byref(e), C.byref(n)))
+    return e.value, n.value
+
+
+def vqe_energy_grad(psi, lam, c, params, h, method=GRAD_ADJOINT, expect_mode=EXPECT_GROUPED, ckpt=()):
+    p, pp = _arr(params, np.float64, C.c_double)
+    g = np.zeros(len(p), dtype=np.float64)
+    arr = (C.c_void_p * max(len(ckpt), 1))(*ckpt)
+    opts = vqe_grad_opts(method, expect_mode, len(ckpt), 0, C.cast(arr, C.POINTER(C.c_void_p)))
+    e = C.c_double()
+    check("vqe_energy_grad", lib().vqe_energy_grad(psi, lam, c, pp, len(p), h, C.byref(opts), C.byref(e),
+                                                   g.ctypes.data_as(C.POINTER(C.c_double))))
+    return e.value, g
+
+
+def vqe_slim_hamiltonian(x, z, w, mode, value):
+    x, xp = _arr(x, np.uint64, C.c_uint64)
+    z, zp = _arr(z, np.uint64, C.c_uint64)
+    w, wp = _arr(w, np.float64, C.c_double)
+    keep = np.zeros(len(w), dtype=np.uint8)
+    nk, dropped = _SZ(), C.c_double()
+    check("vqe_slim_hamiltonian", lib().vqe_slim_hamiltonian(
+        xp, zp, wp, len(w), mode, float(value), keep.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(nk),
+        C.byref(dropped)))
+    return keep, nk.value, dropped.value

@@ -1,0 +1,959 @@
+// C ABI of the VQE library: state handles, circuits (fused pass plans),
+// Hamiltonian tables and the energy / gradient drivers.  All device work is
+// enqueued on the state's stream; host scalars are returned after one
+// synchronisation of that stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+#include "vqe_internal.h"
+
+using namespace vqe;
+
+namespace vqe {
+namespace {
+thread_local std::string g_last_error;
+}
+void set_error(const std::string& m) { g_last_error = m; }
+}  // namespace vqe
+
+#define VQE_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));              \
+            return VQE_ERR_DEVICE;                                                     \
+        }                                                                              \
+    } while (0)
+
+#define VQE_GUARD_BEGIN try {
+#define VQE_GUARD_END                                                                  \
+    }                                                                                  \
+    catch (const std::bad_alloc&) {                                                    \
+        set_error("host allocation failed");                                           \
+        return VQE_ERR_OOM;                                                            \
+    }                                                                                  \
+    catch (const std::exception& ex) {                                                 \
+        set_error(std::string("internal error: ") + ex.what());                        \
+        return VQE_ERR_STATE;                                                          \
+    }
+
+// ---------------------------------------------------------------- handles
+struct vqe_state {
+    int n = 0;
+    int dtype = 0;
+    void* data = nullptr;
+    size_t bytes = 0;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double* d_part = nullptr;  // per-block partials: kMaxBlocks * kMaxGradSlots
+    double* d_res = nullptr;   // results (energies, gradients), grown on demand
+    size_t res_cap = 0;
+    double* h_res = nullptr;   // pinned host mirror of d_res
+};
+
+struct PassOps {
+    std::vector<KOp> fwd, rev;
+    std::vector<int> fwd_mat_gate, rev_mat_gate;  // matrix slot -> gate index
+    std::vector<int32_t> slot_param;              // reverse gradient slot -> parameter
+};
+
+// A fused pass plan for one window size.
+struct Plan {
+    std::vector<PlannedPass> passes;
+    std::vector<PassOps> ops;
+    std::vector<int32_t> slotmap;   // all passes' gradient slot -> parameter maps
+    int32_t* d_slotmap = nullptr;   // uploaded on first use on a device
+    std::vector<size_t> slot_off;
+};
+
+struct vqe_circuit {
+    int n = 0;
+    std::vector<Gate> gates;
+    size_t n_params = 0;
+    Plan plan[2];  // [0]: complex64 windows, [1]: complex128 windows
+    const Plan& for_dtype(int dtype) const { return plan[dtype == VQE_C64 ? 0 : 1]; }
+};
+
+struct vqe_hamiltonian {
+    int n = 0;
+    std::vector<uint64_t> x, z;  // combined terms, sorted by (x, z)
+    std::vector<double> w;
+    std::vector<GroupDesc> groups;
+    std::vector<TermDesc<float>> t32;
+    std::vector<TermDesc<double>> t64;
+    double identity = 0.0;
+    // device tables, uploaded on first use on a device
+    GroupDesc* d_groups = nullptr;
+    TermDesc<float>* d_t32 = nullptr;
+    TermDesc<double>* d_t64 = nullptr;
+};
+
+namespace {
+
+size_t amp_bytes(int dtype) { return dtype == VQE_C64 ? 8 : 16; }
+
+int ensure_res(vqe_state* s, size_t count) {
+    if (count <= s->res_cap) return VQE_OK;
+    size_t cap = std::max<size_t>(count, 1024);
+    if (s->d_res) {
+        VQE_HIP(hipStreamSynchronize(s->stream));
+        VQE_HIP(hipFree(s->d_res));
+        s->d_res = nullptr;
+    }
+    if (s->h_res) {
+        VQE_HIP(hipHostFree(s->h_res));
+        s->h_res = nullptr;
+    }
+    s->res_cap = 0;
+    if (hipMalloc((void**)&s->d_res, cap * sizeof(double)) != hipSuccess) {
+        set_error("hipMalloc of the result buffer failed");
+        return VQE_ERR_OOM;
+    }
+    if (hipHostMalloc((void**)&s->h_res, cap * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        set_error("hipHostMalloc of the result buffer failed");
+        return VQE_ERR_OOM;
+    }
+    s->res_cap = cap;
+    return VQE_OK;
+}
+
+int upload_plan(const Plan& cpl);
+
+// Uploads the grouped term tables to the current device (once).
+int upload_hamiltonian(const vqe_hamiltonian* ch) {
+    vqe_hamiltonian* h = const_cast<vqe_hamiltonian*>(ch);
+    if (h->d_groups) return VQE_OK;
+    if (hipMalloc((void**)&h->d_groups, h->groups.size() * sizeof(GroupDesc)) != hipSuccess ||
+        hipMalloc((void**)&h->d_t32, h->t32.size() * sizeof(TermDesc<float>)) != hipSuccess ||
+        hipMalloc((void**)&h->d_t64, h->t64.size() * sizeof(TermDesc<double>)) != hipSuccess) {
+        if (h->d_groups) (void)hipFree(h->d_groups);
+        if (h->d_t32) (void)hipFree(h->d_t32);
+        h->d_groups = nullptr;
+        h->d_t32 = nullptr;
+        set_error("hipMalloc of the Hamiltonian tables failed");
+        return VQE_ERR_OOM;
+    }
+    VQE_HIP(hipMemcpy(h->d_groups, h->groups.data(), h->groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
+    VQE_HIP(hipMemcpy(h->d_t32, h->t32.data(), h->t32.size() * sizeof(TermDesc<float>), hipMemcpyHostToDevice));
+    VQE_HIP(hipMemcpy(h->d_t64, h->t64.data(), h->t64.size() * sizeof(TermDesc<double>), hipMemcpyHostToDevice));
+    return VQE_OK;
+}
+
+// Angle of gate g under params.
+double angle_of(const Gate& g, const double* params) { return g.pidx >= 0 ? params[g.pidx] : g.angle; }
+
+template <typename T>
+void fill_matrix(Mat2<T>& m, const Gate& g, double th, bool inverse) {
+    if (inverse) th = -th;
+    const double c = std::cos(th / 2), s = std::sin(th / 2);
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    switch (g.kind) {
+        case VQE_GATE_RY:  // [[c, -s], [s, c]]
+            v[0] = c; v[2] = -s; v[4] = s; v[6] = c;
+            break;
+        case VQE_GATE_RZ:  // diag(e^{-i t/2}, e^{i t/2})
+            v[0] = c; v[1] = -s; v[6] = c; v[7] = s;
+            break;
+        case VQE_GATE_RX:  // [[c, -i s], [-i s, c]]
+            v[0] = c; v[3] = -s; v[5] = -s; v[6] = c;
+            break;
+        case VQE_GATE_H: {
+            const double r = 1.0 / std::sqrt(2.0);
+            v[0] = r; v[2] = r; v[4] = r; v[6] = -r;
+            break;
+        }
+        default:
+            break;
+    }
+    for (int i = 0; i < 8; ++i) m.v[i] = (T)v[i];
+}
+
+uint8_t mat_op(int kind) {
+    switch (kind) {
+        case VQE_GATE_RY: return OP_R2;
+        case VQE_GATE_RZ: return OP_DIAG;
+        case VQE_GATE_H: return OP_R2;
+        default: return OP_U2;
+    }
+}
+
+uint8_t grad_op(int kind) {
+    switch (kind) {
+        case VQE_GATE_RY: return OP_GY;
+        case VQE_GATE_RZ: return OP_GZ;
+        default: return OP_GX;
+    }
+}
+
+int local_bit(const PlannedPass& p, int q) {
+    for (int j = 0; j < p.K; ++j)
+        if (p.pos[j] == q) return j;
+    return -1;
+}
+
+// Appends the op that applies gate gi (or its inverse) to `ops`.
+void emit_gate(const Gate& g, int gi, const PlannedPass& p, std::vector<KOp>& ops,
+               std::vector<int>& mat_gate) {
+    KOp op{};
+    op.a = (uint8_t)local_bit(p, g.q0);
+    switch (g.kind) {
+        case VQE_GATE_CNOT:
+            op.type = OP_CNOT;
+            op.b = (uint8_t)local_bit(p, g.q1);
+            break;
+        case VQE_GATE_CZ:
+            op.type = OP_CZ;
+            op.b = (uint8_t)local_bit(p, g.q1);
+            break;
+        case VQE_GATE_X:
+            op.type = OP_XFLIP;
+            break;
+        default:
+            op.type = mat_op(g.kind);
+            op.slot = (uint8_t)mat_gate.size();
+            mat_gate.push_back(gi);
+            break;
+    }
+    ops.push_back(op);
+}
+
+template <typename T>
+void build_args(const vqe_circuit* c, const Plan& pl, size_t pi, const double* params, bool reverse,
+                PassArgs<T>& a) {
+    const PlannedPass& p = pl.passes[pi];
+    const PassOps& po = pl.ops[pi];
+    std::memset(&a, 0, sizeof(a));
+    a.K = (uint32_t)p.K;
+    a.n_cosets = 1ull << (c->n - p.K);
+    for (int j = 0; j < p.K; ++j) a.pos[j] = (uint32_t)p.pos[j];
+    const auto& ops = reverse ? po.rev : po.fwd;
+    const auto& mg = reverse ? po.rev_mat_gate : po.fwd_mat_gate;
+    a.n_ops = (uint32_t)ops.size();
+    for (size_t i = 0; i < ops.size(); ++i) a.ops[i] = ops[i];
+    for (size_t i = 0; i < mg.size(); ++i) {
+        const Gate& g = c->gates[mg[i]];
+        fill_matrix(a.mats[i], g, angle_of(g, params), reverse);
+    }
+    a.n_gslots = reverse ? (uint32_t)po.slot_param.size() : 0;
+}
+
+int check_state(const vqe_state* s, const char* fn) {
+    if (!s || !s->data) {
+        set_error(std::string(fn) + ": null state");
+        return VQE_ERR_ARG;
+    }
+    return VQE_OK;
+}
+
+int check_params(const vqe_circuit* c, const double* params, size_t n_params, const char* fn) {
+    if (n_params != c->n_params) {
+        set_error(std::string(fn) + ": n_params " + std::to_string(n_params) + " does not match the circuit's " +
+                  std::to_string(c->n_params));
+        return VQE_ERR_ARG;
+    }
+    if (n_params > 0 && !params) {
+        set_error(std::string(fn) + ": null params");
+        return VQE_ERR_ARG;
+    }
+    for (size_t i = 0; i < n_params; ++i)
+        if (!std::isfinite(params[i])) {
+            set_error(std::string(fn) + ": non-finite parameter");
+            return VQE_ERR_ARG;
+        }
+    return VQE_OK;
+}
+
+// Forward passes from |b0> (or in place on the current state when reset is false).
+// ckpt_ptr[k] receives the state at boundary bounds[k] (pass index + 1).
+template <typename T>
+int forward(vqe_state* s, const vqe_circuit* c, const double* params, const std::vector<size_t>& bounds,
+            const std::vector<void*>& ckpt_ptr) {
+    void* cur = s->data;
+    PassArgs<T> a;
+    const Plan& pl = c->for_dtype(s->dtype);
+    for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
+        void* out = s->data;
+        for (size_t k = 0; k < bounds.size(); ++k)
+            if (bounds[k] == pi + 1) out = ckpt_ptr[k];
+        build_args<T>(c, pl, pi, params, false, a);
+        VQE_HIP(launch_window_fwd<T>(a, cur, out, s->stream));
+        cur = out;
+    }
+    return VQE_OK;
+}
+
+template <typename T>
+const TermDesc<T>* terms_of(const vqe_hamiltonian* h);
+template <>
+const TermDesc<float>* terms_of<float>(const vqe_hamiltonian* h) { return h->d_t32; }
+template <>
+const TermDesc<double>* terms_of<double>(const vqe_hamiltonian* h) { return h->d_t64; }
+
+// Grouped energy partials reduced into d_res[off], d_res[off+1].
+template <typename T>
+int energy_grouped(vqe_state* s, const vqe_hamiltonian* h, size_t off) {
+    uint32_t nb = 0;
+    VQE_HIP(launch_hpsi<T>(s->n, s->data, nullptr, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 1,
+                           s->d_part, &nb, s->stream));
+    VQE_HIP(launch_reduce(s->d_part, nb, 2, nullptr, s->d_res + off, 0, s->stream));
+    return VQE_OK;
+}
+
+// Per-term partials: d_res[off + 2t] = <P_t>, d_res[off + 2t + 1] = norm.
+template <typename T>
+int energy_per_term(vqe_state* s, const vqe_hamiltonian* h, size_t off) {
+    for (size_t t = 0; t < h->w.size(); ++t) {
+        uint32_t nb = 0;
+        VQE_HIP(launch_expect_term<T>(s->n, s->data, h->x[t], h->z[t], s->d_part, &nb, s->stream));
+        VQE_HIP(launch_reduce(s->d_part, nb, 2, nullptr, s->d_res + off + 2 * t, 0, s->stream));
+    }
+    return VQE_OK;
+}
+
+double combine_per_term(const vqe_hamiltonian* h, const double* r, double* norm) {
+    double e = 0.0;
+    for (size_t t = 0; t < h->w.size(); ++t) e += h->w[t] * r[2 * t];
+    *norm = h->w.empty() ? 0.0 : r[1];
+    return e;
+}
+
+template <typename T>
+int expect_impl(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy, double* norm) {
+    const size_t need = mode == VQE_EXPECT_PER_TERM ? 2 * h->w.size() + 2 : 2;
+    int rc = ensure_res(s, need);
+    if (rc) return rc;
+    if (mode == VQE_EXPECT_PER_TERM) {
+        if (h->w.empty()) {
+            set_error("vqe_expect_pauli: empty Hamiltonian");
+            return VQE_ERR_ARG;
+        }
+        rc = energy_per_term<T>(s, h, 0);
+        if (rc) return rc;
+        VQE_HIP(hipMemcpyAsync(s->h_res, s->d_res, 2 * h->w.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        VQE_HIP(hipStreamSynchronize(s->stream));
+        double nrm = 0.0;
+        const double e = combine_per_term(h, s->h_res, &nrm);
+        *energy = e / nrm;
+        if (norm) *norm = nrm;
+    } else {
+        rc = energy_grouped<T>(s, h, 0);
+        if (rc) return rc;
+        VQE_HIP(hipMemcpyAsync(s->h_res, s->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        VQE_HIP(hipStreamSynchronize(s->stream));
+        *energy = s->h_res[0] / s->h_res[1];
+        if (norm) *norm = s->h_res[1];
+    }
+    return VQE_OK;
+}
+
+template <typename T>
+int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const double* params,
+                 const vqe_hamiltonian* h, const vqe_grad_opts* o, double* energy, double* grad) {
+    const Plan& pl = c->for_dtype(psi->dtype);
+    if (int rc0 = upload_plan(pl)) return rc0;
+    const size_t P = pl.passes.size();
+    std::vector<size_t> bounds;
+    std::vector<void*> ck;
+    const int nck = o ? o->n_ckpt : 0;
+    for (int k = 0; k < nck; ++k) {
+        size_t b = (size_t)std::llround((double)(k + 1) * (double)P / (double)(nck + 1));
+        if (b < 1 || b >= P) continue;
+        if (std::find(bounds.begin(), bounds.end(), b) != bounds.end()) continue;
+        bounds.push_back(b);
+        ck.push_back(o->ckpt[k]->data);
+    }
+    int rc = ensure_res(psi, 2 + c->n_params);
+    if (rc) return rc;
+    double* d_e = psi->d_res;
+    double* d_g = psi->d_res + 2;
+    hipStream_t st = psi->stream;
+    VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, st));
+    rc = forward<T>(psi, c, params, bounds, ck);
+    if (rc) return rc;
+    uint32_t nb = 0;
+    VQE_HIP(launch_hpsi<T>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 0,
+                           psi->d_part, &nb, st));
+    VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, d_e, 0, st));
+    VQE_HIP(launch_zero(d_g, c->n_params, st));
+    PassArgs<T> a;
+    for (size_t pi = P; pi-- > 0;) {
+        const void* pin = psi->data;
+        for (size_t k = 0; k < bounds.size(); ++k)
+            if (bounds[k] == pi + 1) pin = ck[k];
+        build_args<T>(c, pl, pi, params, true, a);
+        uint32_t gb = 0;
+        VQE_HIP(launch_window_rev<T>(a, pin, psi->data, lam->data, lam->data, psi->d_part, &gb, st));
+        if (a.n_gslots)
+            VQE_HIP(launch_reduce(psi->d_part, gb, a.n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, 1, st));
+    }
+    VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, (2 + c->n_params) * sizeof(double), hipMemcpyDeviceToHost, st));
+    VQE_HIP(hipStreamSynchronize(st));
+    const double nrm = psi->h_res[1];
+    *energy = psi->h_res[0] / nrm;
+    for (size_t k = 0; k < c->n_params; ++k) grad[k] = psi->h_res[2 + k] / nrm;
+    return VQE_OK;
+}
+
+template <typename T>
+int param_shift_impl(vqe_state* psi, const vqe_circuit* c, const double* params, const vqe_hamiltonian* h,
+                     int mode, double* energy, double* grad) {
+    const size_t P = c->n_params;
+    const size_t per = mode == VQE_EXPECT_PER_TERM ? 2 * h->w.size() : 2;
+    const size_t n_eval = 2 * P + 1;
+    int rc = ensure_res(psi, per * n_eval);
+    if (rc) return rc;
+    std::vector<double> th(params, params + P);
+    const std::vector<size_t> nob;
+    const std::vector<void*> nock;
+    // Evaluation 0 last so that psi ends in U(theta)|0>.
+    for (size_t e = n_eval; e-- > 0;) {
+        std::copy(params, params + P, th.begin());
+        if (e > 0) {
+            const size_t k = (e - 1) / 2;
+            th[k] += (e % 2 == 1) ? M_PI / 2 : -M_PI / 2;
+        }
+        VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, psi->stream));
+        rc = forward<T>(psi, c, th.data(), nob, nock);
+        if (rc) return rc;
+        rc = mode == VQE_EXPECT_PER_TERM ? energy_per_term<T>(psi, h, e * per) : energy_grouped<T>(psi, h, e * per);
+        if (rc) return rc;
+    }
+    VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, per * n_eval * sizeof(double), hipMemcpyDeviceToHost, psi->stream));
+    VQE_HIP(hipStreamSynchronize(psi->stream));
+    std::vector<double> E(n_eval);
+    for (size_t e = 0; e < n_eval; ++e) {
+        const double* r = psi->h_res + e * per;
+        if (mode == VQE_EXPECT_PER_TERM) {
+            double nrm = 0.0;
+            const double v = combine_per_term(h, r, &nrm);
+            E[e] = v / nrm;
+        } else {
+            E[e] = r[0] / r[1];
+        }
+    }
+    *energy = E[0];
+    for (size_t k = 0; k < P; ++k) grad[k] = 0.5 * (E[1 + 2 * k] - E[2 + 2 * k]);
+    return VQE_OK;
+}
+
+
+void free_circuit(vqe_circuit* c) {
+    if (!c) return;
+    for (auto& pl : c->plan)
+        if (pl.d_slotmap) (void)hipFree(pl.d_slotmap);
+    delete c;
+}
+
+// Plans fused passes with windows of at most kwin qubits and lowers them to
+// kernel op lists (forward, and reverse with gradient ops).
+int build_plan(vqe_circuit* c, int kwin, Plan& pl) {
+    std::string msg;
+    if (!plan_passes(c->n, c->gates, kwin, pl.passes, msg)) {
+        set_error("vqe_circuit_create: " + msg);
+        return VQE_ERR_STATE;
+    }
+    std::vector<int32_t>& slotmap = pl.slotmap;
+    pl.ops.resize(pl.passes.size());
+    for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
+        const PlannedPass& p = pl.passes[pi];
+        PassOps& po = pl.ops[pi];
+        for (int gi : p.gates) emit_gate(c->gates[gi], gi, p, po.fwd, po.fwd_mat_gate);
+        std::map<int, int> pslot;
+        for (auto it = p.gates.rbegin(); it != p.gates.rend(); ++it) {
+            const Gate& g = c->gates[*it];
+            if (g.pidx >= 0) {
+                auto f = pslot.find(g.pidx);
+                int slot;
+                if (f == pslot.end()) {
+                    slot = (int)po.slot_param.size();
+                    pslot[g.pidx] = slot;
+                    po.slot_param.push_back(g.pidx);
+                } else {
+                    slot = f->second;
+                }
+                KOp gop{};
+                gop.type = grad_op(g.kind);
+                gop.a = (uint8_t)local_bit(p, g.q0);
+                gop.slot = (uint8_t)slot;
+                po.rev.push_back(gop);
+            }
+            emit_gate(g, *it, p, po.rev, po.rev_mat_gate);
+        }
+        pl.slot_off.push_back(slotmap.size());
+        slotmap.insert(slotmap.end(), po.slot_param.begin(), po.slot_param.end());
+    }
+    return VQE_OK;
+}
+
+// Uploads the gradient slot maps of a plan to the current device (once).
+int upload_plan(const Plan& cpl) {
+    Plan& pl = const_cast<Plan&>(cpl);
+    if (pl.d_slotmap || pl.slotmap.empty()) return VQE_OK;
+    if (hipMalloc((void**)&pl.d_slotmap, pl.slotmap.size() * sizeof(int32_t)) != hipSuccess) {
+        set_error("hipMalloc of the gradient slot map failed");
+        return VQE_ERR_OOM;
+    }
+    VQE_HIP(hipMemcpy(pl.d_slotmap, pl.slotmap.data(), pl.slotmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return VQE_OK;
+}
+}  // namespace
+
+// ================================================================ exported
+extern "C" {
+
+const char* vqe_last_error(void) { return g_last_error.c_str(); }
+
+const char* vqe_version(void) { return "1.0.0"; }
+
+int vqe_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+int vqe_state_alloc(int n_qubits, int dtype, void* device_buf, size_t buf_bytes, void* hip_stream, vqe_state** out) {
+    VQE_GUARD_BEGIN
+    if (!out) {
+        set_error("vqe_state_alloc: null out");
+        return VQE_ERR_ARG;
+    }
+    if (n_qubits < 1 || n_qubits > 40) {
+        set_error("vqe_state_alloc: n_qubits must be in [1, 40]");
+        return VQE_ERR_ARG;
+    }
+    if (dtype != VQE_C64 && dtype != VQE_C128) {
+        set_error("vqe_state_alloc: dtype must be VQE_C64 or VQE_C128");
+        return VQE_ERR_ARG;
+    }
+    const size_t need = (size_t(1) << n_qubits) * amp_bytes(dtype);
+    if (device_buf && buf_bytes < need) {
+        set_error("vqe_state_alloc: device buffer of " + std::to_string(buf_bytes) + " bytes is smaller than the " +
+                  std::to_string(need) + " bytes the state needs");
+        return VQE_ERR_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        set_error("vqe_state_alloc: no HIP device");
+        return VQE_ERR_DEVICE;
+    }
+    auto* s = new vqe_state();
+    s->n = n_qubits;
+    s->dtype = dtype;
+    s->bytes = need;
+    s->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        set_error("vqe_state_alloc: hipGetDevice failed");
+        return VQE_ERR_DEVICE;
+    }
+    if (device_buf) {
+        s->data = device_buf;
+    } else {
+        if (hipMalloc(&s->data, need) != hipSuccess) {
+            delete s;
+            set_error("vqe_state_alloc: hipMalloc of " + std::to_string(need) + " bytes failed");
+            return VQE_ERR_OOM;
+        }
+        s->owned = true;
+    }
+    if (hipMalloc((void**)&s->d_part, (size_t)kMaxBlocks * kMaxGradSlots * sizeof(double)) != hipSuccess) {
+        if (s->owned) (void)hipFree(s->data);
+        delete s;
+        set_error("vqe_state_alloc: hipMalloc of the partial-sum buffer failed");
+        return VQE_ERR_OOM;
+    }
+    int rc = ensure_res(s, 1024);
+    if (rc) {
+        (void)hipFree(s->d_part);
+        if (s->owned) (void)hipFree(s->data);
+        delete s;
+        return rc;
+    }
+    if (launch_set_basis(dtype, s->data, 1ull << n_qubits, 0, s->stream) != hipSuccess) {
+        set_error("vqe_state_alloc: initialisation kernel failed");
+        (void)hipFree(s->d_part);
+        (void)hipFree(s->d_res);
+        (void)hipHostFree(s->h_res);
+        if (s->owned) (void)hipFree(s->data);
+        delete s;
+        return VQE_ERR_DEVICE;
+    }
+    *out = s;
+    return VQE_OK;
+    VQE_GUARD_END
+}
+
+int vqe_state_free(vqe_state* s) {
+    if (!s) return VQE_OK;
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    if (s->owned && s->data) (void)hipFree(s->data);
+    if (s->d_part) (void)hipFree(s->d_part);
+    if (s->d_res) (void)hipFree(s->d_res);
+    if (s->h_res) (void)hipHostFree(s->h_res);
+    delete s;
+    return VQE_OK;
+}
+
+int vqe_state_set_basis(vqe_state* s, uint64_t b) {
+    if (int rc = check_state(s, "vqe_state_set_basis")) return rc;
+    if (b >= (1ull << s->n)) {
+        set_error("vqe_state_set_basis: basis index out of range");
+        return VQE_ERR_ARG;
+    }
+    VQE_HIP(hipSetDevice(s->device));
+    VQE_HIP(launch_set_basis(s->dtype, s->data, 1ull << s->n, b, s->stream));
+    return VQE_OK;
+}
+
+int vqe_state_info(const vqe_state* s, void** device_ptr, int* n_qubits, int* dtype) {
+    if (int rc = check_state(s, "vqe_state_info")) return rc;
+    if (device_ptr) *device_ptr = s->data;
+    if (n_qubits) *n_qubits = s->n;
+    if (dtype) *dtype = s->dtype;
+    return VQE_OK;
+}
+
+int vqe_state_read(const vqe_state* s, uint64_t offset, uint64_t count, void* host_dst) {
+    if (int rc = check_state(s, "vqe_state_read")) return rc;
+    if (!host_dst && count) {
+        set_error("vqe_state_read: null destination");
+        return VQE_ERR_ARG;
+    }
+    if (offset > (1ull << s->n) || count > (1ull << s->n) - offset) {
+        set_error("vqe_state_read: range out of bounds");
+        return VQE_ERR_ARG;
+    }
+    const size_t ab = amp_bytes(s->dtype);
+    VQE_HIP(hipSetDevice(s->device));
+    VQE_HIP(hipMemcpyAsync(host_dst, (const char*)s->data + offset * ab, count * ab, hipMemcpyDeviceToHost, s->stream));
+    VQE_HIP(hipStreamSynchronize(s->stream));
+    return VQE_OK;
+}
+
+int vqe_state_write(vqe_state* s, uint64_t offset, uint64_t count, const void* host_src) {
+    if (int rc = check_state(s, "vqe_state_write")) return rc;
+    if (!host_src && count) {
+        set_error("vqe_state_write: null source");
+        return VQE_ERR_ARG;
+    }
+    if (offset > (1ull << s->n) || count > (1ull << s->n) - offset) {
+        set_error("vqe_state_write: range out of bounds");
+        return VQE_ERR_ARG;
+    }
+    const size_t ab = amp_bytes(s->dtype);
+    VQE_HIP(hipSetDevice(s->device));
+    VQE_HIP(hipMemcpyAsync((char*)s->data + offset * ab, host_src, count * ab, hipMemcpyHostToDevice, s->stream));
+    VQE_HIP(hipStreamSynchronize(s->stream));
+    return VQE_OK;
+}
+
+int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_circuit** out) {
+    VQE_GUARD_BEGIN
+    if (!out || (n_gates && !gates)) {
+        set_error("vqe_circuit_create: null argument");
+        return VQE_ERR_ARG;
+    }
+    if (n_qubits < 1 || n_qubits > 40) {
+        set_error("vqe_circuit_create: n_qubits must be in [1, 40]");
+        return VQE_ERR_ARG;
+    }
+    std::vector<Gate> gs(n_gates);
+    size_t n_params = 0;
+    for (size_t i = 0; i < n_gates; ++i) {
+        const vqe_gate& g = gates[i];
+        const bool two = g.kind == VQE_GATE_CNOT || g.kind == VQE_GATE_CZ;
+        if (g.kind > VQE_GATE_CZ) {
+            set_error("vqe_circuit_create: gate " + std::to_string(i) + " has an unknown kind");
+            return VQE_ERR_ARG;
+        }
+        if (g.q0 >= n_qubits || (two && (g.q1 >= n_qubits || g.q1 == g.q0))) {
+            set_error("vqe_circuit_create: gate " + std::to_string(i) + " has an invalid qubit");
+            return VQE_ERR_ARG;
+        }
+        if (g.param_index >= 0 && !(g.kind == VQE_GATE_RY || g.kind == VQE_GATE_RZ || g.kind == VQE_GATE_RX)) {
+            set_error("vqe_circuit_create: gate " + std::to_string(i) + " cannot take a parameter");
+            return VQE_ERR_ARG;
+        }
+        if (g.param_index < -1) {
+            set_error("vqe_circuit_create: gate " + std::to_string(i) + " has param_index < -1");
+            return VQE_ERR_ARG;
+        }
+        if (g.param_index < 0 && !std::isfinite(g.angle)) {
+            set_error("vqe_circuit_create: gate " + std::to_string(i) + " has a non-finite angle");
+            return VQE_ERR_ARG;
+        }
+        gs[i] = Gate{g.kind, g.q0, two ? g.q1 : g.q0, g.param_index, g.angle};
+        if (g.param_index >= 0) n_params = std::max(n_params, (size_t)g.param_index + 1);
+    }
+    auto* c = new vqe_circuit();
+    c->n = n_qubits;
+    c->gates = std::move(gs);
+    c->n_params = n_params;
+    const int windows[2] = {kWindowC64, kWindowC128};
+    for (int v = 0; v < 2; ++v) {
+        int rc = build_plan(c, windows[v], c->plan[v]);
+        if (rc) {
+            free_circuit(c);
+            return rc;
+        }
+    }
+    *out = c;
+    return VQE_OK;
+    VQE_GUARD_END
+}
+
+int vqe_circuit_free(vqe_circuit* c) {
+    free_circuit(c);
+    return VQE_OK;
+}
+
+int vqe_circuit_info(const vqe_circuit* c, size_t* n_params, size_t* n_passes) {
+    if (!c) {
+        set_error("vqe_circuit_info: null circuit");
+        return VQE_ERR_ARG;
+    }
+    if (n_params) *n_params = c->n_params;
+    if (n_passes) *n_passes = c->plan[0].passes.size();
+    return VQE_OK;
+}
+
+int vqe_circuit_pass(const vqe_circuit* c, int dtype, size_t pass, int* window, int* qubits, size_t* n_gates,
+                     int32_t* gate_index, size_t capacity) {
+    if (!c || (dtype != VQE_C64 && dtype != VQE_C128)) {
+        set_error("vqe_circuit_pass: null circuit or bad dtype");
+        return VQE_ERR_ARG;
+    }
+    const Plan& pl = c->for_dtype(dtype);
+    if (pass >= pl.passes.size()) {
+        set_error("vqe_circuit_pass: pass index out of range");
+        return VQE_ERR_ARG;
+    }
+    const PlannedPass& p = pl.passes[pass];
+    if (window) *window = p.K;
+    if (qubits)
+        for (int j = 0; j < p.K; ++j) qubits[j] = p.pos[j];
+    if (n_gates) *n_gates = p.gates.size();
+    if (gate_index) {
+        if (capacity < p.gates.size()) {
+            set_error("vqe_circuit_pass: gate_index capacity too small");
+            return VQE_ERR_ARG;
+        }
+        for (size_t i = 0; i < p.gates.size(); ++i) gate_index[i] = p.gates[i];
+    }
+    return VQE_OK;
+}
+
+int vqe_apply_circuit(vqe_state* s, const vqe_circuit* c, const double* params, size_t n_params) {
+    VQE_GUARD_BEGIN
+    if (int rc = check_state(s, "vqe_apply_circuit")) return rc;
+    if (!c || c->n != s->n) {
+        set_error("vqe_apply_circuit: circuit missing or of a different qubit count");
+        return VQE_ERR_ARG;
+    }
+    if (int rc = check_params(c, params, n_params, "vqe_apply_circuit")) return rc;
+    VQE_HIP(hipSetDevice(s->device));
+    const std::vector<size_t> nob;
+    const std::vector<void*> nock;
+    return s->dtype == VQE_C64 ? forward<float>(s, c, params, nob, nock) : forward<double>(s, c, params, nob, nock);
+    VQE_GUARD_END
+}
+
+int vqe_hamiltonian_create(int n_qubits, const uint64_t* x, const uint64_t* z, const double* w, size_t n_terms,
+                           vqe_hamiltonian** out) {
+    VQE_GUARD_BEGIN
+    if (!out || (n_terms && (!x || !z || !w))) {
+        set_error("vqe_hamiltonian_create: null argument");
+        return VQE_ERR_ARG;
+    }
+    if (n_qubits < 1 || n_qubits > 40) {
+        set_error("vqe_hamiltonian_create: n_qubits must be in [1, 40]");
+        return VQE_ERR_ARG;
+    }
+    if (n_terms == 0) {
+        set_error("vqe_hamiltonian_create: no terms");
+        return VQE_ERR_ARG;
+    }
+    const uint64_t lim = 1ull << n_qubits;
+    for (size_t i = 0; i < n_terms; ++i) {
+        if (x[i] >= lim || z[i] >= lim) {
+            set_error("vqe_hamiltonian_create: term " + std::to_string(i) + " has a mask bit >= n_qubits");
+            return VQE_ERR_ARG;
+        }
+        if (!std::isfinite(w[i])) {
+            set_error("vqe_hamiltonian_create: term " + std::to_string(i) + " has a non-finite weight");
+            return VQE_ERR_ARG;
+        }
+    }
+    std::vector<size_t> idx(n_terms);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+        return x[a] != x[b] ? x[a] < x[b] : z[a] < z[b];
+    });
+    auto* h = new vqe_hamiltonian();
+    h->n = n_qubits;
+    for (size_t k = 0; k < n_terms; ++k) {
+        const size_t i = idx[k];
+        if (!h->x.empty() && h->x.back() == x[i] && h->z.back() == z[i]) {
+            h->w.back() += w[i];
+        } else {
+            h->x.push_back(x[i]);
+            h->z.push_back(z[i]);
+            h->w.push_back(w[i]);
+        }
+    }
+    std::vector<TermDesc<float>>& t32 = h->t32;
+    std::vector<TermDesc<double>>& t64 = h->t64;
+    t32.resize(h->w.size());
+    t64.resize(h->w.size());
+    for (size_t t = 0; t < h->w.size(); ++t) {
+        if (h->x[t] == 0 && h->z[t] == 0) h->identity += h->w[t];
+        if (h->groups.empty() || h->groups.back().x != h->x[t]) {
+            GroupDesc g{};
+            g.x = h->x[t];
+            g.begin = (uint32_t)t;
+            g.hbit = h->x[t] ? 63 - __builtin_clzll(h->x[t]) : 0;
+            h->groups.push_back(g);
+        }
+        h->groups.back().end = (uint32_t)t + 1;
+        // c = w (-i)^y with y = popcount(x & z) mod 4
+        const int y = __builtin_popcountll(h->x[t] & h->z[t]) & 3;
+        const double wv = h->w[t];
+        const double cre = (y == 0) ? wv : (y == 2 ? -wv : 0.0);
+        const double cim = (y == 1) ? -wv : (y == 3 ? wv : 0.0);
+        t64[t] = TermDesc<double>{h->z[t], cre, cim};
+        t32[t] = TermDesc<float>{h->z[t], (float)cre, (float)cim};
+    }
+    *out = h;
+    return VQE_OK;
+    VQE_GUARD_END
+}
+
+int vqe_hamiltonian_free(vqe_hamiltonian* h) {
+    if (!h) return VQE_OK;
+    if (h->d_groups) (void)hipFree(h->d_groups);
+    if (h->d_t32) (void)hipFree(h->d_t32);
+    if (h->d_t64) (void)hipFree(h->d_t64);
+    delete h;
+    return VQE_OK;
+}
+
+int vqe_hamiltonian_info(const vqe_hamiltonian* h, size_t* n_terms, size_t* n_groups, double* identity_weight) {
+    if (!h) {
+        set_error("vqe_hamiltonian_info: null Hamiltonian");
+        return VQE_ERR_ARG;
+    }
+    if (n_terms) *n_terms = h->w.size();
+    if (n_groups) *n_groups = h->groups.size();
+    if (identity_weight) *identity_weight = h->identity;
+    return VQE_OK;
+}
+
+int vqe_expect_pauli(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy, double* norm) {
+    VQE_GUARD_BEGIN
+    if (int rc = check_state(s, "vqe_expect_pauli")) return rc;
+    if (!h || h->n != s->n || !energy) {
+        set_error("vqe_expect_pauli: Hamiltonian missing, of a different qubit count, or null energy");
+        return VQE_ERR_ARG;
+    }
+    if (mode != VQE_EXPECT_GROUPED && mode != VQE_EXPECT_PER_TERM) {
+        set_error("vqe_expect_pauli: unknown mode");
+        return VQE_ERR_ARG;
+    }
+    VQE_HIP(hipSetDevice(s->device));
+    if (int rc = upload_hamiltonian(h)) return rc;
+    return s->dtype == VQE_C64 ? expect_impl<float>(s, h, mode, energy, norm)
+                               : expect_impl<double>(s, h, mode, energy, norm);
+    VQE_GUARD_END
+}
+
+int vqe_apply_hamiltonian(vqe_state* psi, vqe_state* lam, const vqe_hamiltonian* h, double* energy, double* norm) {
+    VQE_GUARD_BEGIN
+    if (int rc = check_state(psi, "vqe_apply_hamiltonian")) return rc;
+    if (int rc = check_state(lam, "vqe_apply_hamiltonian")) return rc;
+    if (psi == lam || psi->data == lam->data || lam->n != psi->n || lam->dtype != psi->dtype || !h ||
+        h->n != psi->n) {
+        set_error("vqe_apply_hamiltonian: lam must be a distinct state of the same n and dtype as psi");
+        return VQE_ERR_ARG;
+    }
+    VQE_HIP(hipSetDevice(psi->device));
+    int rc = upload_hamiltonian(h);
+    if (rc) return rc;
+    rc = ensure_res(psi, 2);
+    if (rc) return rc;
+    uint32_t nb = 0;
+    if (psi->dtype == VQE_C64)
+        VQE_HIP(launch_hpsi<float>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(), h->d_t32, 0,
+                                   psi->d_part, &nb, psi->stream));
+    else
+        VQE_HIP(launch_hpsi<double>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(), h->d_t64,
+                                    0, psi->d_part, &nb, psi->stream));
+    VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, psi->d_res, 0, psi->stream));
+    VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, psi->stream));
+    VQE_HIP(hipStreamSynchronize(psi->stream));
+    if (energy) *energy = psi->h_res[0] / psi->h_res[1];
+    if (norm) *norm = psi->h_res[1];
+    return VQE_OK;
+    VQE_GUARD_END
+}
+
+int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const double* params, size_t n_params,
+                    const vqe_hamiltonian* h, const vqe_grad_opts* opts, double* energy, double* grad) {
+    VQE_GUARD_BEGIN
+    if (int rc = check_state(psi, "vqe_energy_grad")) return rc;
+    if (!c || c->n != psi->n || !h || h->n != psi->n || !energy || (n_params && !grad)) {
+        set_error("vqe_energy_grad: circuit / Hamiltonian missing or of a different qubit count, or null output");
+        return VQE_ERR_ARG;
+    }
+    if (int rc = check_params(c, params, n_params, "vqe_energy_grad")) return rc;
+    const int method = opts ? opts->method : VQE_GRAD_ADJOINT;
+    VQE_HIP(hipSetDevice(psi->device));
+    if (int rc = upload_hamiltonian(h)) return rc;
+    if (method == VQE_GRAD_PARAM_SHIFT) {
+        const int mode = opts ? opts->expect_mode : VQE_EXPECT_GROUPED;
+        if (mode != VQE_EXPECT_GROUPED && mode != VQE_EXPECT_PER_TERM) {
+            set_error("vqe_energy_grad: unknown expect_mode");
+            return VQE_ERR_ARG;
+        }
+        return psi->dtype == VQE_C64 ? param_shift_impl<float>(psi, c, params, h, mode, energy, grad)
+                                     : param_shift_impl<double>(psi, c, params, h, mode, energy, grad);
+    }
+    if (method != VQE_GRAD_ADJOINT) {
+        set_error("vqe_energy_grad: unknown method");
+        return VQE_ERR_ARG;
+    }
+    if (int rc = check_state(lam, "vqe_energy_grad")) return rc;
+    if (lam == psi || lam->data == psi->data || lam->n != psi->n || lam->dtype != psi->dtype) {
+        set_error("vqe_energy_grad: lam must be a distinct state of the same n and dtype as psi");
+        return VQE_ERR_ARG;
+    }
+    if (opts && opts->n_ckpt > 0) {
+        if (!opts->ckpt) {
+            set_error("vqe_energy_grad: n_ckpt > 0 with a null ckpt array");
+            return VQE_ERR_ARG;
+        }
+        for (int k = 0; k < opts->n_ckpt; ++k) {
+            const vqe_state* ck = opts->ckpt[k];
+            if (!ck || !ck->data || ck->n != psi->n || ck->dtype != psi->dtype || ck->data == psi->data ||
+                ck->data == lam->data) {
+                set_error("vqe_energy_grad: checkpoint " + std::to_string(k) +
+                          " must be a distinct state of the same n and dtype as psi");
+                return VQE_ERR_ARG;
+            }
+            for (int j = 0; j < k; ++j)
+                if (opts->ckpt[j]->data == ck->data) {
+                    set_error("vqe_energy_grad: checkpoint states must be distinct");
+                    return VQE_ERR_ARG;
+                }
+        }
+    }
+    return psi->dtype == VQE_C64 ? adjoint_impl<float>(psi, lam, c, params, h, opts, energy, grad)
+                                 : adjoint_impl<double>(psi, lam, c, params, h, opts, energy, grad);
+    VQE_GUARD_END
+}
+
+}  // extern "C"

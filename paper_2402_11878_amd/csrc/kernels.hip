@@ -1,0 +1,627 @@
+// HIP kernels of the VQE hot path, written for gfx950 (CDNA4, wave64).
+//
+//  * window_kernel   : one fused pass of the ansatz (eq. 6).  Each thread owns
+//                      the 2^K amplitudes of one coset of a K-qubit window,
+//                      found by inserting zero bits at the window positions
+//                      into the thread's linear index (index-bit insertion),
+//                      so consecutive lanes read consecutive addresses.  All
+//                      gates of the pass are applied in registers; the state
+//                      is read and written once.  The reverse variant carries
+//                      (psi, lam), un-applies the gates in reverse order and
+//                      accumulates the adjoint gradient Im<lam|G|psi>.
+//  * hpsi_kernel     : (H psi)[b] = sum_x psi[b^x] D_x(b) with
+//                      D_x(b) = sum_{z in group x} c_z (-1)^popcount(z&b):
+//                      terms grouped by X mask, one read of the partner tile
+//                      serves every Z pattern of the group (eq. 7 energy from
+//                      the same pass).
+//  * expect_term_kernel : one sweep per Pauli term, the paper's evaluation
+//                      order (Sec. III-D), used as the baseline form.
+//  * reduce_kernel   : fixed-order FP64 sum of per-block partials (no atomics,
+//                      deterministic bits).
+#include <type_traits>
+
+#include "vqe_internal.h"
+
+namespace vqe {
+namespace {
+
+template <typename T> struct VecOf;
+template <> struct VecOf<float> { using type = float2; };
+template <> struct VecOf<double> { using type = double2; };
+
+// ---------------------------------------------------------------- register ops
+template <int K, int B, int NV, typename T>
+__device__ __forceinline__ void op_u2(T (&re)[NV][1 << K], T (&im)[NV][1 << K], const T* m) {
+    const T m0r = m[0], m0i = m[1], m1r = m[2], m1i = m[3];
+    const T m2r = m[4], m2i = m[5], m3r = m[6], m3i = m[7];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << K); ++i) {
+            if (i & (1 << B)) continue;
+            const int j = i | (1 << B);
+            const T ar = re[v][i], ai = im[v][i], br = re[v][j], bi = im[v][j];
+            re[v][i] = m0r * ar - m0i * ai + m1r * br - m1i * bi;
+            im[v][i] = m0r * ai + m0i * ar + m1r * bi + m1i * br;
+            re[v][j] = m2r * ar - m2i * ai + m3r * br - m3i * bi;
+            im[v][j] = m2r * ai + m2i * ar + m3r * bi + m3i * br;
+        }
+    }
+}
+
+template <int K, int B, int NV, typename T>
+__device__ __forceinline__ void op_r2(T (&re)[NV][1 << K], T (&im)[NV][1 << K], const T* m) {
+    const T a = m[0], b = m[2], c = m[4], d = m[6];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << K); ++i) {
+            if (i & (1 << B)) continue;
+            const int j = i | (1 << B);
+            const T ar = re[v][i], ai = im[v][i], br = re[v][j], bi = im[v][j];
+            re[v][i] = a * ar + b * br;
+            im[v][i] = a * ai + b * bi;
+            re[v][j] = c * ar + d * br;
+            im[v][j] = c * ai + d * bi;
+        }
+    }
+}
+
+template <int K, int B, int NV, typename T>
+__device__ __forceinline__ void op_diag(T (&re)[NV][1 << K], T (&im)[NV][1 << K], const T* m) {
+    const T p0r = m[0], p0i = m[1], p1r = m[6], p1i = m[7];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << K); ++i) {
+            const T pr = (i & (1 << B)) ? p1r : p0r;
+            const T pi = (i & (1 << B)) ? p1i : p0i;
+            const T ar = re[v][i], ai = im[v][i];
+            re[v][i] = pr * ar - pi * ai;
+            im[v][i] = pr * ai + pi * ar;
+        }
+    }
+}
+
+template <int K, int C, int Tg, int NV, typename T>
+__device__ __forceinline__ void op_cnot(T (&re)[NV][1 << K], T (&im)[NV][1 << K]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << K); ++i) {
+            if (!(i & (1 << C)) || (i & (1 << Tg))) continue;
+            const int j = i | (1 << Tg);
+            const T tr = re[v][i], ti = im[v][i];
+            re[v][i] = re[v][j];
+            im[v][i] = im[v][j];
+            re[v][j] = tr;
+            im[v][j] = ti;
+        }
+    }
+}
+
+template <int K, int A, int B, int NV, typename T>
+__device__ __forceinline__ void op_cz(T (&re)[NV][1 << K], T (&im)[NV][1 << K]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << K); ++i) {
+            if ((i & (1 << A)) && (i & (1 << B))) {
+                re[v][i] = -re[v][i];
+                im[v][i] = -im[v][i];
+            }
+        }
+    }
+}
+
+template <int K, int B, int NV, typename T>
+__device__ __forceinline__ void op_xflip(T (&re)[NV][1 << K], T (&im)[NV][1 << K]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << K); ++i) {
+            if (i & (1 << B)) continue;
+            const int j = i | (1 << B);
+            const T tr = re[v][i], ti = im[v][i];
+            re[v][i] = re[v][j];
+            im[v][i] = im[v][j];
+            re[v][j] = tr;
+            im[v][j] = ti;
+        }
+    }
+}
+
+// Im<lam| G_B |psi> over the thread's coset; vector 0 = psi, vector 1 = lam.
+template <int K, int B, int G, typename T>
+__device__ __forceinline__ T op_grad(T (&re)[2][1 << K], T (&im)[2][1 << K]) {
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < (1 << K); ++i) {
+        if (i & (1 << B)) continue;
+        const int j = i | (1 << B);
+        const T p0r = re[0][i], p0i = im[0][i], p1r = re[0][j], p1i = im[0][j];
+        const T l0r = re[1][i], l0i = im[1][i], l1r = re[1][j], l1i = im[1][j];
+        if constexpr (G == OP_GZ) {
+            // Z psi = (psi0, -psi1):  Im(conj(l0) p0) - Im(conj(l1) p1)
+            acc += (l0r * p0i - l0i * p0r) - (l1r * p1i - l1i * p1r);
+        } else if constexpr (G == OP_GY) {
+            // Y psi = (-i psi1, i psi0)
+            acc += (l1r * p0r + l1i * p0i) - (l0r * p1r + l0i * p1i);
+        } else {
+            // X psi = (psi1, psi0)
+            acc += (l0r * p1i - l0i * p1r) + (l1r * p0i - l1i * p0r);
+        }
+    }
+    return acc;
+}
+
+// Explicit switch dispatch from a uniform runtime bit to the template
+// instantiation, so that every register index is a compile-time constant.
+#define VQE_BIT_CASES(CALL)                                       \
+    case 0: if constexpr (K > 0) { constexpr int B = 0; CALL; } break; \
+    case 1: if constexpr (K > 1) { constexpr int B = 1; CALL; } break; \
+    case 2: if constexpr (K > 2) { constexpr int B = 2; CALL; } break; \
+    case 3: if constexpr (K > 3) { constexpr int B = 3; CALL; } break; \
+    case 4: if constexpr (K > 4) { constexpr int B = 4; CALL; } break; \
+    default: break;
+
+template <int K, int NV, typename T>
+__device__ __forceinline__ void d_u2(int b, T (&re)[NV][1 << K], T (&im)[NV][1 << K], const T* m) {
+    switch (b) { VQE_BIT_CASES((op_u2<K, B, NV, T>(re, im, m))) }
+}
+template <int K, int NV, typename T>
+__device__ __forceinline__ void d_r2(int b, T (&re)[NV][1 << K], T (&im)[NV][1 << K], const T* m) {
+    switch (b) { VQE_BIT_CASES((op_r2<K, B, NV, T>(re, im, m))) }
+}
+template <int K, int NV, typename T>
+__device__ __forceinline__ void d_diag(int b, T (&re)[NV][1 << K], T (&im)[NV][1 << K], const T* m) {
+    switch (b) { VQE_BIT_CASES((op_diag<K, B, NV, T>(re, im, m))) }
+}
+template <int K, int NV, typename T>
+__device__ __forceinline__ void d_xflip(int b, T (&re)[NV][1 << K], T (&im)[NV][1 << K]) {
+    switch (b) { VQE_BIT_CASES((op_xflip<K, B, NV, T>(re, im))) }
+}
+template <int K, int C, int NV, typename T>
+__device__ __forceinline__ void d_cnot_t(int t, T (&re)[NV][1 << K], T (&im)[NV][1 << K]) {
+    switch (t) { VQE_BIT_CASES(if constexpr (B != C) (op_cnot<K, C, B, NV, T>(re, im))) }
+}
+template <int K, int NV, typename T>
+__device__ __forceinline__ void d_cnot(int c, int t, T (&re)[NV][1 << K], T (&im)[NV][1 << K]) {
+    switch (c) { VQE_BIT_CASES((d_cnot_t<K, B, NV, T>(t, re, im))) }
+}
+template <int K, int A, int NV, typename T>
+__device__ __forceinline__ void d_cz_b(int b2, T (&re)[NV][1 << K], T (&im)[NV][1 << K]) {
+    switch (b2) { VQE_BIT_CASES(if constexpr (B != A) (op_cz<K, A, B, NV, T>(re, im))) }
+}
+template <int K, int NV, typename T>
+__device__ __forceinline__ void d_cz(int a, int b2, T (&re)[NV][1 << K], T (&im)[NV][1 << K]) {
+    switch (a) { VQE_BIT_CASES((d_cz_b<K, B, NV, T>(b2, re, im))) }
+}
+template <int K, int G, typename T>
+__device__ __forceinline__ T d_grad(int b, T (&re)[2][1 << K], T (&im)[2][1 << K]) {
+    T g = 0;
+    switch (b) { VQE_BIT_CASES(g = (op_grad<K, B, G, T>(re, im))) }
+    return g;
+}
+
+template <int K, int NV, typename T>
+__device__ __forceinline__ void run_ops(const PassArgs<T>& a, T (&re)[NV][1 << K],
+                                        T (&im)[NV][1 << K], double* gacc, int tid) {
+    for (uint32_t o = 0; o < a.n_ops; ++o) {
+        const KOp op = a.ops[o];
+        const T* m = a.mats[op.slot].v;
+        switch (op.type) {
+            case OP_U2: d_u2<K, NV, T>(op.a, re, im, m); break;
+            case OP_R2: d_r2<K, NV, T>(op.a, re, im, m); break;
+            case OP_DIAG: d_diag<K, NV, T>(op.a, re, im, m); break;
+            case OP_XFLIP: d_xflip<K, NV, T>(op.a, re, im); break;
+            case OP_CNOT: d_cnot<K, NV, T>(op.a, op.b, re, im); break;
+            case OP_CZ: d_cz<K, NV, T>(op.a, op.b, re, im); break;
+            case OP_GX:
+                if constexpr (NV == 2) gacc[op.slot * kBlock + tid] += (double)d_grad<K, OP_GX, T>(op.a, re, im);
+                break;
+            case OP_GY:
+                if constexpr (NV == 2) gacc[op.slot * kBlock + tid] += (double)d_grad<K, OP_GY, T>(op.a, re, im);
+                break;
+            case OP_GZ:
+                if constexpr (NV == 2) gacc[op.slot * kBlock + tid] += (double)d_grad<K, OP_GZ, T>(op.a, re, im);
+                break;
+            default:
+                break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- window pass
+template <typename T, int K, int NV>
+__global__ void __launch_bounds__(kBlock)
+window_kernel(const PassArgs<T> a, const typename VecOf<T>::type* __restrict__ in0,
+              typename VecOf<T>::type* __restrict__ out0,
+              const typename VecOf<T>::type* __restrict__ in1,
+              typename VecOf<T>::type* __restrict__ out1, double* __restrict__ gpart) {
+    using V = typename VecOf<T>::type;
+    constexpr int N = 1 << K;
+    __shared__ double gacc[NV == 2 ? kMaxGradSlots * kBlock : 1];
+    const int tid = threadIdx.x;
+    if constexpr (NV == 2) {
+        for (uint32_t s = 0; s < a.n_gslots; ++s) gacc[s * kBlock + tid] = 0.0;
+    }
+    uint64_t bitval[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) bitval[j] = 1ull << a.pos[j];
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + tid; c < a.n_cosets; c += stride) {
+        uint64_t base = c;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint64_t low = base & (bitval[j] - 1);
+            base = ((base ^ low) << 1) | low;
+        }
+        T re[NV][N], im[NV][N];
+        // Per-pattern offsets are wave-uniform; only the coset base lives in
+        // VGPRs.  The empty asm makes the store base opaque so that the 2^K
+        // load addresses are not kept live across the gate loop.
+        uint64_t sbase = base;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            uint64_t off = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (p & (1 << j)) off += bitval[j];
+            const uint64_t idx = base + off;
+            const V v0 = in0[idx];
+            re[0][p] = v0.x;
+            im[0][p] = v0.y;
+            if constexpr (NV == 2) {
+                const V v1 = in1[idx];
+                re[NV - 1][p] = v1.x;
+                im[NV - 1][p] = v1.y;
+            }
+        }
+        run_ops<K, NV, T>(a, re, im, gacc, tid);
+        asm volatile("" : "+v"(sbase));
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            uint64_t off = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (p & (1 << j)) off += bitval[j];
+            const uint64_t idx = sbase + off;
+            V v0;
+            v0.x = re[0][p];
+            v0.y = im[0][p];
+            out0[idx] = v0;
+            if constexpr (NV == 2) {
+                V v1;
+                v1.x = re[NV - 1][p];
+                v1.y = im[NV - 1][p];
+                out1[idx] = v1;
+            }
+        }
+    }
+    if constexpr (NV == 2) {
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (tid < w)
+                for (uint32_t s = 0; s < a.n_gslots; ++s)
+                    gacc[s * kBlock + tid] += gacc[s * kBlock + tid + w];
+            __syncthreads();
+        }
+        if (tid < (int)a.n_gslots) gpart[(uint64_t)blockIdx.x * a.n_gslots + tid] = gacc[tid * kBlock];
+    }
+}
+
+// ---------------------------------------------------------------- H psi
+// Block = one tile of 2^tb amplitudes at a time (grid-stride over tiles);
+// thread t owns local indices r*TPT + t, r < R.
+template <typename T, int R, int MODE>
+__global__ void __launch_bounds__(kBlock)
+hpsi_kernel(int n, int tb, const typename VecOf<T>::type* __restrict__ psi,
+            typename VecOf<T>::type* __restrict__ lam, const GroupDesc* __restrict__ groups,
+            uint32_t n_groups, const TermDesc<T>* __restrict__ terms, double* __restrict__ part) {
+    using V = typename VecOf<T>::type;
+    __shared__ double red[2][kBlock];
+    const int tid = threadIdx.x;
+    const int tpt = (1 << tb) / R;  // threads per tile
+    const uint64_t n_tiles = 1ull << (n - tb);
+    double e_acc = 0.0, n_acc = 0.0;
+    if (tid < tpt) {
+        for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+            const uint64_t tbase = tile << tb;
+            uint32_t loc[R];
+            V own[R];
+            T ar[R], ai[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                loc[r] = (uint32_t)(r * tpt + tid);
+                own[r] = psi[tbase | loc[r]];
+                ar[r] = 0;
+                ai[r] = 0;
+            }
+            for (uint32_t g = 0; g < n_groups; ++g) {
+                const GroupDesc G = groups[g];
+                T wgt = 1;
+                if (MODE == 1 && G.x != 0 && G.hbit >= (uint32_t)tb) {
+                    if ((tbase >> G.hbit) & 1) continue;
+                    wgt = 2;
+                }
+                T dr[R], di[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    dr[r] = 0;
+                    di[r] = 0;
+                }
+                for (uint32_t t = G.begin; t < G.end; ++t) {
+                    const TermDesc<T> tm = terms[t];
+                    const uint32_t phi = __popcll(tm.z & tbase) & 1u;
+                    const uint32_t zl = (uint32_t)tm.z;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const uint32_t par = (__popc(zl & loc[r]) & 1u) ^ phi;
+                        dr[r] += par ? -tm.cre : tm.cre;
+                        di[r] += par ? -tm.cim : tm.cim;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const V pv = (G.x == 0) ? own[r] : psi[(tbase | loc[r]) ^ G.x];
+                    const T pr = pv.x, pi = pv.y;
+                    ar[r] += wgt * (dr[r] * pr - di[r] * pi);
+                    ai[r] += wgt * (dr[r] * pi + di[r] * pr);
+                }
+            }
+            T e_t = 0, n_t = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                e_t += own[r].x * ar[r] + own[r].y * ai[r];
+                n_t += own[r].x * own[r].x + own[r].y * own[r].y;
+                if (MODE == 0) {
+                    V o;
+                    o.x = ar[r];
+                    o.y = ai[r];
+                    lam[tbase | loc[r]] = o;
+                }
+            }
+            e_acc += (double)e_t;
+            n_acc += (double)n_t;
+        }
+    }
+    red[0][tid] = e_acc;
+    red[1][tid] = n_acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            red[0][tid] += red[0][tid + w];
+            red[1][tid] += red[1][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        part[2 * blockIdx.x + 0] = red[0][0];
+        part[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+// ---------------------------------------------------------------- one term
+// x != 0: visit each pair (b, b^x) once (bit h of b clear) and add
+// 2 Re(conj(psi_b) c (-1)^{z.b} psi_{b^x}); x = 0: sum (-1)^{z.b} |psi_b|^2.
+// c = (-i)^popcount(x&z).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+expect_term_kernel(int n, const typename VecOf<T>::type* __restrict__ psi, uint64_t x, uint64_t z,
+                   uint32_t hbit, T cre, T cim, double* __restrict__ part) {
+    using V = typename VecOf<T>::type;
+    __shared__ double red[2][kBlock];
+    const int tid = threadIdx.x;
+    const uint64_t count = (x == 0) ? (1ull << n) : (1ull << (n - 1));
+    const uint64_t hmask = (x == 0) ? 0 : ((1ull << hbit) - 1);
+    double v_acc = 0.0, n_acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + tid; i < count; i += stride) {
+        uint64_t b = i;
+        if (x != 0) {
+            const uint64_t low = i & hmask;
+            b = ((i ^ low) << 1) | low;
+        }
+        const V p = psi[b];
+        const T sgn = (__popcll(z & b) & 1) ? T(-1) : T(1);
+        if (x == 0) {
+            const T m = p.x * p.x + p.y * p.y;
+            v_acc += (double)(sgn * m);
+            n_acc += (double)m;
+        } else {
+            const V q = psi[b ^ x];
+            // conj(p) * (cre + i cim) * q
+            const T qr = cre * q.x - cim * q.y, qi = cre * q.y + cim * q.x;
+            v_acc += 2.0 * (double)(sgn * (p.x * qr + p.y * qi));
+            n_acc += (double)(p.x * p.x + p.y * p.y + q.x * q.x + q.y * q.y);
+        }
+    }
+    red[0][tid] = v_acc;
+    red[1][tid] = n_acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            red[0][tid] += red[0][tid + w];
+            red[1][tid] += red[1][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        part[2 * blockIdx.x + 0] = red[0][0];
+        part[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+// ---------------------------------------------------------------- misc
+template <typename V>
+__global__ void __launch_bounds__(kBlock) set_basis_kernel(V* __restrict__ psi, uint64_t dim, uint64_t b) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < dim; i += stride) {
+        V v;
+        v.x = (i == b) ? 1 : 0;
+        v.y = 0;
+        psi[i] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) zero_kernel(double* __restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kBlock) copy_kernel(const V* __restrict__ src, V* __restrict__ dst, uint64_t dim) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < dim; i += stride) dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(kBlock)
+reduce_kernel(const double* __restrict__ part, uint32_t nblocks, uint32_t nslots,
+              const int32_t* __restrict__ map, double* __restrict__ out, int accumulate) {
+    __shared__ double red[kBlock];
+    const int tid = threadIdx.x;
+    const uint32_t s = blockIdx.x;
+    double acc = 0.0;
+    for (uint32_t i = tid; i < nblocks; i += kBlock) acc += part[(uint64_t)i * nslots + s];
+    red[tid] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int idx = map ? map[s] : (int)s;
+        out[idx] = accumulate ? out[idx] + red[0] : red[0];
+    }
+}
+
+uint32_t grid_for(uint64_t items) {
+    uint64_t b = (items + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > (uint64_t)kMaxBlocks) b = kMaxBlocks;
+    return (uint32_t)b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_set_basis(int dtype, void* psi, uint64_t dim, uint64_t b, hipStream_t st) {
+    const uint32_t g = grid_for(dim);
+    if (dtype == VQE_C64)
+        hipLaunchKernelGGL(set_basis_kernel<float2>, dim3(g), dim3(kBlock), 0, st, (float2*)psi, dim, b);
+    else
+        hipLaunchKernelGGL(set_basis_kernel<double2>, dim3(g), dim3(kBlock), 0, st, (double2*)psi, dim, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, uint64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int dtype, const void* src, void* dst, uint64_t dim, hipStream_t st) {
+    const uint32_t g = grid_for(dim);
+    if (dtype == VQE_C64)
+        hipLaunchKernelGGL(copy_kernel<float2>, dim3(g), dim3(kBlock), 0, st, (const float2*)src, (float2*)dst, dim);
+    else
+        hipLaunchKernelGGL(copy_kernel<double2>, dim3(g), dim3(kBlock), 0, st, (const double2*)src, (double2*)dst, dim);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_window_fwd(const PassArgs<T>& a, const void* in, void* out, hipStream_t st) {
+    using V = typename VecOf<T>::type;
+    const uint32_t g = grid_for(a.n_cosets);
+    const V* i0 = (const V*)in;
+    V* o0 = (V*)out;
+    switch (a.K) {
+        case 1: hipLaunchKernelGGL((window_kernel<T, 1, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
+        case 2: hipLaunchKernelGGL((window_kernel<T, 2, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
+        case 3: hipLaunchKernelGGL((window_kernel<T, 3, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
+        case 4: hipLaunchKernelGGL((window_kernel<T, 4, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
+        case 5: hipLaunchKernelGGL((window_kernel<T, 5, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_window_rev(const PassArgs<T>& a, const void* psi_in, void* psi_out, const void* lam_in,
+                             void* lam_out, double* gpart, uint32_t* nblocks, hipStream_t st) {
+    using V = typename VecOf<T>::type;
+    const uint32_t g = grid_for(a.n_cosets);
+    *nblocks = g;
+    const V* i0 = (const V*)psi_in;
+    V* o0 = (V*)psi_out;
+    const V* i1 = (const V*)lam_in;
+    V* o1 = (V*)lam_out;
+    switch (a.K) {
+        case 1: hipLaunchKernelGGL((window_kernel<T, 1, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
+        case 2: hipLaunchKernelGGL((window_kernel<T, 2, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
+        case 3: hipLaunchKernelGGL((window_kernel<T, 3, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
+        case 4: hipLaunchKernelGGL((window_kernel<T, 4, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
+        case 5: hipLaunchKernelGGL((window_kernel<T, 5, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* groups, uint32_t n_groups,
+                       const TermDesc<T>* terms, int mode, double* part, uint32_t* nblocks, hipStream_t st) {
+    using V = typename VecOf<T>::type;
+    const int tb = n < kTileBits ? n : kTileBits;
+    const uint64_t n_tiles = 1ull << (n - tb);
+    const uint32_t g = n_tiles > (uint64_t)kMaxBlocks ? (uint32_t)kMaxBlocks : (uint32_t)n_tiles;
+    *nblocks = g;
+    const int tile = 1 << tb;
+    const int R = tile >= 4 * kBlock ? 4 : (tile >= 2 * kBlock ? 2 : 1);
+    const V* p = (const V*)psi;
+    V* l = (V*)lam;
+#define VQE_HPSI(RR, MM) \
+    hipLaunchKernelGGL((hpsi_kernel<T, RR, MM>), dim3(g), dim3(kBlock), 0, st, n, tb, p, l, groups, n_groups, terms, part)
+    if (mode == 0) {
+        if (R == 4) VQE_HPSI(4, 0); else if (R == 2) VQE_HPSI(2, 0); else VQE_HPSI(1, 0);
+    } else {
+        if (R == 4) VQE_HPSI(4, 1); else if (R == 2) VQE_HPSI(2, 1); else VQE_HPSI(1, 1);
+    }
+#undef VQE_HPSI
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_expect_term(int n, const void* psi, uint64_t x, uint64_t z, double* part,
+                              uint32_t* nblocks, hipStream_t st) {
+    using V = typename VecOf<T>::type;
+    const uint64_t count = (x == 0) ? (1ull << n) : (1ull << (n - 1));
+    const uint32_t g = grid_for(count);
+    *nblocks = g;
+    uint32_t hbit = 0;
+    if (x != 0) hbit = 63 - __builtin_clzll(x);
+    const int y = __builtin_popcountll(x & z) & 3;
+    // (-i)^y
+    const T cre = (y == 0) ? T(1) : (y == 2 ? T(-1) : T(0));
+    const T cim = (y == 1) ? T(-1) : (y == 3 ? T(1) : T(0));
+    hipLaunchKernelGGL(expect_term_kernel<T>, dim3(g), dim3(kBlock), 0, st, n, (const V*)psi, x, z, hbit, cre, cim, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* part, uint32_t nblocks, uint32_t nslots, const int32_t* map, double* out,
+                         int accumulate, hipStream_t st) {
+    if (nslots == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(nslots), dim3(kBlock), 0, st, part, nblocks, nslots, map, out, accumulate);
+    return hipGetLastError();
+}
+
+template hipError_t launch_window_fwd<float>(const PassArgs<float>&, const void*, void*, hipStream_t);
+template hipError_t launch_window_fwd<double>(const PassArgs<double>&, const void*, void*, hipStream_t);
+template hipError_t launch_window_rev<float>(const PassArgs<float>&, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_window_rev<double>(const PassArgs<double>&, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, double*, uint32_t*, hipStream_t);
+template hipError_t launch_expect_term<float>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);
+template hipError_t launch_expect_term<double>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);
+
+}  // namespace vqe

@@ -1,0 +1,130 @@
+// Internal definitions shared by the host side (planner, Hamiltonian tables,
+// C ABI) and the HIP kernels of the VQE library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/vqe.h"
+
+namespace vqe {
+
+// ---------------------------------------------------------------- limits
+constexpr int kMaxWindow = 5;     // qubits fused per pass (2^5 amplitudes per thread)
+constexpr int kWindowC64 = 5;     // window used for complex64 states
+constexpr int kWindowC128 = 4;    // window used for complex128 states (register budget)
+constexpr int kMaxOps = 64;       // kernel ops per pass
+constexpr int kMaxMats = 32;      // 2x2 matrices per pass
+constexpr int kMaxGradSlots = 16; // parameterised gates per pass
+constexpr int kBlock = 256;       // threads per block of every streaming kernel
+constexpr int kMaxBlocks = 2048;  // grid-stride kernels use at most this many blocks
+constexpr int kTileBits = 10;     // amplitudes per Hamiltonian tile = 2^kTileBits
+
+// ---------------------------------------------------------------- kernel ops
+// A fused pass is a list of ops on the local bits 0..K-1 of a window.
+enum OpType : uint8_t {
+    OP_U2 = 0,    // general complex 2x2 on bit a, matrix mats[slot]
+    OP_R2 = 1,    // real 2x2 on bit a (re parts of mats[slot])
+    OP_DIAG = 2,  // diag(m00, m11) on bit a
+    OP_CNOT = 3,  // control a, target b
+    OP_CZ = 4,    // phase -1 where bits a and b are both set
+    OP_XFLIP = 5, // Pauli X on bit a
+    OP_GX = 6,    // gradient slot += Im<lam| X_a |psi>
+    OP_GY = 7,    // gradient slot += Im<lam| Y_a |psi>
+    OP_GZ = 8,    // gradient slot += Im<lam| Z_a |psi>
+};
+
+struct KOp {
+    uint8_t type, a, b, slot;
+};
+
+// Matrix of a 2x2 op: row-major entries u00 u01 u10 u11, each (re, im).
+template <typename T>
+struct Mat2 {
+    T v[8];
+};
+
+template <typename T>
+struct PassArgs {
+    uint64_t n_cosets;      // 2^(n-K): one coset = the 2^K amplitudes of a window
+    uint32_t K;
+    uint32_t n_ops;
+    uint32_t n_gslots;
+    uint32_t pos[kMaxWindow];  // window qubits, ascending
+    KOp ops[kMaxOps];
+    Mat2<T> mats[kMaxMats];
+};
+
+// ---------------------------------------------------------------- Hamiltonian tables
+// Terms grouped by x mask.  For group g, terms [begin, end) carry z masks and
+// the coefficient c = w * (-i)^popcount(x&z) split as (cre, cim), so that
+// (H psi)[b] = sum_g psi[b ^ x_g] * sum_t c_t (-1)^popcount(z_t & b).
+struct GroupDesc {
+    uint64_t x;
+    uint32_t begin, end;
+    uint32_t hbit;     // highest set bit of x (0 for x = 0)
+    uint32_t pad;
+};
+
+template <typename T>
+struct TermDesc {
+    uint64_t z;
+    T cre, cim;
+};
+
+// ---------------------------------------------------------------- launchers (kernels.hip)
+hipError_t launch_set_basis(int dtype, void* psi, uint64_t dim, uint64_t b, hipStream_t st);
+hipError_t launch_zero(double* p, uint64_t n, hipStream_t st);
+hipError_t launch_copy(int dtype, const void* src, void* dst, uint64_t dim, hipStream_t st);
+
+// in == out allowed (in place).  NV = 1 vector.
+template <typename T>
+hipError_t launch_window_fwd(const PassArgs<T>& a, const void* in, void* out, hipStream_t st);
+
+// Reverse pass on (psi, lam); writes per-block gradient partials
+// [blocks][n_gslots] into gpart.  Returns the block count used via *nblocks.
+template <typename T>
+hipError_t launch_window_rev(const PassArgs<T>& a, const void* psi_in, void* psi_out,
+                             const void* lam_in, void* lam_out, double* gpart,
+                             uint32_t* nblocks, hipStream_t st);
+
+// H psi tile kernel.  mode 0: lam = H psi and (Re<psi|lam>, <psi|psi>) partials.
+// mode 1: energy partials only, off-tile groups visited once per pair.
+template <typename T>
+hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* groups, uint32_t n_groups,
+                       const TermDesc<T>* terms, int mode, double* part, uint32_t* nblocks,
+                       hipStream_t st);
+
+// One term: partials of Re<psi|P(x,z)|psi> (pair-halved) and <psi|psi>.
+template <typename T>
+hipError_t launch_expect_term(int n, const void* psi, uint64_t x, uint64_t z, double* part,
+                              uint32_t* nblocks, hipStream_t st);
+
+// out[map ? map[s] : s] (+)= sum over blocks of part[block][s], fixed order, FP64.
+hipError_t launch_reduce(const double* part, uint32_t nblocks, uint32_t nslots,
+                         const int32_t* map, double* out, int accumulate, hipStream_t st);
+
+// ---------------------------------------------------------------- planner (plan.cpp)
+struct Gate {
+    int kind, q0, q1, pidx;
+    double angle;
+};
+
+struct PlannedPass {
+    int K = 0;
+    int pos[kMaxWindow] = {0};
+    std::vector<int> gates;      // indices into the circuit's gate list, execution order
+};
+
+// Partition gates into fused passes.  Returns false (with msg) on failure.
+// kmax = largest window (<= kMaxWindow).
+bool plan_passes(int n, const std::vector<Gate>& gates, int kmax, std::vector<PlannedPass>& out,
+                 std::string& msg);
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& m);
+
+}  // namespace vqe

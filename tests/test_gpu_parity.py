@@ -1,0 +1,237 @@
+"""GPU parity of the HIP path against the CPU FP64 oracle, through the C ABI.
+
+Tolerances (relative errors are |x - ref| / max(|ref|, 1)):
+  energies      complex128 <= 1e-10, complex64 <= 1e-5;
+  amplitudes    complex128 <= 1e-12 absolute, complex64 <= 2e-5 absolute
+                (unit-norm vectors; FP32 rounding of O(10^2) gates);
+  gradients     complex128 max|g - g_ref| / max(|g_ref|_inf, 1) <= 1e-9,
+                complex64 <= 1e-4.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import expect as oex, grad as ogr, hamiltonian as oham, statevector as osv
+from paper_2402_11878_amd import _lib, ansatz, hamiltonians as lham
+
+from gpu_util import Dev, oracle_gates, rel_err, say, tol_energy
+from test_host import random_circuit
+
+pytestmark = pytest.mark.gpu
+
+DT = {"c64": _lib.VQE_C64, "c128": _lib.VQE_C128}
+AMP_TOL = {_lib.VQE_C64: 2e-5, _lib.VQE_C128: 1e-12}
+GRAD_TOL = {_lib.VQE_C64: 1e-4, _lib.VQE_C128: 1e-9}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    assert _lib.vqe_device_count() >= 1
+    yield
+    torch.cuda.synchronize()
+
+
+def _ham_from_oracle(H, n):
+    x, z, w = oham.to_masks(H)
+    return _lib.vqe_hamiltonian_create(n, x, z, w), (x, z, w)
+
+
+def _random_pauli_sum(n, n_terms, seed):
+    rng = np.random.default_rng(seed)
+    H = {}
+    for _ in range(n_terms):
+        s = tuple(rng.choice(list("IXYZ"), size=n, p=[0.4, 0.2, 0.2, 0.2]))
+        H[s] = H.get(s, 0.0) + float(rng.normal())
+    H[tuple("I" * n)] = 0.3
+    return H
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,kind,seed", [
+    (1, "random", 11), (2, "random", 12), (3, "random", 13), (5, "random", 14), (7, "random", 15),
+    (9, "layered", 16), (11, "random", 17), (12, "layered", 18), (14, "random", 19)])
+def test_state_matches_oracle(n, kind, seed, dt):
+    dtype = DT[dt]
+    if kind == "layered":
+        arr, P = ansatz.layered(n, 3), 6 * n
+    else:
+        arr, P = random_circuit(n, 60 + 5 * n, seed)
+    th = synth.theta(seed, max(P, 1))[:P]
+    say(f"case state n={n} {kind} seed={seed} {dt}")
+    ref = osv.run(n, oracle_gates(arr), th)
+    c = _lib.vqe_circuit_create(n, arr)
+    s = Dev(n, dtype)
+    try:
+        _lib.vqe_state_set_basis(s.h, 0)
+        _lib.vqe_apply_circuit(s.h, c, th)
+        got = s.read()
+        assert np.max(np.abs(got - ref)) <= AMP_TOL[dtype]
+    finally:
+        s.free()
+        _lib.vqe_circuit_free(c)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,seed", [(3, 1), (6, 2), (8, 3), (9, 4), (10, 5), (11, 6), (13, 7)])
+def test_energy_random_pauli_sums(n, seed, dt):
+    """Grouped and per-term energies and H psi on random Pauli sums with every
+    Pauli type (X, Y, Z mixtures) and tiles spanning several blocks."""
+    dtype = DT[dt]
+    say(f"case energy-random n={n} seed={seed} {dt}")
+    H = _random_pauli_sum(n, 40, seed)
+    arr, P = ansatz.layered(n, 2), 4 * n
+    th = synth.theta(seed, P)
+    psi_ref = osv.run(n, oracle_gates(arr), th)
+    E_ref, _ = oex.energy(psi_ref, n, H)
+    lam_ref = oex.apply_hamiltonian(psi_ref, n, H)
+    h, _ = _ham_from_oracle(H, n)
+    c = _lib.vqe_circuit_create(n, arr)
+    s, l = Dev(n, dtype), Dev(n, dtype)
+    try:
+        _lib.vqe_state_set_basis(s.h, 0)
+        _lib.vqe_apply_circuit(s.h, c, th)
+        for mode in (_lib.EXPECT_GROUPED, _lib.EXPECT_PER_TERM):
+            E, nrm = _lib.vqe_expect_pauli(s.h, h, mode)
+            assert rel_err(E, E_ref) <= tol_energy(dtype), (mode, E, E_ref)
+            assert abs(nrm - 1.0) <= (1e-12 if dtype == _lib.VQE_C128 else 1e-5)
+        E2, _ = _lib.vqe_apply_hamiltonian(s.h, l.h, h)
+        assert rel_err(E2, E_ref) <= tol_energy(dtype)
+        lam = l.read()
+        scale = max(np.max(np.abs(lam_ref)), 1.0)
+        assert np.max(np.abs(lam - lam_ref)) / scale <= (1e-12 if dtype == _lib.VQE_C128 else 2e-5)
+    finally:
+        s.free(), l.free()
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_config0_energy_and_gradients(dt):
+    """12-qubit 1-D Hubbard chain, 4 layers, 96 parameters, seed 0: energy,
+    adjoint gradient and GPU parameter shift against the oracle's parameter
+    shift."""
+    dtype = DT[dt]
+    wl = synth.WORKLOADS["hubbard1d_6"]
+    n = wl.n_qubits
+    say(f"case config0 {dt}")
+    Ho = oham.hubbard(wl.lattice.n_sites, list(wl.lattice.bonds), wl.lattice.t, wl.lattice.U)
+    x, z, w = lham.from_lattice(wl.lattice)
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    arr = ansatz.layered(n, wl.layers)
+    og = oracle_gates(arr)
+    th = wl.thetas()[0]
+    E_ref, _ = oex.energy(osv.run(n, og, th), n, Ho)
+    ps = ogr.param_shift(n, og, th, Ho)
+    g_ref = np.array([ps[k] for k in range(len(th))])
+    gscale = max(np.max(np.abs(g_ref)), 1.0)
+    c = _lib.vqe_circuit_create(n, arr)
+    s, l = Dev(n, dtype), Dev(n, dtype)
+    try:
+        E, g = _lib.vqe_energy_grad(s.h, l.h, c, th, h)
+        assert rel_err(E, E_ref) <= tol_energy(dtype)
+        assert np.max(np.abs(g - g_ref)) / gscale <= GRAD_TOL[dtype]
+        for mode in (_lib.EXPECT_GROUPED, _lib.EXPECT_PER_TERM):
+            E2, g2 = _lib.vqe_energy_grad(s.h, None, c, th, h, method=_lib.GRAD_PARAM_SHIFT, expect_mode=mode)
+            assert rel_err(E2, E_ref) <= tol_energy(dtype)
+            assert np.max(np.abs(g2 - g_ref)) / gscale <= (1e-9 if dtype == _lib.VQE_C128 else 1e-4)
+    finally:
+        s.free(), l.free()
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,seed", [(5, 21), (10, 22)])
+def test_adjoint_random_circuits(n, seed, dt):
+    """Adjoint gradient on random circuits with every gate kind (RX parameters,
+    H, X, CZ, reversed CNOTs) against the oracle adjoint and parameter shift."""
+    dtype = DT[dt]
+    say(f"case adjoint-random n={n} {dt}")
+    arr, P = random_circuit(n, 70, seed)
+    th = synth.theta(seed, P)
+    og = oracle_gates(arr)
+    H = _random_pauli_sum(n, 30, seed)
+    E_ref, g_ref = ogr.adjoint(n, og, th, H)
+    ps = ogr.param_shift(n, og, th, H, indices=range(0, P, 7))
+    for k, v in ps.items():
+        assert abs(v - g_ref[k]) < 1e-10
+    h, _ = _ham_from_oracle(H, n)
+    c = _lib.vqe_circuit_create(n, arr)
+    s, l = Dev(n, dtype), Dev(n, dtype)
+    try:
+        E, g = _lib.vqe_energy_grad(s.h, l.h, c, th, h)
+        gscale = max(np.max(np.abs(g_ref)), 1.0)
+        assert rel_err(E, E_ref) <= tol_energy(dtype)
+        assert np.max(np.abs(g - g_ref)) / gscale <= GRAD_TOL[dtype]
+    finally:
+        s.free(), l.free()
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_checkpoints_and_determinism(dt):
+    """Checkpointed reverse sweeps give the gradient of the plain sweep; two
+    identical calls return identical bits."""
+    dtype = DT[dt]
+    n, L = 13, 6
+    say(f"case ckpt n={n} {dt}")
+    h_, g_ = synth.molecule_integrals(3, 4)
+    x, z, w = lham.molecule(h_, g_)
+    # embed the 6-qubit molecule into 13 qubits (upper qubits idle)
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    arr = ansatz.layered(n, L)
+    th = synth.theta(5, 2 * n * L)
+    c = _lib.vqe_circuit_create(n, arr)
+    s, l = Dev(n, dtype), Dev(n, dtype)
+    cks = [Dev(n, dtype) for _ in range(3)]
+    try:
+        E0, g0 = _lib.vqe_energy_grad(s.h, l.h, c, th, h)
+        E0b, g0b = _lib.vqe_energy_grad(s.h, l.h, c, th, h)
+        assert E0 == E0b and np.array_equal(g0, g0b)
+        for k in (1, 3):
+            E1, g1 = _lib.vqe_energy_grad(s.h, l.h, c, th, h, ckpt=[cc.h for cc in cks[:k]])
+            assert E1 == E0
+            assert np.max(np.abs(g1 - g0)) <= (1e-12 if dtype == _lib.VQE_C128 else 2e-5)
+        Ho = oham.from_masks(n, x, z, w)
+        E_ref, g_ref = ogr.adjoint(n, oracle_gates(arr), th, Ho)
+        assert rel_err(E0, E_ref) <= tol_energy(dtype)
+        assert np.max(np.abs(g0 - g_ref)) / max(np.max(np.abs(g_ref)), 1) <= GRAD_TOL[dtype]
+    finally:
+        for d in [s, l] + cks:
+            d.free()
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
+
+
+def test_library_owned_state_and_errors():
+    """A state whose memory the library allocates; argument errors on device calls."""
+    n = 6
+    say("case owned-state")
+    sh = _lib.vqe_state_alloc(n, _lib.VQE_C128)
+    sh2 = _lib.vqe_state_alloc(n + 1, _lib.VQE_C128)
+    try:
+        v = _lib.vqe_state_read(sh, 0, 1 << n, _lib.VQE_C128)
+        assert v[0] == 1.0 and np.all(v[1:] == 0)
+        _lib.vqe_state_set_basis(sh, 5)
+        v = _lib.vqe_state_read(sh, 0, 1 << n, _lib.VQE_C128)
+        assert v[5] == 1.0 and np.sum(np.abs(v)) == 1.0
+        with pytest.raises(_lib.VqeError):
+            _lib.vqe_state_set_basis(sh, 1 << n)
+        c = _lib.vqe_circuit_create(n, ansatz.layered(n, 1))
+        with pytest.raises(_lib.VqeError):
+            _lib.vqe_apply_circuit(sh, c, np.zeros(3))        # wrong parameter count
+        with pytest.raises(_lib.VqeError):
+            _lib.vqe_apply_circuit(sh2, c, np.zeros(2 * n))   # wrong qubit count
+        h = _lib.vqe_hamiltonian_create(n, np.array([1], np.uint64), np.array([0], np.uint64), np.array([1.0]))
+        with pytest.raises(_lib.VqeError):
+            _lib.vqe_energy_grad(sh, sh, c, np.zeros(2 * n), h)  # lam must differ from psi
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
+    finally:
+        _lib.vqe_state_free(sh)
+        _lib.vqe_state_free(sh2)

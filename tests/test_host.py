@@ -1,0 +1,220 @@
+"""Host-side tests of the library (no GPU needed).
+
+* libvqe.so loads and exports every function declared in include/vqe.h;
+* the library's bit-mask Jordan-Wigner equals the oracle's string JW
+  (masks bit-exact, coefficients within 1e-14);
+* vqe_slim_hamiltonian selects exactly the oracle's terms;
+* the fused pass plan is a valid reordering of the circuit (checked by running
+  both orders in the oracle) and respects the window limits;
+* C ABI argument checking.
+"""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import hamiltonian as oham, slim as oslim, statevector as osv
+from paper_2402_11878_amd import _lib, ansatz, hamiltonians as lham
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_header_symbols():
+    hdr = open(os.path.join(ROOT, "include", "vqe.h")).read()
+    declared = set(re.findall(r"^(?:const char\*|int)\s+(vqe_\w+)\s*\(", hdr, flags=re.M))
+    assert len(declared) >= 20
+    L = _lib.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(_lib.exported_symbols())
+
+
+def _oracle_masks(H):
+    return oham.to_masks(H)
+
+
+@pytest.mark.parametrize("name", ["hubbard1d_6", "hubbard2x7", "hubbard4x4"])
+def test_jw_hubbard_matches_oracle(name):
+    lat = synth.WORKLOADS[name].lattice
+    ox, oz, ow = _oracle_masks(oham.hubbard(lat.n_sites, list(lat.bonds), lat.t, lat.U))
+    lx, lz, lw = lham.from_lattice(lat)
+    assert np.array_equal(ox, lx) and np.array_equal(oz, lz)
+    assert np.max(np.abs(ow - lw)) <= 1e-14
+
+
+@pytest.mark.parametrize("n_orb,seed", [(2, 0), (3, 1), (4, 2)])
+def test_jw_molecule_matches_oracle(n_orb, seed):
+    h, g = synth.molecule_integrals(n_orb, seed)
+    ox, oz, ow = _oracle_masks(oham.molecule(h, g))
+    lx, lz, lw = lham.molecule(h, g)
+    assert np.array_equal(ox, lx) and np.array_equal(oz, lz)
+    assert np.max(np.abs(ow - lw)) <= 1e-14
+
+
+def test_hamiltonian_tables_group_counts():
+    for name, terms, groups in (("hubbard1d_6", 39, 11), ("hubbard2x7", 127, 43), ("hubbard4x4", 145, 49)):
+        wl = synth.WORKLOADS[name]
+        x, z, w = lham.from_lattice(wl.lattice)
+        h = _lib.vqe_hamiltonian_create(wl.n_qubits, x, z, w)
+        nt, ng, idw = _lib.vqe_hamiltonian_info(h)
+        _lib.vqe_hamiltonian_free(h)
+        assert (nt, ng) == (terms, groups)
+        assert abs(idw - wl.lattice.n_sites * wl.lattice.U / 4) < 1e-12
+
+
+def _slim_inputs(seed, ties):
+    rng = np.random.default_rng(seed)
+    n = 300
+    x = rng.integers(0, 1 << 12, size=n).astype(np.uint64)
+    z = rng.integers(0, 1 << 12, size=n).astype(np.uint64)
+    w = rng.normal(size=n) * 10.0 ** rng.uniform(-7, 0, size=n)
+    if ties:
+        w = np.round(w * 8) / 8
+        w[w == 0] = -0.125
+    x[0] = z[0] = 0
+    x[5] = z[5] = 0          # a repeated identity entry
+    return x, z, w
+
+
+@pytest.mark.parametrize("seed,ties", [(0, False), (1, True), (2, True), (3, False)])
+def test_slim_matches_oracle_bit_exact(seed, ties):
+    x, z, w = _slim_inputs(seed, ties)
+    ths = [0.0, 1e-6, 1e-4, 1e-3, 0.125, float(abs(w[17])), float(abs(w[42]))]
+    for th in ths:
+        keep, nk, dropped = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_THRESHOLD, th)
+        ok, od = oslim.threshold(x, z, w, th)
+        assert np.array_equal(keep, ok) and nk == int(ok.sum()) and dropped == od
+    for pct in (0, 10, 25, 60, 70, 80, 90, 100):
+        keep, nk, dropped = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_REMOVE_PERCENT, pct)
+        ok, od = oslim.remove_percent(x, z, w, pct)
+        assert np.array_equal(keep, ok) and dropped == od
+    for lim in (0.0, 1e-5, 1e-3, 0.5, 3.0, 1e9):
+        keep, nk, dropped = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_BUDGET, lim)
+        ok, od = oslim.budget(x, z, w, lim)
+        assert np.array_equal(keep, ok) and dropped == od
+
+
+def test_slim_molecule_counts_monotone():
+    h, g = synth.molecule_integrals(4, 0)
+    x, z, w = lham.molecule(h, g)
+    prev = len(w) + 1
+    for th in (0.0, 1e-6, 1e-4, 1e-3, 1e-2):
+        keep, nk, dropped = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_THRESHOLD, th)
+        assert nk <= prev
+        prev = nk
+
+
+def test_slim_argument_errors():
+    x = np.zeros(2, np.uint64)
+    w = np.ones(2)
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_slim_hamiltonian(x, x, w, 7, 0.1)
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_slim_hamiltonian(x, x, w, _lib.SLIM_REMOVE_PERCENT, 12.5)
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_slim_hamiltonian(x, x, w, _lib.SLIM_THRESHOLD, -1.0)
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_slim_hamiltonian(x, x, np.array([1.0, np.nan]), _lib.SLIM_THRESHOLD, 0.1)
+
+
+def _oracle_gates(arr):
+    names = {0: "RY", 1: "RZ", 2: "RX", 3: "H", 4: "X", 5: "CNOT", 6: "CZ"}
+    return [(names[int(g["kind"])], int(g["q0"]), int(g["q1"]), int(g["param_index"]), float(g["angle"]))
+            for g in arr]
+
+
+def random_circuit(n, n_gates, seed):
+    rng = np.random.default_rng(seed)
+    gates = []
+    p = 0
+    for _ in range(n_gates):
+        k = int(rng.integers(0, 7))
+        q0 = int(rng.integers(0, n))
+        q1 = int(rng.integers(0, n - 1)) if n > 1 else 0
+        if q1 >= q0:
+            q1 += 1
+        if k in (5, 6) and n < 2:
+            k = 0
+        if k in (0, 1, 2):
+            if rng.random() < 0.7:
+                gates.append((k, q0, 0, p, 0.0))
+                p += 1
+            else:
+                gates.append((k, q0, 0, -1, float(rng.uniform(-3, 3))))
+        elif k in (5, 6):
+            gates.append((k, q0, q1, -1, 0.0))
+        else:
+            gates.append((k, q0, 0, -1, 0.0))
+    return ansatz.gates_array(gates), p
+
+
+@pytest.mark.parametrize("n,kind,seed", [(8, "layered", 0), (13, "layered", 1), (7, "random", 2), (9, "random", 3),
+                                         (1, "random", 4), (2, "random", 5)])
+def test_plan_is_valid_reordering(n, kind, seed):
+    if kind == "layered":
+        arr = ansatz.layered(n, 3)
+        P = 6 * n
+    else:
+        arr, P = random_circuit(n, 80, seed)
+    c = _lib.vqe_circuit_create(n, arr)
+    try:
+        og = _oracle_gates(arr)
+        th = synth.theta(seed, max(P, 1))
+        ref = osv.run(n, og, th)
+        for dtype, kmax in ((_lib.VQE_C64, 5), (_lib.VQE_C128, 4)):
+            order = []
+            p = 0
+            while True:
+                try:
+                    qubits, idx = _lib.vqe_circuit_pass(c, dtype, p)
+                except _lib.VqeError:
+                    break
+                assert 1 <= len(qubits) <= min(kmax, n)
+                for gi in idx:
+                    g = og[gi]
+                    assert g[1] in qubits
+                    if g[0] in ("CNOT", "CZ"):
+                        assert g[2] in qubits
+                order += idx
+                p += 1
+            assert sorted(order) == list(range(len(og)))
+            got = osv.run(n, [og[i] for i in order], th)
+            assert np.max(np.abs(got - ref)) < 1e-12
+    finally:
+        _lib.vqe_circuit_free(c)
+
+
+def test_plan_pass_counts_beat_layerwise():
+    for n, L in ((20, 8), (28, 16), (32, 8)):
+        c = _lib.vqe_circuit_create(n, ansatz.layered(n, L))
+        _, npass = _lib.vqe_circuit_info(c)
+        _lib.vqe_circuit_free(c)
+        assert npass <= L * math.ceil((n - 1) / 4)
+
+
+def test_abi_argument_errors():
+    g = ansatz.layered(4, 1)
+    with pytest.raises(_lib.VqeError) as e:
+        _lib.vqe_circuit_create(41, g)
+    assert e.value.code == _lib.VQE_ERR_ARG
+    bad = g.copy()
+    bad[0]["q0"] = 9
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_circuit_create(4, bad)
+    bad = g.copy()
+    bad[-1]["param_index"] = 3          # CNOT cannot take a parameter
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_circuit_create(4, bad)
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_hamiltonian_create(3, np.array([8], np.uint64), np.array([0], np.uint64), np.array([1.0]))
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_hamiltonian_create(3, np.array([1], np.uint64), np.array([0], np.uint64), np.array([np.inf]))
+    if _lib.vqe_device_count() == 0:
+        with pytest.raises(_lib.VqeError) as e:
+            _lib.vqe_state_alloc(4, _lib.VQE_C64)
+        assert e.value.code == _lib.VQE_ERR_DEVICE
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_state_alloc(4, 7)
