@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: VQE energy + adjoint-gradient evaluations per second at 32 qubits.
+
+One step = one pass of the whole hot path on one parameter vector: reset to
+|0...0>, the fused forward ansatz sweeps (eq. 6), lam = H psi with the energy
+(eq. 7) from the X-mask-grouped kernel, and the reverse sweep that un-applies
+every gate from (psi, lam) while accumulating dE/dtheta for all parameters.
+
+Workload (default): 2-D Fermi-Hubbard on a 4 x 4 open lattice, t = 1, U = 4,
+Jordan-Wigner in snake order (32 qubits, 145 Pauli terms, 49 X-mask groups),
+8 layers of [RY, RZ on every qubit; CNOT ladder] = 760 gates and 512
+parameters drawn uniform in [-pi, pi) from seed 0.  The headline figure uses
+a complex128 state (64 GiB per vector, psi + lam + one checkpoint); the same
+step on a complex64 state (FP32 amplitudes, FP64 reductions) is reported
+beside it, with its energy and gradient error against the complex128 result.
+
+Prints one JSON line.  Inputs are synthetic and resident in HBM before the
+timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_dtype(torch, L, core, wl, dtype, n_ckpt, steps, warmup, theta):
+    """Times `steps` energy+gradient evaluations; returns a result dict."""
+    from paper_2402_11878_amd import hamiltonians as hm
+    n = wl.n_qubits
+    x, z, w = hm.from_lattice(wl.lattice)
+    H = core.Hamiltonian(n, x, z, w)
+    circ = core.Circuit.layered(n, wl.layers)
+    tdt = torch.complex64 if dtype == L.VQE_C64 else torch.complex128
+    bufs = [torch.empty(1 << n, dtype=tdt, device="cuda") for _ in range(2 + n_ckpt)]
+    st = torch.cuda.current_stream()
+    handles = [L.vqe_state_alloc(n, dtype, b.data_ptr(), b.numel() * b.element_size(), st.cuda_stream) for b in bufs]
+    psi, lam, ck = handles[0], handles[1], handles[2:]
+    name = "c64" if dtype == L.VQE_C64 else "c128"
+    try:
+        for i in range(warmup):
+            log(f"[bench] {name} warmup step {i + 1}/{warmup}")
+            E, g = L.vqe_energy_grad(psi, lam, circ.handle, theta, H.handle, ckpt=ck)
+        torch.cuda.synchronize()
+        L.vqe_profile_reset()
+        L.vqe_profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        energies = []
+        for i in range(steps):
+            E, g = L.vqe_energy_grad(psi, lam, circ.handle, theta, H.handle, ckpt=ck)
+            energies.append(E)
+            log(f"[bench] {name} step {i + 1}/{steps} E={E:.12f}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.vqe_profile_enable(False)
+        prof = {k: L.vqe_profile_read(k) for k in range(5)}
+        L.vqe_profile_reset()
+    finally:
+        for hnd in handles:
+            L.vqe_state_free(hnd)
+        del bufs
+        torch.cuda.empty_cache()
+    sec = (t1 - t0) / steps
+    return dict(name=name, sec=sec, E=energies[-1], grad=g, energies=energies, prof=prof,
+                n_gates=len(circ.gates), n_passes=circ.n_passes, n_terms=H.n_terms, n_groups=H.n_groups,
+                state_bytes=(1 << n) * (8 if dtype == L.VQE_C64 else 16), n_ckpt=n_ckpt)
+
+
+def cpu_baseline(wl_name):
+    """The CPU oracle, as it stands, on a bounded sample of the workload.
+
+    The 32-qubit state does not fit the oracle's NumPy temporaries on the
+    host, so the sample is the same workload shape at 20 qubits: a 2 x 5
+    open Hubbard lattice (t = 1, U = 4, snake order), the same ansatz at 4
+    layers, energy + adjoint gradient by the oracle's gate-by-gate reverse
+    sweep.  Its
+    time is scaled to the 32-qubit step by 2^(32-20) (state size) times the
+    ratio of (3 gates + terms) (gate sweeps of psi forward and of psi, lam in
+    reverse, plus one sweep per Hamiltonian term).
+    """
+    import synth
+    from oracle import grad as ogr, hamiltonian as oham, statevector as osv
+    wl = synth.WORKLOADS[wl_name]
+    ns = 20
+    bonds = synth.snake_bonds(2, 5, False)
+    Hs = oham.hubbard(10, bonds, 1.0, 4.0)
+    ls = 4
+    gates = osv.layered_ansatz(ns, ls)
+    th = synth.theta(0, 2 * ns * ls)
+    t0 = time.perf_counter()
+    ogr.adjoint(ns, gates, th, Hs)
+    t = time.perf_counter() - t0
+    lat = wl.lattice
+    T32 = 4 * len(lat.bonds) + 3 * lat.n_sites + 1
+    G32 = wl.layers * (2 * wl.n_qubits + wl.n_qubits - 1)
+    scale = 2.0 ** (wl.n_qubits - ns) * (3 * G32 + T32) / (3 * len(gates) + len(Hs))
+    return dict(value=1.0 / (t * scale), unit="evals/s", cores=1, kind="oracle",
+                sample=(f"oracle energy+adjoint gradient of a 20-qubit 2x5 Hubbard lattice with the same "
+                        f"ansatz at {ls} layers ({len(gates)} gates) took {t:.2f} s on 1 host core; scaled by "
+                        f"2^12 x (3*gates+terms) ratio, {scale:.0f} in all, to the 32-qubit step"),
+                sample_seconds=t, host_cpus=os.cpu_count())
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="hubbard4x4")
+    ap.add_argument("--skip-c64", action="store_true")
+    ap.add_argument("--skip-c128", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (the path is single-device; "
+              f"multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_2402_11878_amd import _lib as L, core
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    L.lib()
+    wl = synth.WORKLOADS[args.workload]
+    theta = wl.thetas()[0]
+    res = {}
+    if not args.skip_c128:
+        res["c128"] = run_dtype(torch, L, core, wl, L.VQE_C128, 1, args.steps, args.warmup, theta)
+    if not args.skip_c64:
+        res["c64"] = run_dtype(torch, L, core, wl, L.VQE_C64, 4, args.steps, args.warmup, theta)
+    head = res["c128"] if "c128" in res else res["c64"]
+
+    n_rev, ms_rev, b_rev = head["prof"][L.KERNEL_WINDOW_REV]
+    avg_ms = ms_rev / max(n_rev, 1)
+    bytes_per_launch = b_rev / max(n_rev, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernels = {}
+    names = {0: "window_fwd", 1: "window_rev", 2: "hpsi", 3: "expect_grouped", 4: "expect_per_term"}
+    for k, (cnt, ms, b) in head["prof"].items():
+        if cnt:
+            kernels[names[k]] = dict(launches=cnt, avg_ms=ms / cnt, gbs=(b / cnt) / (ms / cnt * 1e-3) / 1e9,
+                                     frac=(b / cnt) / (ms / cnt * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     share=ms / (head["sec"] * 1e3 * args.steps))
+    out = {
+        "metric": "VQE energy+adjoint-grad evals/s at 32q",
+        "value": 1.0 / head["sec"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["sec"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head["name"] == "c128" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: 2-D Fermi-Hubbard 4x4 open, t=1, U=4, JW snake order, {wl.n_qubits} qubits, "
+                        f"{head['n_terms']} Pauli terms / {head['n_groups']} X-groups; {wl.layers}-layer RY/RZ/CNOT "
+                        f"ansatz ({head['n_gates']} gates, {wl.n_params} params, seed {wl.theta_seed}); "
+                        f"{head['name']} state, {head['n_ckpt']} checkpoint(s); energy + adjoint gradient",
+            "n_qubits": wl.n_qubits,
+            "state": head["name"],
+            "fused_passes": head["n_passes"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "window_rev (reverse fused pass on psi and lam)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": avg_ms,
+        },
+        "kernels": kernels,
+        "gates_per_s": head["n_gates"] / head["sec"],
+        "pauli_terms_per_s": head["n_terms"] / head["sec"],
+        "energy": head["E"],
+    }
+    if "c64" in res and "c128" in res:
+        a, b = res["c64"], res["c128"]
+        gs = max(np.max(np.abs(b["grad"])), 1.0)
+        out["c64"] = dict(value=1.0 / a["sec"], ms_per_step=a["sec"] * 1e3,
+                          energy_rel_err_vs_c128=abs(a["E"] - b["E"]) / max(abs(b["E"]), 1.0),
+                          grad_err_vs_c128=float(np.max(np.abs(a["grad"] - b["grad"])) / gs),
+                          n_ckpt=a["n_ckpt"],
+                          window_rev_frac=(a["prof"][1][2] / a["prof"][1][0]) / (a["prof"][1][1] / a["prof"][1][0] * 1e-3)
+                          / 1e9 / HBM_PEAK_GBS if a["prof"][1][0] else None)
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

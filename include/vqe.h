@@ -199,6 +199,25 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,
                     const double* params, size_t n_params, const vqe_hamiltonian* h,
                     const vqe_grad_opts* opts, double* energy, double* grad);
 
+/* ------------------------------------------------------------------ tracing
+ * Per-kernel timing with HIP events.  While enabled (process-wide), every
+ * launch of a state-sweeping kernel is bracketed by two events recorded on
+ * the stream it runs on; vqe_profile_read synchronises those events and
+ * returns, for one kernel kind, the number of launches, their summed device
+ * time in milliseconds and their summed algorithmic bytes (the bytes the
+ * method must move: 2 S per forward window pass, 4 S per reverse window
+ * pass, (1 + D) S read + S written for H psi where D is the number of
+ * distinct partner tiles, S per per-term sweep; S = state bytes). */
+#define VQE_KERNEL_WINDOW_FWD  0
+#define VQE_KERNEL_WINDOW_REV  1
+#define VQE_KERNEL_HPSI        2
+#define VQE_KERNEL_EXPECT_HALF 3   /* grouped energy-only sweep (H psi without the write) */
+#define VQE_KERNEL_PER_TERM    4
+#define VQE_KERNEL_KINDS       5
+int vqe_profile_enable(int on);
+int vqe_profile_reset(void);
+int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* bytes);
+
 /* ------------------------------------------------------------------ slimming
  * Hamiltonian cutoff (Sec. II-D; terms sorted by |w|, small ones dropped).
  * Host only.  The identity term (x = z = 0) is always kept.  The order of

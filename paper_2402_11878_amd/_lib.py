@@ -19,6 +19,7 @@ GATE_RY, GATE_RZ, GATE_RX, GATE_H, GATE_X, GATE_CNOT, GATE_CZ = range(7)
 EXPECT_GROUPED, EXPECT_PER_TERM = 0, 1
 GRAD_ADJOINT, GRAD_PARAM_SHIFT = 0, 1
 SLIM_THRESHOLD, SLIM_REMOVE_PERCENT, SLIM_BUDGET = 0, 1, 2
+KERNEL_WINDOW_FWD, KERNEL_WINDOW_REV, KERNEL_HPSI, KERNEL_EXPECT_HALF, KERNEL_PER_TERM = range(5)
 
 
 class VqeError(RuntimeError):
@@ -67,6 +68,9 @@ _SIGS = {
     "vqe_apply_hamiltonian": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "vqe_energy_grad": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double), _SZ, _P, C.POINTER(vqe_grad_opts),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vqe_profile_enable": (C.c_int, [C.c_int]),
+    "vqe_profile_reset": (C.c_int, []),
+    "vqe_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "vqe_slim_hamiltonian": (C.c_int, [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_double),
                                        _SZ, C.c_int, C.c_double, C.POINTER(C.c_uint8), C.POINTER(_SZ),
                                        C.POINTER(C.c_double)]),
@@ -223,3 +227,17 @@ def vqe_slim_hamiltonian(x, z, w, mode, value):
         xp, zp, wp, len(w), mode, float(value), keep.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(nk),
         C.byref(dropped)))
     return keep, nk.value, dropped.value
+
+
+def vqe_profile_enable(on=True):
+    check("vqe_profile_enable", lib().vqe_profile_enable(1 if on else 0))
+
+
+def vqe_profile_reset():
+    check("vqe_profile_reset", lib().vqe_profile_reset())
+
+
+def vqe_profile_read(kind):
+    n, ms, b = C.c_uint64(), C.c_double(), C.c_double()
+    check("vqe_profile_read", lib().vqe_profile_read(kind, C.byref(n), C.byref(ms), C.byref(b)))
+    return n.value, ms.value, b.value

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 
 #include "vqe_internal.h"
@@ -95,6 +96,62 @@ struct vqe_hamiltonian {
 namespace {
 
 size_t amp_bytes(int dtype) { return dtype == VQE_C64 ? 8 : 16; }
+
+// ---------------------------------------------------------------- tracing
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+};
+struct ProfTotals {
+    uint64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+ProfTotals g_prof_tot[VQE_KERNEL_KINDS];
+
+// Brackets one kernel launch with events when tracing is on.
+struct ProfScope {
+    bool on;
+    ProfRec r{};
+    hipStream_t st;
+    ProfScope(int kind, double bytes, hipStream_t s) : on(false), st(s) {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (!g_prof_on) return;
+        if (hipEventCreate(&r.a) != hipSuccess) return;
+        if (hipEventCreate(&r.b) != hipSuccess) {
+            (void)hipEventDestroy(r.a);
+            return;
+        }
+        r.kind = kind;
+        r.bytes = bytes;
+        on = hipEventRecord(r.a, st) == hipSuccess;
+    }
+    void end() {
+        if (!on) return;
+        on = false;
+        (void)hipEventRecord(r.b, st);
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        g_prof_pending.push_back(r);
+    }
+    ~ProfScope() { end(); }
+};
+
+void prof_drain() {
+    for (auto& r : g_prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            g_prof_tot[r.kind].launches += 1;
+            g_prof_tot[r.kind].ms += ms;
+            g_prof_tot[r.kind].bytes += r.bytes;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+}
 
 int ensure_res(vqe_state* s, size_t count) {
     if (count <= s->res_cap) return VQE_OK;
@@ -280,7 +337,9 @@ int forward(vqe_state* s, const vqe_circuit* c, const double* params, const std:
         for (size_t k = 0; k < bounds.size(); ++k)
             if (bounds[k] == pi + 1) out = ckpt_ptr[k];
         build_args<T>(c, pl, pi, params, false, a);
+        ProfScope ps(VQE_KERNEL_WINDOW_FWD, 2.0 * (double)s->bytes, s->stream);
         VQE_HIP(launch_window_fwd<T>(a, cur, out, s->stream));
+        ps.end();
         cur = out;
     }
     return VQE_OK;
@@ -293,12 +352,31 @@ const TermDesc<float>* terms_of<float>(const vqe_hamiltonian* h) { return h->d_t
 template <>
 const TermDesc<double>* terms_of<double>(const vqe_hamiltonian* h) { return h->d_t64; }
 
+// Algorithmic bytes of one H psi sweep: own tile + one partner tile per
+// distinct out-of-tile partner offset (x >> tile bits), plus the write of lam.
+// The energy-only sweep visits each out-of-tile pair once (half the partners).
+double hpsi_bytes(const vqe_hamiltonian* h, const vqe_state* s, bool write) {
+    const int tb = s->n < kTileBits ? s->n : kTileBits;
+    std::vector<uint64_t> hi;
+    for (const auto& g : h->groups) {
+        const uint64_t xh = g.x >> tb;
+        if (xh && (hi.empty() || hi.back() != xh)) hi.push_back(xh);
+    }
+    std::sort(hi.begin(), hi.end());
+    const size_t D = std::unique(hi.begin(), hi.end()) - hi.begin();
+    const double S = (double)s->bytes;
+    return write ? (1.0 + (double)D) * S + S : (1.0 + 0.5 * (double)D) * S;
+}
+
 // Grouped energy partials reduced into d_res[off], d_res[off+1].
 template <typename T>
 int energy_grouped(vqe_state* s, const vqe_hamiltonian* h, size_t off) {
     uint32_t nb = 0;
-    VQE_HIP(launch_hpsi<T>(s->n, s->data, nullptr, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 1,
-                           s->d_part, &nb, s->stream));
+    {
+        ProfScope ps(VQE_KERNEL_EXPECT_HALF, hpsi_bytes(h, s, false), s->stream);
+        VQE_HIP(launch_hpsi<T>(s->n, s->data, nullptr, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 1,
+                               s->d_part, &nb, s->stream));
+    }
     VQE_HIP(launch_reduce(s->d_part, nb, 2, nullptr, s->d_res + off, 0, s->stream));
     return VQE_OK;
 }
@@ -308,7 +386,9 @@ template <typename T>
 int energy_per_term(vqe_state* s, const vqe_hamiltonian* h, size_t off) {
     for (size_t t = 0; t < h->w.size(); ++t) {
         uint32_t nb = 0;
+        ProfScope ps(VQE_KERNEL_PER_TERM, (double)s->bytes, s->stream);
         VQE_HIP(launch_expect_term<T>(s->n, s->data, h->x[t], h->z[t], s->d_part, &nb, s->stream));
+        ps.end();
         VQE_HIP(launch_reduce(s->d_part, nb, 2, nullptr, s->d_res + off + 2 * t, 0, s->stream));
     }
     return VQE_OK;
@@ -375,8 +455,11 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
     rc = forward<T>(psi, c, params, bounds, ck);
     if (rc) return rc;
     uint32_t nb = 0;
-    VQE_HIP(launch_hpsi<T>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 0,
-                           psi->d_part, &nb, st));
+    {
+        ProfScope ps(VQE_KERNEL_HPSI, hpsi_bytes(h, psi, true), st);
+        VQE_HIP(launch_hpsi<T>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(),
+                               terms_of<T>(h), 0, psi->d_part, &nb, st));
+    }
     VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, d_e, 0, st));
     VQE_HIP(launch_zero(d_g, c->n_params, st));
     PassArgs<T> a;
@@ -386,7 +469,9 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
             if (bounds[k] == pi + 1) pin = ck[k];
         build_args<T>(c, pl, pi, params, true, a);
         uint32_t gb = 0;
+        ProfScope ps(VQE_KERNEL_WINDOW_REV, 4.0 * (double)psi->bytes, st);
         VQE_HIP(launch_window_rev<T>(a, pin, psi->data, lam->data, lam->data, psi->d_part, &gb, st));
+        ps.end();
         if (a.n_gslots)
             VQE_HIP(launch_reduce(psi->d_part, gb, a.n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, 1, st));
     }
@@ -954,6 +1039,32 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const 
     return psi->dtype == VQE_C64 ? adjoint_impl<float>(psi, lam, c, params, h, opts, energy, grad)
                                  : adjoint_impl<double>(psi, lam, c, params, h, opts, energy, grad);
     VQE_GUARD_END
+}
+
+int vqe_profile_enable(int on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+    return VQE_OK;
+}
+
+int vqe_profile_reset(void) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    prof_drain();
+    for (auto& t : g_prof_tot) t = ProfTotals{};
+    return VQE_OK;
+}
+
+int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* bytes) {
+    if (kind < 0 || kind >= VQE_KERNEL_KINDS) {
+        set_error("vqe_profile_read: unknown kernel kind");
+        return VQE_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    prof_drain();
+    if (launches) *launches = g_prof_tot[kind].launches;
+    if (total_ms) *total_ms = g_prof_tot[kind].ms;
+    if (bytes) *bytes = g_prof_tot[kind].bytes;
+    return VQE_OK;
 }
 
 }  // extern "C"
