@@ -80,9 +80,19 @@ _lib = None
 
 
 def lib():
-    """The loaded library; raises if libvqe.so has not been built."""
+    """The loaded library; raises if libvqe.so has not been built.
+
+    torch is imported first: its bundled HIP runtime has the same SONAME as
+    ROCm's, so loading torch first makes libvqe.so bind to that one runtime
+    (device memory and streams from torch are then the library's too).
+    Loading libvqe.so first would put a second HIP runtime in the process.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_11878_amd.build`")
         L = C.CDLL(LIB_PATH)

@@ -50,7 +50,7 @@ struct vqe_state {
     bool owned = false;
     hipStream_t stream = nullptr;
     int device = 0;
-    double* d_part = nullptr;  // per-block partials: kMaxBlocks * kMaxGradSlots
+    double* d_part = nullptr;  // per-block partial sums (allocated on first use)
     double* d_res = nullptr;   // results (energies, gradients), grown on demand
     size_t res_cap = 0;
     double* h_res = nullptr;   // pinned host mirror of d_res
@@ -75,8 +75,12 @@ struct vqe_circuit {
     int n = 0;
     std::vector<Gate> gates;
     size_t n_params = 0;
-    Plan plan[2];  // [0]: complex64 windows, [1]: complex128 windows
+    Plan plan[2];  // [0]: kWindowC64-qubit windows, [1]: kWindowC128-qubit windows
+    // Forward-only sweeps (vqe_apply_circuit, parameter shift).
     const Plan& for_dtype(int dtype) const { return plan[dtype == VQE_C64 ? 0 : 1]; }
+    // Adjoint evaluations: the reverse kernel holds psi and lam, so both
+    // precisions use the smaller window (register budget of the reverse pass).
+    const Plan& for_adjoint() const { return plan[1]; }
 };
 
 struct vqe_hamiltonian {
@@ -197,6 +201,19 @@ int upload_hamiltonian(const vqe_hamiltonian* ch) {
     VQE_HIP(hipMemcpy(h->d_groups, h->groups.data(), h->groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
     VQE_HIP(hipMemcpy(h->d_t32, h->t32.data(), h->t32.size() * sizeof(TermDesc<float>), hipMemcpyHostToDevice));
     VQE_HIP(hipMemcpy(h->d_t64, h->t64.data(), h->t64.size() * sizeof(TermDesc<double>), hipMemcpyHostToDevice));
+    return VQE_OK;
+}
+
+// Per-block partial-sum buffer of a state: room for the largest launch
+// (kMaxPartBlocks blocks x kMaxGradSlots slots).
+int ensure_part(vqe_state* s) {
+    if (s->d_part) return VQE_OK;
+    const size_t count = std::max((size_t)kMaxPartBlocks * kMaxGradSlots, (size_t)kMaxBlocks * 2);
+    if (hipMalloc((void**)&s->d_part, count * sizeof(double)) != hipSuccess) {
+        s->d_part = nullptr;
+        set_error("hipMalloc of the partial-sum buffer failed");
+        return VQE_ERR_OOM;
+    }
     return VQE_OK;
 }
 
@@ -327,18 +344,17 @@ int check_params(const vqe_circuit* c, const double* params, size_t n_params, co
 // Forward passes from |b0> (or in place on the current state when reset is false).
 // ckpt_ptr[k] receives the state at boundary bounds[k] (pass index + 1).
 template <typename T>
-int forward(vqe_state* s, const vqe_circuit* c, const double* params, const std::vector<size_t>& bounds,
-            const std::vector<void*>& ckpt_ptr) {
+int forward(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* params,
+            const std::vector<size_t>& bounds, const std::vector<void*>& ckpt_ptr) {
     void* cur = s->data;
     PassArgs<T> a;
-    const Plan& pl = c->for_dtype(s->dtype);
     for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
         void* out = s->data;
         for (size_t k = 0; k < bounds.size(); ++k)
             if (bounds[k] == pi + 1) out = ckpt_ptr[k];
         build_args<T>(c, pl, pi, params, false, a);
         ProfScope ps(VQE_KERNEL_WINDOW_FWD, 2.0 * (double)s->bytes, s->stream);
-        VQE_HIP(launch_window_fwd<T>(a, cur, out, s->stream));
+        VQE_HIP(launch_window_fwd<T>(a, s->n, cur, out, s->stream));
         ps.end();
         cur = out;
     }
@@ -433,7 +449,7 @@ int expect_impl(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy
 template <typename T>
 int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const double* params,
                  const vqe_hamiltonian* h, const vqe_grad_opts* o, double* energy, double* grad) {
-    const Plan& pl = c->for_dtype(psi->dtype);
+    const Plan& pl = c->for_adjoint();
     if (int rc0 = upload_plan(pl)) return rc0;
     const size_t P = pl.passes.size();
     std::vector<size_t> bounds;
@@ -452,7 +468,7 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
     double* d_g = psi->d_res + 2;
     hipStream_t st = psi->stream;
     VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, st));
-    rc = forward<T>(psi, c, params, bounds, ck);
+    rc = forward<T>(psi, c, pl, params, bounds, ck);
     if (rc) return rc;
     uint32_t nb = 0;
     {
@@ -470,7 +486,7 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
         build_args<T>(c, pl, pi, params, true, a);
         uint32_t gb = 0;
         ProfScope ps(VQE_KERNEL_WINDOW_REV, 4.0 * (double)psi->bytes, st);
-        VQE_HIP(launch_window_rev<T>(a, pin, psi->data, lam->data, lam->data, psi->d_part, &gb, st));
+        VQE_HIP(launch_window_rev<T>(a, psi->n, pin, psi->data, lam->data, lam->data, psi->d_part, &gb, st));
         ps.end();
         if (a.n_gslots)
             VQE_HIP(launch_reduce(psi->d_part, gb, a.n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, 1, st));
@@ -502,7 +518,7 @@ int param_shift_impl(vqe_state* psi, const vqe_circuit* c, const double* params,
             th[k] += (e % 2 == 1) ? M_PI / 2 : -M_PI / 2;
         }
         VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, psi->stream));
-        rc = forward<T>(psi, c, th.data(), nob, nock);
+        rc = forward<T>(psi, c, c->for_dtype(psi->dtype), th.data(), nob, nock);
         if (rc) return rc;
         rc = mode == VQE_EXPECT_PER_TERM ? energy_per_term<T>(psi, h, e * per) : energy_grouped<T>(psi, h, e * per);
         if (rc) return rc;
@@ -645,22 +661,14 @@ int vqe_state_alloc(int n_qubits, int dtype, void* device_buf, size_t buf_bytes,
         }
         s->owned = true;
     }
-    if (hipMalloc((void**)&s->d_part, (size_t)kMaxBlocks * kMaxGradSlots * sizeof(double)) != hipSuccess) {
-        if (s->owned) (void)hipFree(s->data);
-        delete s;
-        set_error("vqe_state_alloc: hipMalloc of the partial-sum buffer failed");
-        return VQE_ERR_OOM;
-    }
     int rc = ensure_res(s, 1024);
     if (rc) {
-        (void)hipFree(s->d_part);
         if (s->owned) (void)hipFree(s->data);
         delete s;
         return rc;
     }
     if (launch_set_basis(dtype, s->data, 1ull << n_qubits, 0, s->stream) != hipSuccess) {
         set_error("vqe_state_alloc: initialisation kernel failed");
-        (void)hipFree(s->d_part);
         (void)hipFree(s->d_res);
         (void)hipHostFree(s->h_res);
         if (s->owned) (void)hipFree(s->data);
@@ -844,7 +852,8 @@ int vqe_apply_circuit(vqe_state* s, const vqe_circuit* c, const double* params, 
     VQE_HIP(hipSetDevice(s->device));
     const std::vector<size_t> nob;
     const std::vector<void*> nock;
-    return s->dtype == VQE_C64 ? forward<float>(s, c, params, nob, nock) : forward<double>(s, c, params, nob, nock);
+    const Plan& pl = c->for_dtype(s->dtype);
+    return s->dtype == VQE_C64 ? forward<float>(s, c, pl, params, nob, nock) : forward<double>(s, c, pl, params, nob, nock);
     VQE_GUARD_END
 }
 
@@ -951,6 +960,7 @@ int vqe_expect_pauli(vqe_state* s, const vqe_hamiltonian* h, int mode, double* e
     }
     VQE_HIP(hipSetDevice(s->device));
     if (int rc = upload_hamiltonian(h)) return rc;
+    if (int rc = ensure_part(s)) return rc;
     return s->dtype == VQE_C64 ? expect_impl<float>(s, h, mode, energy, norm)
                                : expect_impl<double>(s, h, mode, energy, norm);
     VQE_GUARD_END
@@ -968,15 +978,19 @@ int vqe_apply_hamiltonian(vqe_state* psi, vqe_state* lam, const vqe_hamiltonian*
     VQE_HIP(hipSetDevice(psi->device));
     int rc = upload_hamiltonian(h);
     if (rc) return rc;
+    if ((rc = ensure_part(psi))) return rc;
     rc = ensure_res(psi, 2);
     if (rc) return rc;
     uint32_t nb = 0;
-    if (psi->dtype == VQE_C64)
-        VQE_HIP(launch_hpsi<float>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(), h->d_t32, 0,
-                                   psi->d_part, &nb, psi->stream));
-    else
-        VQE_HIP(launch_hpsi<double>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(), h->d_t64,
-                                    0, psi->d_part, &nb, psi->stream));
+    {
+        ProfScope ps(VQE_KERNEL_HPSI, hpsi_bytes(h, psi, true), psi->stream);
+        if (psi->dtype == VQE_C64)
+            VQE_HIP(launch_hpsi<float>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(),
+                                       h->d_t32, 0, psi->d_part, &nb, psi->stream));
+        else
+            VQE_HIP(launch_hpsi<double>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(),
+                                        h->d_t64, 0, psi->d_part, &nb, psi->stream));
+    }
     VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, psi->d_res, 0, psi->stream));
     VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, psi->stream));
     VQE_HIP(hipStreamSynchronize(psi->stream));
@@ -998,6 +1012,7 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const 
     const int method = opts ? opts->method : VQE_GRAD_ADJOINT;
     VQE_HIP(hipSetDevice(psi->device));
     if (int rc = upload_hamiltonian(h)) return rc;
+    if (int rc = ensure_part(psi)) return rc;
     if (method == VQE_GRAD_PARAM_SHIFT) {
         const int mode = opts ? opts->expect_mode : VQE_EXPECT_GROUPED;
         if (mode != VQE_EXPECT_GROUPED && mode != VQE_EXPECT_PER_TERM) {

@@ -233,9 +233,31 @@ __device__ __forceinline__ void run_ops(const PassArgs<T>& a, T (&re)[NV][1 << K
 }
 
 // ---------------------------------------------------------------- window pass
+// Loads / stores of one coset (the 2^K amplitudes of a window) to / from
+// registers.  `base` is the coset's lowest index; offsets are wave-uniform.
+template <typename T, int K, int NV>
+struct Coset {
+    using V = typename VecOf<T>::type;
+    T re[NV][1 << K], im[NV][1 << K];
+};
+
+template <typename T, int K>
+__device__ __forceinline__ uint64_t pattern_offset(const uint64_t (&bitval)[K], int p) {
+    uint64_t off = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (p & (1 << j)) off += bitval[j];
+    return off;
+}
+
+// Direct mode: every window qubit is >= 6, so consecutive lanes hold
+// consecutive cosets at consecutive addresses.  Each thread handles cpt
+// cosets: block-contiguous for one-shot grids (forward passes), interleaved
+// across the grid for persistent grids (reverse passes, whose per-block
+// gradient reduction is amortised over many cosets).
 template <typename T, int K, int NV>
 __global__ void __launch_bounds__(kBlock)
-window_kernel(const PassArgs<T> a, const typename VecOf<T>::type* __restrict__ in0,
+window_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, const typename VecOf<T>::type* __restrict__ in0,
               typename VecOf<T>::type* __restrict__ out0,
               const typename VecOf<T>::type* __restrict__ in1,
               typename VecOf<T>::type* __restrict__ out1, double* __restrict__ gpart) {
@@ -249,8 +271,11 @@ window_kernel(const PassArgs<T> a, const typename VecOf<T>::type* __restrict__ i
     uint64_t bitval[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) bitval[j] = 1ull << a.pos[j];
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + tid; c < a.n_cosets; c += stride) {
+    for (uint32_t it = 0; it < cpt; ++it) {
+        // block-contiguous (one-shot grids) or interleaved (persistent grids)
+        const uint64_t blk = interleave ? (uint64_t)it * gridDim.x + blockIdx.x : (uint64_t)blockIdx.x * cpt + it;
+        const uint64_t c = blk * kBlock + tid;
+        if (c >= a.n_cosets) break;
         uint64_t base = c;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -258,17 +283,12 @@ window_kernel(const PassArgs<T> a, const typename VecOf<T>::type* __restrict__ i
             base = ((base ^ low) << 1) | low;
         }
         T re[NV][N], im[NV][N];
-        // Per-pattern offsets are wave-uniform; only the coset base lives in
-        // VGPRs.  The empty asm makes the store base opaque so that the 2^K
-        // load addresses are not kept live across the gate loop.
+        // Only the coset base lives in VGPRs; the empty asm keeps the store
+        // base opaque so the 2^K load addresses are not held across the ops.
         uint64_t sbase = base;
 #pragma unroll
         for (int p = 0; p < N; ++p) {
-            uint64_t off = 0;
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (p & (1 << j)) off += bitval[j];
-            const uint64_t idx = base + off;
+            const uint64_t idx = base + pattern_offset<T, K>(bitval, p);
             const V v0 = in0[idx];
             re[0][p] = v0.x;
             im[0][p] = v0.y;
@@ -282,11 +302,7 @@ window_kernel(const PassArgs<T> a, const typename VecOf<T>::type* __restrict__ i
         asm volatile("" : "+v"(sbase));
 #pragma unroll
         for (int p = 0; p < N; ++p) {
-            uint64_t off = 0;
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (p & (1 << j)) off += bitval[j];
-            const uint64_t idx = sbase + off;
+            const uint64_t idx = sbase + pattern_offset<T, K>(bitval, p);
             V v0;
             v0.x = re[0][p];
             v0.y = im[0][p];
@@ -311,12 +327,136 @@ window_kernel(const PassArgs<T> a, const typename VecOf<T>::type* __restrict__ i
     }
 }
 
+// LDS-staged mode, for windows that include lane qubits (< 6).  The union U of
+// the window bits and the 6 lowest non-window bits always contains bits 0..5,
+// so the 2^(K+6) amplitudes of one U-chunk are read with fully coalesced
+// wave loads (64 consecutive amplitudes per instruction) into LDS; each lane
+// then gathers its coset (its lane bits fixed, window bits varying), runs the
+// ops in registers, scatters back and the chunk is stored coalesced.  One
+// chunk per wave, one-shot grid.  LDS slots are XOR-swizzled,
+// slot(u) = u ^ ((u >> 5) & 31), to spread strided gathers over the banks.
+struct LdsMap {
+    uint64_t n_chunks;          // 2^(n - K - 6)
+    uint32_t upos[kMaxWindow + 6];  // U positions, ascending (upos[j] = j for j < 6)
+    uint32_t rank_lane[6];      // rank in U of the j-th lowest non-window bit
+    uint32_t rank_win[kMaxWindow];  // rank in U of window bit j
+};
+
+__device__ __forceinline__ uint32_t lds_slot(uint32_t u) { return u ^ ((u >> 5) & 31u); }
+
+template <typename T, int K, int NV>
+__global__ void __launch_bounds__(kBlock)
+window_lds_kernel(const PassArgs<T> a, const LdsMap m, uint32_t cpt, uint32_t interleave,
+                  const typename VecOf<T>::type* __restrict__ in0,
+                  typename VecOf<T>::type* __restrict__ out0,
+                  const typename VecOf<T>::type* __restrict__ in1,
+                  typename VecOf<T>::type* __restrict__ out1, double* __restrict__ gpart) {
+    using V = typename VecOf<T>::type;
+    constexpr int N = 1 << K;
+    constexpr int NU = K + 6;
+    constexpr int CH = 1 << NU;       // amplitudes per chunk
+    constexpr int WAVES = kBlock / 64;
+    __shared__ V chunk[WAVES][CH];
+    __shared__ double gacc[NV == 2 ? kMaxGradSlots * kBlock : 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    if constexpr (NV == 2) {
+        for (uint32_t s = 0; s < a.n_gslots; ++s) gacc[s * kBlock + tid] = 0.0;
+    }
+    // per-lane union index of the lane's coset
+    uint32_t ul = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ul |= (uint32_t)((lane >> j) & 1) << m.rank_lane[j];
+    // Every wave of the block runs the same cpt iterations (uniform barriers).
+    for (uint32_t it = 0; it < cpt; ++it) {
+        const uint64_t blk = interleave ? (uint64_t)it * gridDim.x + blockIdx.x : (uint64_t)blockIdx.x * cpt + it;
+        const uint64_t ch = blk * WAVES + wv;
+        const bool live = ch < m.n_chunks;
+        // chunk base: insert zeros at the U positions
+        uint64_t cbase = live ? ch : 0;
+    #pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const uint64_t low = cbase & ((1ull << m.upos[j]) - 1);
+            cbase = ((cbase ^ low) << 1) | low;
+        }
+        // per-lane union index of the lane's coset
+        uint32_t ul = 0;
+    #pragma unroll
+        for (int j = 0; j < 6; ++j) ul |= (uint32_t)((lane >> j) & 1) << m.rank_lane[j];
+        T re[NV][N], im[NV][N];
+    #pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const V* src = v == 0 ? in0 : in1;
+            if (live) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    uint64_t off = 0;
+    #pragma unroll
+                    for (int j = 6; j < NU; ++j)
+                        if (i & (1 << (j - 6))) off += 1ull << m.upos[j];
+                    chunk[wv][lds_slot((uint32_t)(i * 64 + lane))] = src[cbase + off + lane];
+                }
+            }
+            __syncthreads();
+    #pragma unroll
+            for (int p = 0; p < N; ++p) {
+                uint32_t up = 0;
+    #pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (p & (1 << k)) up |= 1u << m.rank_win[k];
+                const V x = chunk[wv][lds_slot(ul | up)];
+                re[v][p] = x.x;
+                im[v][p] = x.y;
+            }
+            __syncthreads();
+        }
+        if (live) run_ops<K, NV, T>(a, re, im, gacc, tid);
+    #pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            V* dst = v == 0 ? out0 : out1;
+    #pragma unroll
+            for (int p = 0; p < N; ++p) {
+                uint32_t up = 0;
+    #pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (p & (1 << k)) up |= 1u << m.rank_win[k];
+                V x;
+                x.x = re[v][p];
+                x.y = im[v][p];
+                chunk[wv][lds_slot(ul | up)] = x;
+            }
+            __syncthreads();
+            if (live) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    uint64_t off = 0;
+    #pragma unroll
+                    for (int j = 6; j < NU; ++j)
+                        if (i & (1 << (j - 6))) off += 1ull << m.upos[j];
+                    dst[cbase + off + lane] = chunk[wv][lds_slot((uint32_t)(i * 64 + lane))];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if constexpr (NV == 2) {
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (tid < w)
+                for (uint32_t s = 0; s < a.n_gslots; ++s)
+                    gacc[s * kBlock + tid] += gacc[s * kBlock + tid + w];
+            __syncthreads();
+        }
+        if (tid < (int)a.n_gslots) gpart[(uint64_t)blockIdx.x * a.n_gslots + tid] = gacc[tid * kBlock];
+    }
+}
+
 // ---------------------------------------------------------------- H psi
 // Block = one tile of 2^tb amplitudes at a time (grid-stride over tiles);
 // thread t owns local indices r*TPT + t, r < R.
 template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(kBlock)
-hpsi_kernel(int n, int tb, const typename VecOf<T>::type* __restrict__ psi,
+hpsi_kernel(int n, int tb, uint32_t tpb, const typename VecOf<T>::type* __restrict__ psi,
             typename VecOf<T>::type* __restrict__ lam, const GroupDesc* __restrict__ groups,
             uint32_t n_groups, const TermDesc<T>* __restrict__ terms, double* __restrict__ part) {
     using V = typename VecOf<T>::type;
@@ -326,7 +466,9 @@ hpsi_kernel(int n, int tb, const typename VecOf<T>::type* __restrict__ psi,
     const uint64_t n_tiles = 1ull << (n - tb);
     double e_acc = 0.0, n_acc = 0.0;
     if (tid < tpt) {
-        for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        // block b owns tiles [b*tpb, (b+1)*tpb)
+        const uint64_t t_end = ((uint64_t)blockIdx.x + 1) * tpb < n_tiles ? ((uint64_t)blockIdx.x + 1) * tpb : n_tiles;
+        for (uint64_t tile = (uint64_t)blockIdx.x * tpb; tile < t_end; ++tile) {
             const uint64_t tbase = tile << tb;
             uint32_t loc[R];
             V own[R];
@@ -408,7 +550,7 @@ hpsi_kernel(int n, int tb, const typename VecOf<T>::type* __restrict__ psi,
 // c = (-i)^popcount(x&z).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-expect_term_kernel(int n, const typename VecOf<T>::type* __restrict__ psi, uint64_t x, uint64_t z,
+expect_term_kernel(int n, uint32_t cpt, const typename VecOf<T>::type* __restrict__ psi, uint64_t x, uint64_t z,
                    uint32_t hbit, T cre, T cim, double* __restrict__ part) {
     using V = typename VecOf<T>::type;
     __shared__ double red[2][kBlock];
@@ -416,8 +558,10 @@ expect_term_kernel(int n, const typename VecOf<T>::type* __restrict__ psi, uint6
     const uint64_t count = (x == 0) ? (1ull << n) : (1ull << (n - 1));
     const uint64_t hmask = (x == 0) ? 0 : ((1ull << hbit) - 1);
     double v_acc = 0.0, n_acc = 0.0;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + tid; i < count; i += stride) {
+    const uint64_t i0 = (uint64_t)blockIdx.x * kBlock * cpt + tid;
+    for (uint32_t it = 0; it < cpt; ++it) {
+        const uint64_t i = i0 + (uint64_t)it * kBlock;
+        if (i >= count) break;
         uint64_t b = i;
         if (x != 0) {
             const uint64_t low = i & hmask;
@@ -530,42 +674,119 @@ hipError_t launch_copy(int dtype, const void* src, void* dst, uint64_t dim, hipS
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_window_fwd(const PassArgs<T>& a, const void* in, void* out, hipStream_t st) {
-    using V = typename VecOf<T>::type;
-    const uint32_t g = grid_for(a.n_cosets);
-    const V* i0 = (const V*)in;
-    V* o0 = (V*)out;
-    switch (a.K) {
-        case 1: hipLaunchKernelGGL((window_kernel<T, 1, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
-        case 2: hipLaunchKernelGGL((window_kernel<T, 2, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
-        case 3: hipLaunchKernelGGL((window_kernel<T, 3, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
-        case 4: hipLaunchKernelGGL((window_kernel<T, 4, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
-        case 5: hipLaunchKernelGGL((window_kernel<T, 5, 1>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, nullptr, nullptr, nullptr); break;
-        default: return hipErrorInvalidValue;
+// Launch shape of a window pass.  LDS mode for forward passes whose window
+// includes a lane qubit (< 6), when the state has at least K + 6 qubits.
+struct WinShape {
+    bool lds;
+    LdsMap m;
+    uint32_t cpt, grid, interleave;
+};
+
+// Reverse passes (with per-block gradient partials) use a persistent grid of
+// at most kRevBlocks blocks; forward passes a one-shot grid.
+constexpr uint64_t kRevBlocks = 2048;
+
+void grid_for_units(uint64_t units, bool persistent, WinShape& w) {
+    if (persistent) {
+        const uint64_t g = units < kRevBlocks ? units : kRevBlocks;
+        w.grid = (uint32_t)(g ? g : 1);
+        w.cpt = (uint32_t)((units + w.grid - 1) / w.grid);
+        w.interleave = 1;
+    } else {
+        w.grid = (uint32_t)(units ? units : 1);
+        w.cpt = 1;
+        w.interleave = 0;
     }
+}
+
+template <typename T>
+WinShape window_shape(const PassArgs<T>& a, int n, bool with_partials) {
+    WinShape w{};
+    const int K = (int)a.K;
+    bool low = false;
+    for (int j = 0; j < K; ++j) low |= a.pos[j] < 6;
+    // Measured on MI355X: staging pays for forward passes (one vector) but
+    // not for reverse passes, whose two-vector chunks and barriers cost more
+    // than the partly coalesced direct loads they replace.
+    if (low && n >= K + 6 && !with_partials) {
+        w.lds = true;
+        uint64_t wmask = 0;
+        for (int j = 0; j < K; ++j) wmask |= 1ull << a.pos[j];
+        uint64_t umask = wmask;
+        int got = 0;
+        for (int q = 0; q < n && got < 6; ++q)
+            if (!((wmask >> q) & 1)) {
+                umask |= 1ull << q;
+                ++got;
+            }
+        int r = 0, lj = 0;
+        for (int q = 0; q < n; ++q) {
+            if (!((umask >> q) & 1)) continue;
+            w.m.upos[r] = (uint32_t)q;
+            if ((wmask >> q) & 1) {
+                for (int j = 0; j < K; ++j)
+                    if ((int)a.pos[j] == q) w.m.rank_win[j] = (uint32_t)r;
+            } else {
+                w.m.rank_lane[lj++] = (uint32_t)r;
+            }
+            ++r;
+        }
+        w.m.n_chunks = 1ull << (n - K - 6);
+        const uint64_t per_block = kBlock / 64;
+        grid_for_units((w.m.n_chunks + per_block - 1) / per_block, with_partials, w);
+        return w;
+    }
+    w.lds = false;
+    grid_for_units((a.n_cosets + kBlock - 1) / kBlock, with_partials, w);
+    return w;
+}
+
+template <typename T>
+uint32_t window_blocks(const PassArgs<T>& a, int n, bool with_partials) {
+    return window_shape<T>(a, n, with_partials).grid;
+}
+
+template <typename T, int NV>
+hipError_t launch_window(const PassArgs<T>& a, int n, const void* in0, void* out0, const void* in1, void* out1,
+                         double* gpart, hipStream_t st) {
+    using V = typename VecOf<T>::type;
+    const WinShape w = window_shape<T>(a, n, NV == 2);
+    const V* i0 = (const V*)in0;
+    V* o0 = (V*)out0;
+    const V* i1 = (const V*)in1;
+    V* o1 = (V*)out1;
+#define VQE_WIN(KK)                                                                                      \
+    case KK:                                                                                             \
+        if (w.lds)                                                                                       \
+            hipLaunchKernelGGL((window_lds_kernel<T, KK, NV>), dim3(w.grid), dim3(kBlock), 0, st, a, w.m, \
+                               w.cpt, w.interleave, i0, o0, i1, o1, gpart);                              \
+        else                                                                                             \
+            hipLaunchKernelGGL((window_kernel<T, KK, NV>), dim3(w.grid), dim3(kBlock), 0, st, a, w.cpt, \
+                               w.interleave, i0, o0, i1, o1, gpart);                                     \
+        break;
+    switch (a.K) {
+        VQE_WIN(1)
+        VQE_WIN(2)
+        VQE_WIN(3)
+        VQE_WIN(4)
+        VQE_WIN(5)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef VQE_WIN
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_window_rev(const PassArgs<T>& a, const void* psi_in, void* psi_out, const void* lam_in,
+hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, hipStream_t st) {
+    return launch_window<T, 1>(a, n, in, out, nullptr, nullptr, nullptr, st);
+}
+
+template <typename T>
+hipError_t launch_window_rev(const PassArgs<T>& a, int n, const void* psi_in, void* psi_out, const void* lam_in,
                              void* lam_out, double* gpart, uint32_t* nblocks, hipStream_t st) {
-    using V = typename VecOf<T>::type;
-    const uint32_t g = grid_for(a.n_cosets);
-    *nblocks = g;
-    const V* i0 = (const V*)psi_in;
-    V* o0 = (V*)psi_out;
-    const V* i1 = (const V*)lam_in;
-    V* o1 = (V*)lam_out;
-    switch (a.K) {
-        case 1: hipLaunchKernelGGL((window_kernel<T, 1, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
-        case 2: hipLaunchKernelGGL((window_kernel<T, 2, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
-        case 3: hipLaunchKernelGGL((window_kernel<T, 3, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
-        case 4: hipLaunchKernelGGL((window_kernel<T, 4, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
-        case 5: hipLaunchKernelGGL((window_kernel<T, 5, 2>), dim3(g), dim3(kBlock), 0, st, a, i0, o0, i1, o1, gpart); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    *nblocks = window_blocks<T>(a, n, true);
+    return launch_window<T, 2>(a, n, psi_in, psi_out, lam_in, lam_out, gpart, st);
 }
 
 template <typename T>
@@ -574,14 +795,16 @@ hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* group
     using V = typename VecOf<T>::type;
     const int tb = n < kTileBits ? n : kTileBits;
     const uint64_t n_tiles = 1ull << (n - tb);
-    const uint32_t g = n_tiles > (uint64_t)kMaxBlocks ? (uint32_t)kMaxBlocks : (uint32_t)n_tiles;
+    uint32_t tpb = 1;
+    while ((n_tiles + tpb - 1) / tpb > (uint64_t)kMaxPartBlocks) tpb *= 2;
+    const uint32_t g = (uint32_t)((n_tiles + tpb - 1) / tpb);
     *nblocks = g;
     const int tile = 1 << tb;
     const int R = tile >= 4 * kBlock ? 4 : (tile >= 2 * kBlock ? 2 : 1);
     const V* p = (const V*)psi;
     V* l = (V*)lam;
 #define VQE_HPSI(RR, MM) \
-    hipLaunchKernelGGL((hpsi_kernel<T, RR, MM>), dim3(g), dim3(kBlock), 0, st, n, tb, p, l, groups, n_groups, terms, part)
+    hipLaunchKernelGGL((hpsi_kernel<T, RR, MM>), dim3(g), dim3(kBlock), 0, st, n, tb, tpb, p, l, groups, n_groups, terms, part)
     if (mode == 0) {
         if (R == 4) VQE_HPSI(4, 0); else if (R == 2) VQE_HPSI(2, 0); else VQE_HPSI(1, 0);
     } else {
@@ -596,7 +819,9 @@ hipError_t launch_expect_term(int n, const void* psi, uint64_t x, uint64_t z, do
                               uint32_t* nblocks, hipStream_t st) {
     using V = typename VecOf<T>::type;
     const uint64_t count = (x == 0) ? (1ull << n) : (1ull << (n - 1));
-    const uint32_t g = grid_for(count);
+    uint32_t cpt = 1;
+    while ((count + (uint64_t)kBlock * cpt - 1) / ((uint64_t)kBlock * cpt) > (uint64_t)kMaxPartBlocks) cpt *= 2;
+    const uint32_t g = (uint32_t)((count + (uint64_t)kBlock * cpt - 1) / ((uint64_t)kBlock * cpt));
     *nblocks = g;
     uint32_t hbit = 0;
     if (x != 0) hbit = 63 - __builtin_clzll(x);
@@ -604,7 +829,7 @@ hipError_t launch_expect_term(int n, const void* psi, uint64_t x, uint64_t z, do
     // (-i)^y
     const T cre = (y == 0) ? T(1) : (y == 2 ? T(-1) : T(0));
     const T cim = (y == 1) ? T(-1) : (y == 3 ? T(1) : T(0));
-    hipLaunchKernelGGL(expect_term_kernel<T>, dim3(g), dim3(kBlock), 0, st, n, (const V*)psi, x, z, hbit, cre, cim, part);
+    hipLaunchKernelGGL(expect_term_kernel<T>, dim3(g), dim3(kBlock), 0, st, n, cpt, (const V*)psi, x, z, hbit, cre, cim, part);
     return hipGetLastError();
 }
 
@@ -615,10 +840,10 @@ hipError_t launch_reduce(const double* part, uint32_t nblocks, uint32_t nslots, 
     return hipGetLastError();
 }
 
-template hipError_t launch_window_fwd<float>(const PassArgs<float>&, const void*, void*, hipStream_t);
-template hipError_t launch_window_fwd<double>(const PassArgs<double>&, const void*, void*, hipStream_t);
-template hipError_t launch_window_rev<float>(const PassArgs<float>&, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
-template hipError_t launch_window_rev<double>(const PassArgs<double>&, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_window_fwd<float>(const PassArgs<float>&, int, const void*, void*, hipStream_t);
+template hipError_t launch_window_fwd<double>(const PassArgs<double>&, int, const void*, void*, hipStream_t);
+template hipError_t launch_window_rev<float>(const PassArgs<float>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_window_rev<double>(const PassArgs<double>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_expect_term<float>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);

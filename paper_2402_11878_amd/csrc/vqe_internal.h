@@ -21,6 +21,7 @@ constexpr int kMaxMats = 32;      // 2x2 matrices per pass
 constexpr int kMaxGradSlots = 16; // parameterised gates per pass
 constexpr int kBlock = 256;       // threads per block of every streaming kernel
 constexpr int kMaxBlocks = 2048;  // grid-stride kernels use at most this many blocks
+constexpr int kMaxPartBlocks = 1 << 17;  // blocks writing per-block partial sums
 constexpr int kTileBits = 10;     // amplitudes per Hamiltonian tile = 2^kTileBits
 
 // ---------------------------------------------------------------- kernel ops
@@ -80,14 +81,14 @@ hipError_t launch_set_basis(int dtype, void* psi, uint64_t dim, uint64_t b, hipS
 hipError_t launch_zero(double* p, uint64_t n, hipStream_t st);
 hipError_t launch_copy(int dtype, const void* src, void* dst, uint64_t dim, hipStream_t st);
 
-// in == out allowed (in place).  NV = 1 vector.
+// in == out allowed (in place).  n = qubits of the state.
 template <typename T>
-hipError_t launch_window_fwd(const PassArgs<T>& a, const void* in, void* out, hipStream_t st);
+hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, hipStream_t st);
 
 // Reverse pass on (psi, lam); writes per-block gradient partials
 // [blocks][n_gslots] into gpart.  Returns the block count used via *nblocks.
 template <typename T>
-hipError_t launch_window_rev(const PassArgs<T>& a, const void* psi_in, void* psi_out,
+hipError_t launch_window_rev(const PassArgs<T>& a, int n, const void* psi_in, void* psi_out,
                              const void* lam_in, void* lam_out, double* gpart,
                              uint32_t* nblocks, hipStream_t st);
 
