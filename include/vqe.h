@@ -201,6 +201,33 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,
                     const double* params, size_t n_params, const vqe_hamiltonian* h,
                     const vqe_grad_opts* opts, double* energy, double* grad);
 
+/* ------------------------------------------------------------------ batched small states
+ * Many independent energy + gradient evaluations (the independent circuit
+ * runs of Sec. II-C, here from many optimiser instances) in one launch: one
+ * workgroup per item holds psi and lam = H psi of the item in LDS and runs
+ * the forward gates, the energy (eq. 7) and the adjoint reverse sweep.
+ * Items may mix circuits, Hamiltonians and qubit counts; every item needs
+ * n <= VQE_BATCH_MAX_QUBITS_C64 (complex64) or VQE_BATCH_MAX_QUBITS_C128
+ * (complex128).  Each item's result depends only on that item (fixed
+ * per-item work and reduction order), so it is bitwise the same alone or in
+ * any batch.  A batch handle owns device and pinned staging buffers, grown on
+ * demand, and runs on its stream; vqe_batch_energy_grad returns after the
+ * results are on the host. */
+#define VQE_BATCH_MAX_QUBITS_C64  13
+#define VQE_BATCH_MAX_QUBITS_C128 12
+typedef struct vqe_batch vqe_batch;
+typedef struct vqe_batch_item {
+    const vqe_circuit* circuit;
+    const vqe_hamiltonian* hamiltonian;  /* same n as the circuit */
+    const double* params;                /* host, n_params of the circuit */
+    size_t n_params;
+    double* energy;                      /* host out */
+    double* grad;                        /* host out, n_params */
+} vqe_batch_item;
+int vqe_batch_create(int dtype, void* hip_stream, vqe_batch** out);
+int vqe_batch_free(vqe_batch* b);
+int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* items);
+
 /* ------------------------------------------------------------------ tracing
  * Per-kernel timing with HIP events.  While enabled (process-wide), every
  * launch of a state-sweeping kernel is bracketed by two events recorded on

@@ -38,6 +38,13 @@ class vqe_grad_opts(C.Structure):
                 ("reserved", C.c_int32), ("ckpt", C.POINTER(C.c_void_p))]
 
 
+class vqe_batch_item(C.Structure):
+    _fields_ = [("circuit", C.c_void_p), ("hamiltonian", C.c_void_p), ("params", C.POINTER(C.c_double)),
+                ("n_params", C.c_size_t), ("energy", C.POINTER(C.c_double)), ("grad", C.POINTER(C.c_double))]
+
+
+BATCH_MAX_QUBITS = {1: 13, 2: 12}
+
 GATE_DTYPE = np.dtype([("kind", "u1"), ("q0", "u1"), ("q1", "u1"), ("reserved", "u1"),
                        ("param_index", "<i4"), ("angle", "<f8")], align=True)
 assert GATE_DTYPE.itemsize == C.sizeof(vqe_gate) == 16
@@ -68,6 +75,9 @@ _SIGS = {
     "vqe_apply_hamiltonian": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "vqe_energy_grad": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double), _SZ, _P, C.POINTER(vqe_grad_opts),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vqe_batch_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+    "vqe_batch_free": (C.c_int, [_P]),
+    "vqe_batch_energy_grad": (C.c_int, [_P, _SZ, C.POINTER(vqe_batch_item)]),
     "vqe_profile_enable": (C.c_int, [C.c_int]),
     "vqe_profile_reset": (C.c_int, []),
     "vqe_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -251,3 +261,31 @@ def vqe_profile_read(kind):
     n, ms, b = C.c_uint64(), C.c_double(), C.c_double()
     check("vqe_profile_read", lib().vqe_profile_read(kind, C.byref(n), C.byref(ms), C.byref(b)))
     return n.value, ms.value, b.value
+
+
+def vqe_batch_create(dtype, hip_stream=None):
+    out = _P()
+    check("vqe_batch_create", lib().vqe_batch_create(dtype, hip_stream, C.byref(out)))
+    return out.value
+
+
+def vqe_batch_free(b):
+    check("vqe_batch_free", lib().vqe_batch_free(b))
+
+
+def vqe_batch_energy_grad(b, items):
+    """items: list of (circuit_handle, hamiltonian_handle, params).  Returns [(E, grad)]."""
+    n = len(items)
+    arr = (vqe_batch_item * max(n, 1))()
+    keep = []
+    outs = []
+    for i, (c, h, p) in enumerate(items):
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        e = np.zeros(1)
+        g = np.zeros(len(p))
+        keep += [p, e, g]
+        arr[i] = vqe_batch_item(c, h, p.ctypes.data_as(C.POINTER(C.c_double)), len(p),
+                                e.ctypes.data_as(C.POINTER(C.c_double)), g.ctypes.data_as(C.POINTER(C.c_double)))
+        outs.append((e, g))
+    check("vqe_batch_energy_grad", lib().vqe_batch_energy_grad(b, n, arr))
+    return [(float(e[0]), g) for e, g in outs]

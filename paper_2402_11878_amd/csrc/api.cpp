@@ -75,6 +75,8 @@ struct vqe_circuit {
     int n = 0;
     std::vector<Gate> gates;
     size_t n_params = 0;
+    std::vector<BatchGate> bgates;  // gate table of the batched small-state kernel
+    uint32_t n_mats = 0;            // matrices per evaluation (gates with a 2x2 matrix)
     Plan plan[2];  // [0]: kWindowC64-qubit windows, [1]: kWindowC128-qubit windows
     // Forward-only sweeps (vqe_apply_circuit, parameter shift).
     const Plan& for_dtype(int dtype) const { return plan[dtype == VQE_C64 ? 0 : 1]; }
@@ -97,9 +99,21 @@ struct vqe_hamiltonian {
     TermDesc<double>* d_t64 = nullptr;
 };
 
+struct vqe_batch {
+    int dtype = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void* d_buf = nullptr;   // items | gates | mats | out, one allocation
+    size_t d_cap = 0;
+    void* h_buf = nullptr;   // pinned staging of the same layout
+    size_t h_cap = 0;
+};
+
 namespace {
 
 size_t amp_bytes(int dtype) { return dtype == VQE_C64 ? 8 : 16; }
+
+std::mutex g_upload_mu;  // lazy device uploads of shared handles
 
 // ---------------------------------------------------------------- tracing
 struct ProfRec {
@@ -187,6 +201,7 @@ int upload_plan(const Plan& cpl);
 // Uploads the grouped term tables to the current device (once).
 int upload_hamiltonian(const vqe_hamiltonian* ch) {
     vqe_hamiltonian* h = const_cast<vqe_hamiltonian*>(ch);
+    std::lock_guard<std::mutex> g(g_upload_mu);
     if (h->d_groups) return VQE_OK;
     if (hipMalloc((void**)&h->d_groups, h->groups.size() * sizeof(GroupDesc)) != hipSuccess ||
         hipMalloc((void**)&h->d_t32, h->t32.size() * sizeof(TermDesc<float>)) != hipSuccess ||
@@ -593,12 +608,103 @@ int build_plan(vqe_circuit* c, int kwin, Plan& pl) {
 // Uploads the gradient slot maps of a plan to the current device (once).
 int upload_plan(const Plan& cpl) {
     Plan& pl = const_cast<Plan&>(cpl);
+    std::lock_guard<std::mutex> g(g_upload_mu);
     if (pl.d_slotmap || pl.slotmap.empty()) return VQE_OK;
     if (hipMalloc((void**)&pl.d_slotmap, pl.slotmap.size() * sizeof(int32_t)) != hipSuccess) {
         set_error("hipMalloc of the gradient slot map failed");
         return VQE_ERR_OOM;
     }
     VQE_HIP(hipMemcpy(pl.d_slotmap, pl.slotmap.data(), pl.slotmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return VQE_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+template <typename T>
+int batch_impl(vqe_batch* b, size_t n_items, const vqe_batch_item* items) {
+    const int max_q = b->dtype == VQE_C64 ? kBatchMaxQubitsC64 : kBatchMaxQubitsC128;
+    size_t n_gates = 0, n_mats = 1, n_out = 0;
+    int max_n = 1;
+    for (size_t i = 0; i < n_items; ++i) {
+        const vqe_batch_item& it = items[i];
+        if (!it.circuit || !it.hamiltonian || !it.energy || (it.n_params && (!it.params || !it.grad))) {
+            set_error("vqe_batch_energy_grad: item " + std::to_string(i) + " has a null field");
+            return VQE_ERR_ARG;
+        }
+        const vqe_circuit* c = it.circuit;
+        if (c->n > max_q || it.hamiltonian->n != c->n) {
+            set_error("vqe_batch_energy_grad: item " + std::to_string(i) + " has " + std::to_string(c->n) +
+                      " qubits (limit " + std::to_string(max_q) + ") or a Hamiltonian of another size");
+            return VQE_ERR_ARG;
+        }
+        if (int rc = check_params(c, it.params, it.n_params, "vqe_batch_energy_grad")) return rc;
+        if (int rc = upload_hamiltonian(it.hamiltonian)) return rc;
+        n_gates += c->bgates.size();
+        n_mats += c->n_mats;
+        n_out += 1 + c->n_params;
+        max_n = std::max(max_n, c->n);
+    }
+    const size_t o_items = 0;
+    const size_t o_gates = align_up(o_items + n_items * sizeof(BatchDesc<T>), 256);
+    const size_t o_mats = align_up(o_gates + std::max<size_t>(n_gates, 1) * sizeof(BatchGate), 256);
+    const size_t o_out = align_up(o_mats + n_mats * sizeof(Mat2<T>), 256);
+    const size_t total = align_up(o_out + n_out * sizeof(double), 256);
+    if (total > b->d_cap) {
+        VQE_HIP(hipStreamSynchronize(b->stream));
+        if (b->d_buf) VQE_HIP(hipFree(b->d_buf));
+        if (b->h_buf) VQE_HIP(hipHostFree(b->h_buf));
+        b->d_buf = b->h_buf = nullptr;
+        b->d_cap = b->h_cap = 0;
+        const size_t cap = std::max(total * 2, (size_t)1 << 20);
+        if (hipMalloc(&b->d_buf, cap) != hipSuccess || hipHostMalloc(&b->h_buf, cap, hipHostMallocDefault) != hipSuccess) {
+            set_error("vqe_batch_energy_grad: staging allocation failed");
+            return VQE_ERR_OOM;
+        }
+        b->d_cap = b->h_cap = cap;
+    }
+    char* h = (char*)b->h_buf;
+    char* d = (char*)b->d_buf;
+    auto* hi = (BatchDesc<T>*)(h + o_items);
+    auto* hg = (BatchGate*)(h + o_gates);
+    auto* hm = (Mat2<T>*)(h + o_mats);
+    size_t g_off = 0, m_off = 0, out_off = 0;
+    for (size_t i = 0; i < n_items; ++i) {
+        const vqe_circuit* c = items[i].circuit;
+        const vqe_hamiltonian* hh = items[i].hamiltonian;
+        BatchDesc<T> bd{};
+        bd.n = c->n;
+        bd.n_gates = (uint32_t)c->bgates.size();
+        bd.gate_off = (uint32_t)g_off;
+        bd.mat_off = (uint32_t)m_off;
+        bd.n_groups = (uint32_t)hh->groups.size();
+        bd.n_params = (uint32_t)c->n_params;
+        bd.out_off = out_off;
+        bd.groups = hh->d_groups;
+        bd.terms = terms_of<T>(hh);
+        hi[i] = bd;
+        for (size_t k = 0; k < c->bgates.size(); ++k) {
+            hg[g_off + k] = c->bgates[k];
+            const Gate& gt = c->gates[k];
+            if (c->bgates[k].type == OP_U2) fill_matrix(hm[m_off + c->bgates[k].mat], gt, angle_of(gt, items[i].params), false);
+        }
+        g_off += c->bgates.size();
+        m_off += c->n_mats;
+        out_off += 1 + c->n_params;
+    }
+    std::memset(&hm[m_off], 0, sizeof(Mat2<T>));
+    VQE_HIP(hipMemcpyAsync(d, h, o_out, hipMemcpyHostToDevice, b->stream));
+    VQE_HIP(launch_batch<T>((const BatchDesc<T>*)(d + o_items), (uint32_t)n_items, (const BatchGate*)(d + o_gates),
+                            (const Mat2<T>*)(d + o_mats), (double*)(d + o_out), max_n, b->stream));
+    VQE_HIP(hipMemcpyAsync(h + o_out, d + o_out, n_out * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    VQE_HIP(hipStreamSynchronize(b->stream));
+    const double* r = (const double*)(h + o_out);
+    out_off = 0;
+    for (size_t i = 0; i < n_items; ++i) {
+        const vqe_circuit* c = items[i].circuit;
+        *items[i].energy = r[out_off];
+        for (size_t k = 0; k < c->n_params; ++k) items[i].grad[k] = r[out_off + 1 + k];
+        out_off += 1 + c->n_params;
+    }
     return VQE_OK;
 }
 }  // namespace
@@ -787,6 +893,22 @@ int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_
     c->n = n_qubits;
     c->gates = std::move(gs);
     c->n_params = n_params;
+    for (size_t i = 0; i < c->gates.size(); ++i) {
+        const Gate& g = c->gates[i];
+        BatchGate bg{};
+        bg.q0 = (uint8_t)g.q0;
+        bg.q1 = (uint8_t)g.q1;
+        bg.pidx = g.pidx;
+        bg.gen = grad_op(g.kind);
+        if (g.kind == VQE_GATE_CNOT) bg.type = OP_CNOT;
+        else if (g.kind == VQE_GATE_CZ) bg.type = OP_CZ;
+        else if (g.kind == VQE_GATE_X) bg.type = OP_XFLIP;
+        else {
+            bg.type = OP_U2;
+            bg.mat = c->n_mats++;
+        }
+        c->bgates.push_back(bg);
+    }
     const int windows[2] = {kWindowC64, kWindowC128};
     for (int v = 0; v < 2; ++v) {
         int rc = build_plan(c, windows[v], c->plan[v]);
@@ -1053,6 +1175,65 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const 
     }
     return psi->dtype == VQE_C64 ? adjoint_impl<float>(psi, lam, c, params, h, opts, energy, grad)
                                  : adjoint_impl<double>(psi, lam, c, params, h, opts, energy, grad);
+    VQE_GUARD_END
+}
+
+int vqe_batch_create(int dtype, void* hip_stream, vqe_batch** out) {
+    VQE_GUARD_BEGIN
+    if (!out || (dtype != VQE_C64 && dtype != VQE_C128)) {
+        set_error("vqe_batch_create: null out or bad dtype");
+        return VQE_ERR_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        set_error("vqe_batch_create: no HIP device");
+        return VQE_ERR_DEVICE;
+    }
+    {
+        static std::once_flag once;
+        static hipError_t lds_rc = hipSuccess;
+        std::call_once(once, [] { lds_rc = batch_set_lds_limit(); });
+        if (lds_rc != hipSuccess) {
+            set_error(std::string("vqe_batch_create: cannot raise the LDS limit: ") + hipGetErrorString(lds_rc));
+            return VQE_ERR_DEVICE;
+        }
+    }
+    auto* b = new vqe_batch();
+    b->dtype = dtype;
+    b->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        set_error("vqe_batch_create: hipGetDevice failed");
+        return VQE_ERR_DEVICE;
+    }
+    *out = b;
+    return VQE_OK;
+    VQE_GUARD_END
+}
+
+int vqe_batch_free(vqe_batch* b) {
+    if (!b) return VQE_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    if (b->d_buf) (void)hipFree(b->d_buf);
+    if (b->h_buf) (void)hipHostFree(b->h_buf);
+    delete b;
+    return VQE_OK;
+}
+
+int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* items) {
+    VQE_GUARD_BEGIN
+    if (!b || (n_items && !items)) {
+        set_error("vqe_batch_energy_grad: null batch or items");
+        return VQE_ERR_ARG;
+    }
+    if (n_items == 0) return VQE_OK;
+    if (n_items > (1u << 20)) {
+        set_error("vqe_batch_energy_grad: too many items in one batch (limit 2^20)");
+        return VQE_ERR_ARG;
+    }
+    VQE_HIP(hipSetDevice(b->device));
+    return b->dtype == VQE_C64 ? batch_impl<float>(b, n_items, items) : batch_impl<double>(b, n_items, items);
     VQE_GUARD_END
 }
 

@@ -1,0 +1,207 @@
+// Batched small-state kernel: one workgroup evaluates one request (energy and
+// adjoint gradient of psi(theta) = U(theta)|0...0>, eqs. 6-7) with the whole
+// state held in LDS.  psi and lam = H psi both live in LDS (2 x 2^n
+// amplitudes, n <= 13 for complex64, n <= 12 for complex128), so a request
+// touches HBM only for its gate table, matrices and results.  Many requests
+// of different circuits and Hamiltonians share one launch (grid = requests).
+//
+// Per request, in order: psi = |0>; every gate applied in turn (one LDS sweep
+// and barrier per gate); lam[b] = sum_x psi[b^x] sum_z c_z (-1)^popcount(z&b)
+// with the energy and norm reduced over the block in a fixed tree; then the
+// gates in reverse: for a parameterised gate, g += Im<lam|G|psi> reduced in
+// the same fixed tree, followed by un-applying the gate (U^dagger = conj
+// transpose, exact) from psi and lam.  The thread -> amplitude map and the
+// reduction order depend only on n, so a request's bits do not depend on the
+// other requests of the batch.
+#include "vqe_internal.h"
+
+namespace vqe {
+namespace {
+
+template <typename T> struct VecB;
+template <> struct VecB<float> { using type = float2; };
+template <> struct VecB<double> { using type = double2; };
+
+constexpr int kBT = 1024;  // threads per request
+
+__device__ __forceinline__ uint32_t ins0(uint32_t k, uint32_t q) {
+    const uint32_t low = k & ((1u << q) - 1);
+    return ((k ^ low) << 1) | low;
+}
+
+// Fixed-tree block sum (all threads participate; returns the total to all).
+__device__ double block_sum(double v, double* red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int w = kBT / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ void apply_gate(typename VecB<T>::type* s, int n, const BatchGate& g, const T* m, bool dag) {
+    using V = typename VecB<T>::type;
+    const int t = threadIdx.x;
+    if (g.type == OP_CNOT || g.type == OP_CZ) {
+        const uint32_t a = g.q0, b = g.q1;
+        const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+        const uint32_t cnt = 1u << (n - 2);
+        for (uint32_t k = t; k < cnt; k += kBT) {
+            const uint32_t i = ins0(ins0(k, lo), hi) | (1u << a);  // control (or first) bit set
+            if (g.type == OP_CNOT) {
+                const uint32_t j = i | (1u << b);
+                const V x = s[i];
+                s[i] = s[j];
+                s[j] = x;
+            } else {
+                const uint32_t j = i | (1u << b);
+                V x = s[j];
+                x.x = -x.x;
+                x.y = -x.y;
+                s[j] = x;
+            }
+        }
+    } else if (g.type == OP_XFLIP) {
+        const uint32_t cnt = 1u << (n - 1);
+        for (uint32_t k = t; k < cnt; k += kBT) {
+            const uint32_t i = ins0(k, g.q0), j = i | (1u << g.q0);
+            const V x = s[i];
+            s[i] = s[j];
+            s[j] = x;
+        }
+    } else {
+        // general 2x2 (U or, for dag, conj(U)^T)
+        T u0r = m[0], u0i = m[1], u1r = m[2], u1i = m[3], u2r = m[4], u2i = m[5], u3r = m[6], u3i = m[7];
+        if (dag) {
+            const T a0r = u0r, a0i = -u0i, a1r = u2r, a1i = -u2i, a2r = u1r, a2i = -u1i, a3r = u3r, a3i = -u3i;
+            u0r = a0r; u0i = a0i; u1r = a1r; u1i = a1i; u2r = a2r; u2i = a2i; u3r = a3r; u3i = a3i;
+        }
+        const uint32_t cnt = 1u << (n - 1);
+        for (uint32_t k = t; k < cnt; k += kBT) {
+            const uint32_t i = ins0(k, g.q0), j = i | (1u << g.q0);
+            const V x = s[i], y = s[j];
+            V o0, o1;
+            o0.x = u0r * x.x - u0i * x.y + u1r * y.x - u1i * y.y;
+            o0.y = u0r * x.y + u0i * x.x + u1r * y.y + u1i * y.x;
+            o1.x = u2r * x.x - u2i * x.y + u3r * y.x - u3i * y.y;
+            o1.y = u2r * x.y + u2i * x.x + u3r * y.y + u3i * y.x;
+            s[i] = o0;
+            s[j] = o1;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBT)
+batch_kernel(const BatchDesc<T>* __restrict__ items, const BatchGate* __restrict__ gates,
+             const Mat2<T>* __restrict__ mats, double* __restrict__ out) {
+    using V = typename VecB<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kBT];
+    const BatchDesc<T> d = items[blockIdx.x];
+    const int n = d.n;
+    const uint32_t dim = 1u << n;
+    V* psi = reinterpret_cast<V*>(smem);
+    V* lam = psi + dim;
+    const int t = threadIdx.x;
+    double* o = out + d.out_off;
+    for (uint32_t b = t; b < dim; b += kBT) {
+        V v;
+        v.x = (b == 0) ? T(1) : T(0);
+        v.y = 0;
+        psi[b] = v;
+    }
+    __syncthreads();
+    // forward
+    for (uint32_t gi = 0; gi < d.n_gates; ++gi) {
+        const BatchGate g = gates[d.gate_off + gi];
+        apply_gate<T>(psi, n, g, mats[d.mat_off + g.mat].v, false);
+    }
+    // lam = H psi, energy and norm
+    double e_acc = 0.0, n_acc = 0.0;
+    for (uint32_t b = t; b < dim; b += kBT) {
+        T ar = 0, ai = 0;
+        for (uint32_t gq = 0; gq < d.n_groups; ++gq) {
+            const GroupDesc G = d.groups[gq];
+            T dr = 0, di = 0;
+            for (uint32_t k = G.begin; k < G.end; ++k) {
+                const TermDesc<T> tm = d.terms[k];
+                const bool neg = __popcll(tm.z & (uint64_t)b) & 1;
+                dr += neg ? -tm.cre : tm.cre;
+                di += neg ? -tm.cim : tm.cim;
+            }
+            const V p = psi[b ^ (uint32_t)G.x];
+            ar += dr * p.x - di * p.y;
+            ai += dr * p.y + di * p.x;
+        }
+        V l;
+        l.x = ar;
+        l.y = ai;
+        lam[b] = l;
+        const V p = psi[b];
+        e_acc += (double)(p.x * ar + p.y * ai);
+        n_acc += (double)(p.x * p.x + p.y * p.y);
+    }
+    __syncthreads();
+    const double E = block_sum(e_acc, red);
+    const double nrm = block_sum(n_acc, red);
+    if (t == 0) o[0] = E / nrm;
+    for (uint32_t k = t; k < d.n_params; k += kBT) o[1 + k] = 0.0;
+    __syncthreads();
+    // reverse sweep
+    for (uint32_t gi = d.n_gates; gi-- > 0;) {
+        const BatchGate g = gates[d.gate_off + gi];
+        if (g.pidx >= 0) {
+            const uint32_t q = g.q0;
+            const uint32_t cnt = 1u << (n - 1);
+            T acc = 0;
+            for (uint32_t k = t; k < cnt; k += kBT) {
+                const uint32_t i = ins0(k, q), j = i | (1u << q);
+                const V p0 = psi[i], p1 = psi[j], l0 = lam[i], l1 = lam[j];
+                if (g.gen == OP_GZ)
+                    acc += (l0.x * p0.y - l0.y * p0.x) - (l1.x * p1.y - l1.y * p1.x);
+                else if (g.gen == OP_GY)
+                    acc += (l1.x * p0.x + l1.y * p0.y) - (l0.x * p1.x + l0.y * p1.y);
+                else
+                    acc += (l0.x * p1.y - l0.y * p1.x) + (l1.x * p0.y - l1.y * p0.x);
+            }
+            const double gsum = block_sum((double)acc, red);
+            if (t == 0) o[1 + g.pidx] += gsum / nrm;
+        }
+        const T* m = mats[d.mat_off + g.mat].v;
+        apply_gate<T>(psi, n, g, m, true);
+        apply_gate<T>(lam, n, g, m, true);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_batch(const BatchDesc<T>* items, uint32_t n_items, const BatchGate* gates, const Mat2<T>* mats,
+                        double* out, int max_n, hipStream_t st) {
+    using V = typename VecB<T>::type;
+    const size_t lds = 2 * ((size_t)1 << max_n) * sizeof(V);
+    hipLaunchKernelGGL(batch_kernel<T>, dim3(n_items), dim3(kBT), lds, st, items, gates, mats, out);
+    return hipGetLastError();
+}
+
+hipError_t batch_set_lds_limit() {
+    hipError_t e = hipFuncSetAttribute((const void*)batch_kernel<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsBytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)batch_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kBatchLdsBytes);
+}
+
+template hipError_t launch_batch<float>(const BatchDesc<float>*, uint32_t, const BatchGate*, const Mat2<float>*,
+                                        double*, int, hipStream_t);
+template hipError_t launch_batch<double>(const BatchDesc<double>*, uint32_t, const BatchGate*,
+                                         const Mat2<double>*, double*, int, hipStream_t);
+
+}  // namespace vqe

@@ -76,6 +76,34 @@ struct TermDesc {
     T cre, cim;
 };
 
+// ---------------------------------------------------------------- batched small states (batch.hip)
+constexpr int kBatchLdsBytes = 128 * 1024;  // psi + lam in LDS
+constexpr int kBatchMaxQubitsC64 = 13;
+constexpr int kBatchMaxQubitsC128 = 12;
+
+struct BatchGate {
+    uint8_t type;  // OP_U2, OP_CNOT, OP_CZ, OP_XFLIP
+    uint8_t q0, q1;
+    uint8_t gen;   // OP_GX / OP_GY / OP_GZ for parameterised gates
+    int32_t pidx;  // parameter index or -1
+    uint32_t mat;  // matrix index within the request
+    uint32_t pad;
+};
+
+template <typename T>
+struct BatchDesc {
+    int32_t n;
+    uint32_t n_gates, gate_off, mat_off, n_groups, n_params;
+    uint64_t out_off;  // out[out_off] = energy, out[out_off + 1 + k] = dE/dtheta_k
+    const GroupDesc* groups;
+    const TermDesc<T>* terms;
+};
+
+template <typename T>
+hipError_t launch_batch(const BatchDesc<T>* items, uint32_t n_items, const BatchGate* gates, const Mat2<T>* mats,
+                        double* out, int max_n, hipStream_t st);
+hipError_t batch_set_lds_limit();
+
 // ---------------------------------------------------------------- launchers (kernels.hip)
 hipError_t launch_set_basis(int dtype, void* psi, uint64_t dim, uint64_t b, hipStream_t st);
 hipError_t launch_zero(double* p, uint64_t n, hipStream_t st);

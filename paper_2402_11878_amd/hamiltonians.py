@@ -49,6 +49,8 @@ def fermion_products(ops, coeff):
     left to right; coeff: array of the same length.  Returns flat (x, z, c).
     """
     T = len(coeff)
+    if T == 0:
+        return np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0, np.complex128)
     x = np.zeros((T, 1), dtype=np.uint64)
     z = np.zeros((T, 1), dtype=np.uint64)
     c = np.asarray(coeff, dtype=np.complex128).reshape(T, 1)

@@ -1,0 +1,274 @@
+"""Continuous-batching request loop for energy + gradient evaluations.
+
+Many optimiser instances (each a circuit, a Hamiltonian and a qubit count)
+send evaluation requests theta -> (E(theta), dE/dtheta); the paper ran the
+independent circuit runs of an optimiser iteration concurrently on separate
+node groups (Sec. II-C).  Here they share one GPU:
+
+  * small requests (n <= the LDS limit of the batched kernel) are collected
+    while the device is busy and launched together, one workgroup per
+    request (vqe_batch_energy_grad);
+  * large requests run on worker threads, each instance on its own HIP stream
+    with its state vectors (psi, lam, checkpoints) resident in HBM, so
+    several instances' kernels overlap on the device;
+  * an instance becomes resident only while the summed footprint of resident
+    instances stays within the HBM budget; idle resident instances are
+    evicted least-recently-used first;
+  * requests are served oldest first; a request that has waited longer than
+    `max_wait` blocks admission of younger ones until it runs (no
+    starvation);
+  * a failing request resolves its own future with the error and the loop
+    carries on.
+Each result depends only on its request (fixed kernels and reduction order),
+so it is bitwise the same whatever else is in flight.
+
+The executor is pluggable: ``GpuExecutor`` drives libvqe.so; tests drive the
+scheduler with a mock executor on the CPU.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Instance:
+    iid: int
+    n: int
+    circuit: object
+    hamiltonian: object
+    footprint: int = 0
+    resident: bool = False
+    busy: bool = False
+    last_used: float = 0.0
+    state: object = None
+
+
+@dataclass
+class Request:
+    inst: Instance
+    theta: np.ndarray
+    submit_t: float
+    future: Future = field(default_factory=Future)
+    done_t: float = 0.0
+
+
+def percentile(values, q):
+    """q-th percentile (0..100) by linear interpolation between order statistics."""
+    v = sorted(values)
+    if not v:
+        return float("nan")
+    pos = (len(v) - 1) * q / 100.0
+    lo = int(np.floor(pos))
+    hi = min(lo + 1, len(v) - 1)
+    return v[lo] + (v[hi] - v[lo]) * (pos - lo)
+
+
+class Server:
+    def __init__(self, executor, budget_bytes, n_workers=4, max_batch=64, max_wait=2.0, clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_batch = max_batch
+        self.max_wait = max_wait
+        self.clock = clock
+        self.instances = {}
+        self.used = 0
+        self.peak_used = 0
+        self._cv = threading.Condition()
+        self._small = collections.deque()
+        self._large = collections.deque()
+        self._closing = False
+        self.completed = []
+        self.batches = []          # sizes of the launched batches
+        self.max_concurrent = 0
+        self._running = 0
+        self._threads = [threading.Thread(target=self._batch_loop, daemon=True)]
+        self._threads += [threading.Thread(target=self._worker_loop, daemon=True) for _ in range(n_workers)]
+        for t in self._threads:
+            t.start()
+
+    # ------------------------------------------------------------ client side
+    def add_instance(self, iid, n, circuit, hamiltonian):
+        inst = Instance(iid, n, circuit, hamiltonian)
+        inst.footprint = self.ex.footprint(inst)
+        if not self.ex.is_small(inst) and inst.footprint > self.budget:
+            raise ValueError(f"instance {iid} needs {inst.footprint} bytes, more than the budget {self.budget}")
+        with self._cv:
+            self.instances[iid] = inst
+        return inst
+
+    def submit(self, iid, theta):
+        inst = self.instances[iid]
+        req = Request(inst, np.asarray(theta, dtype=np.float64), self.clock())
+        with self._cv:
+            if self._closing:
+                raise RuntimeError("server is closed")
+            (self._small if self.ex.is_small(inst) else self._large).append(req)
+            self._cv.notify_all()
+        return req.future
+
+    def close(self):
+        with self._cv:
+            self._closing = True
+            self._cv.notify_all()
+        for t in self._threads:
+            t.join()
+        for inst in self.instances.values():
+            if inst.resident:
+                self.ex.release(inst)
+                inst.resident = False
+
+    def latencies(self):
+        return [r.done_t - r.submit_t for r in self.completed]
+
+    # ------------------------------------------------------------ internals
+    def _finish(self, req, result=None, error=None):
+        req.done_t = self.clock()
+        with self._cv:
+            self.completed.append(req)
+        if error is not None:
+            req.future.set_exception(error)
+        else:
+            req.future.set_result(result)
+
+    def _batch_loop(self):
+        while True:
+            with self._cv:
+                while not self._small and not self._closing:
+                    self._cv.wait()
+                if not self._small and self._closing:
+                    return
+                batch = [self._small.popleft() for _ in range(min(self.max_batch, len(self._small)))]
+                self._running += 1
+                self.max_concurrent = max(self.max_concurrent, self._running)
+            self.batches.append(len(batch))
+            try:
+                results = self.ex.run_batch([(r.inst, r.theta) for r in batch])
+            except Exception as e:  # the whole launch failed: fail its requests, keep serving
+                results = [e] * len(batch)
+            with self._cv:
+                self._running -= 1
+            for r, res in zip(batch, results):
+                if isinstance(res, Exception):
+                    self._finish(r, error=res)
+                else:
+                    self._finish(r, result=res)
+
+    def _admit(self, inst):
+        """Make inst resident if the budget allows (evicting idle instances). Caller holds the lock."""
+        if inst.resident:
+            return True
+        need = inst.footprint
+        if self.used + need > self.budget:
+            idle = sorted((i for i in self.instances.values() if i.resident and not i.busy),
+                          key=lambda i: i.last_used)
+            for victim in idle:
+                if self.used + need <= self.budget:
+                    break
+                self.ex.release(victim)
+                victim.resident = False
+                self.used -= victim.footprint
+        if self.used + need > self.budget:
+            return False
+        self.ex.make_resident(inst)
+        inst.resident = True
+        self.used += need
+        self.peak_used = max(self.peak_used, self.used)
+        return True
+
+    def _pick(self):
+        """Oldest runnable large request (caller holds the lock), or None."""
+        now = self.clock()
+        for k, req in enumerate(self._large):
+            if req.inst.busy:
+                continue
+            if self._admit(req.inst):
+                del self._large[k]
+                return req
+            if now - req.submit_t > self.max_wait:
+                return None          # the old request waits for memory: admit nobody younger
+        return None
+
+    def _worker_loop(self):
+        while True:
+            with self._cv:
+                while True:
+                    if self._closing and not self._large:
+                        return
+                    req = self._pick()
+                    if req is not None:
+                        break
+                    self._cv.wait(timeout=0.05)
+                req.inst.busy = True
+                self._running += 1
+                self.max_concurrent = max(self.max_concurrent, self._running)
+            try:
+                res = self.ex.run_one(req.inst, req.theta)
+                err = None
+            except Exception as e:
+                res, err = None, e
+            with self._cv:
+                req.inst.busy = False
+                req.inst.last_used = self.clock()
+                self._running -= 1
+                self._cv.notify_all()
+            self._finish(req, result=res, error=err)
+
+
+class GpuExecutor:
+    """Runs requests with libvqe.so: batched LDS kernel for small states, the
+    fused-pass adjoint path on per-instance streams for large ones."""
+
+    def __init__(self, dtype="c64", n_ckpt=0, small_n_max=None):
+        import torch
+
+        from . import _lib
+        self.torch, self.L = torch, _lib
+        self.dtype = _lib.VQE_C64 if dtype == "c64" else _lib.VQE_C128
+        self.tdtype = torch.complex64 if self.dtype == _lib.VQE_C64 else torch.complex128
+        self.amp = 8 if self.dtype == _lib.VQE_C64 else 16
+        self.n_ckpt = n_ckpt
+        lim = _lib.BATCH_MAX_QUBITS[self.dtype]
+        self.small_n_max = lim if small_n_max is None else min(small_n_max, lim)
+        self.batch_stream = torch.cuda.Stream()
+        self.batch = _lib.vqe_batch_create(self.dtype, self.batch_stream.cuda_stream)
+
+    def is_small(self, inst):
+        return inst.n <= self.small_n_max
+
+    def footprint(self, inst):
+        # resident vectors: psi, lam and the checkpoints (8 * 2^n bytes per complex64 vector)
+        return 0 if self.is_small(inst) else (2 + self.n_ckpt) * self.amp * (1 << inst.n)
+
+    def make_resident(self, inst):
+        torch, L = self.torch, self.L
+        st = torch.cuda.Stream()
+        bufs = [torch.empty(1 << inst.n, dtype=self.tdtype, device="cuda") for _ in range(2 + self.n_ckpt)]
+        hs = [L.vqe_state_alloc(inst.n, self.dtype, b.data_ptr(), b.numel() * b.element_size(), st.cuda_stream)
+              for b in bufs]
+        inst.state = (st, bufs, hs)
+
+    def release(self, inst):
+        st, bufs, hs = inst.state
+        for h in hs:
+            self.L.vqe_state_free(h)
+        inst.state = None
+
+    def run_one(self, inst, theta):
+        st, bufs, hs = inst.state
+        return self.L.vqe_energy_grad(hs[0], hs[1], inst.circuit.handle, theta, inst.hamiltonian.handle,
+                                      ckpt=hs[2:])
+
+    def run_batch(self, items):
+        return self.L.vqe_batch_energy_grad(
+            self.batch, [(inst.circuit.handle, inst.hamiltonian.handle, th) for inst, th in items])
+
+    def close(self):
+        if self.batch:
+            self.L.vqe_batch_free(self.batch)
+            self.batch = None

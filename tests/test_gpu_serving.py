@@ -1,0 +1,81 @@
+"""GPU: the autograd Function, and the serving loop on the device — every
+served result equals the same request run alone, bit for bit, and matches the
+oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import grad as ogr, hamiltonian as oham
+from paper_2402_11878_amd import _lib, hamiltonians as lham
+from paper_2402_11878_amd.core import Circuit, Hamiltonian
+
+from gpu_util import oracle_gates, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _chain(n, U=4.0):
+    lat = synth.Lattice(n // 2, tuple(synth.chain_bonds(n // 2)), 1.0, U)
+    return lham.from_lattice(lat)
+
+
+def test_energy_fn_autograd():
+    import torch
+    from paper_2402_11878_amd.autograd import EnergyFn, Workspace
+    say("case autograd")
+    n, L = 10, 3
+    x, z, w = _chain(n)
+    H = Hamiltonian(n, x, z, w)
+    C = Circuit.layered(n, L)
+    th = torch.tensor(synth.theta(8, C.n_params), dtype=torch.float64, requires_grad=True)
+    ws = Workspace()
+    E = EnergyFn.apply(th, H, C, "c128", 0, ws)
+    E.backward()
+    E_ref, g_ref = ogr.adjoint(n, oracle_gates(C.gates), th.detach().numpy(), oham.from_masks(n, x, z, w))
+    assert rel_err(E.item(), E_ref) <= 1e-10
+    assert np.max(np.abs(th.grad.numpy() - g_ref)) <= 1e-9 * max(np.max(np.abs(g_ref)), 1)
+    # chain rule through a downstream expression
+    th2 = th.detach().clone().requires_grad_(True)
+    loss = 3.0 * EnergyFn.apply(th2, H, C, "c128", 0, ws) ** 2
+    loss.backward()
+    assert np.max(np.abs(th2.grad.numpy() - 6.0 * E_ref * g_ref)) <= 1e-8 * max(abs(6 * E_ref), 1)
+    ws.clear()
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_served_equals_alone(dt):
+    import torch
+    from paper_2402_11878_amd.serving import GpuExecutor, Server
+    say(f"case serving {dt}")
+    specs = [(8, 2, 0), (12, 3, 1), (14, 2, 2), (16, 2, 3), (10, 4, 4), (18, 1, 5)]
+    insts = []
+    for n, L, seed in specs:
+        x, z, w = _chain(n)
+        insts.append((n, Circuit.layered(n, L), Hamiltonian(n, x, z, w), x, z, w, seed))
+    ex = GpuExecutor(dt, n_ckpt=1)
+    budget = 64 << 20
+    reqs = [(i, synth.theta(100 * i + k, insts[i][1].n_params)) for k in range(3) for i in range(len(insts))]
+    # alone: one request at a time
+    srv = Server(ex, budget, n_workers=1)
+    for i, (n, C, H, *_r) in enumerate(insts):
+        srv.add_instance(i, n, C, H)
+    alone = [srv.submit(i, th).result(timeout=120) for i, th in reqs]
+    srv.close()
+    # mix: everything in flight at once
+    srv = Server(ex, budget, n_workers=4)
+    for i, (n, C, H, *_r) in enumerate(insts):
+        srv.add_instance(i, n, C, H)
+    futs = [srv.submit(i, th) for i, th in reqs]
+    mixed = [f.result(timeout=120) for f in futs]
+    srv.close()
+    ex.close()
+    assert max(srv.batches) >= 1
+    for (E1, g1), (E2, g2) in zip(alone, mixed):
+        assert E1 == E2 and np.array_equal(g1, g2)
+    # and against the oracle
+    te, tg = (1e-10, 1e-9) if dt == "c128" else (1e-5, 1e-4)
+    for (i, th), (E, g) in list(zip(reqs, mixed))[:len(insts)]:
+        n, C, H, x, z, w, seed = insts[i]
+        E_ref, g_ref = ogr.adjoint(n, oracle_gates(C.gates), th, oham.from_masks(n, x, z, w))
+        assert rel_err(E, E_ref) <= te
+        assert np.max(np.abs(g - g_ref)) / max(np.max(np.abs(g_ref)), 1) <= tg

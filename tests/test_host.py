@@ -45,7 +45,15 @@ def test_jw_hubbard_matches_oracle(name):
     assert np.max(np.abs(ow - lw)) <= 1e-14
 
 
-@pytest.mark.parametrize("n_orb,seed", [(2, 0), (3, 1), (4, 2)])
+@pytest.mark.parametrize("sites,bonds", [(1, []), (2, [(0, 1)]), (5, synth.snake_bonds(1, 5, True))])
+def test_jw_small_lattices_match_oracle(sites, bonds):
+    ox, oz, ow = _oracle_masks(oham.hubbard(sites, bonds, 1.0, 3.0))
+    lx, lz, lw = lham.hubbard(sites, bonds, 1.0, 3.0)
+    assert np.array_equal(ox, lx) and np.array_equal(oz, lz)
+    assert np.max(np.abs(ow - lw)) <= 1e-14
+
+
+@pytest.mark.parametrize("n_orb,seed", [(1, 3), (2, 0), (3, 1), (4, 2)])
 def test_jw_molecule_matches_oracle(n_orb, seed):
     h, g = synth.molecule_integrals(n_orb, seed)
     ox, oz, ow = _oracle_masks(oham.molecule(h, g))

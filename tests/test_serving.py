@@ -1,0 +1,176 @@
+"""Scheduler tests of the serving loop on the CPU, with a mock executor that
+sleeps instead of launching kernels and checks the HBM budget itself."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2402_11878_amd.serving import Server, percentile
+
+
+class MockExecutor:
+    def __init__(self, budget, small_n_max=12, fail_theta=None, dur=0.02):
+        self.budget = budget
+        self.small_n_max = small_n_max
+        self.fail_theta = fail_theta
+        self.dur = dur
+        self.resident = 0
+        self.lock = threading.Lock()
+        self.running = 0
+        self.max_running = 0
+        self.order = []
+
+    def is_small(self, inst):
+        return inst.n <= self.small_n_max
+
+    def footprint(self, inst):
+        return 0 if self.is_small(inst) else 3 * 8 * (1 << inst.n)
+
+    def make_resident(self, inst):
+        with self.lock:
+            self.resident += inst.footprint
+            assert self.resident <= self.budget, "budget exceeded"
+        inst.state = "buffers"
+
+    def release(self, inst):
+        with self.lock:
+            self.resident -= inst.footprint
+        inst.state = None
+
+    def _result(self, theta):
+        if self.fail_theta is not None and theta[0] == self.fail_theta:
+            raise RuntimeError("injected failure")
+        return float(np.sum(theta)), 2 * theta
+
+    def run_one(self, inst, theta):
+        assert inst.state == "buffers"
+        with self.lock:
+            self.running += 1
+            self.max_running = max(self.max_running, self.running)
+            self.order.append(inst.iid)
+        time.sleep(self.dur * (1 + (inst.n - 12) / 8))
+        with self.lock:
+            self.running -= 1
+        return self._result(theta)
+
+    def run_batch(self, items):
+        time.sleep(self.dur)
+        out = []
+        for inst, th in items:
+            try:
+                out.append(self._result(th))
+            except Exception as e:
+                out.append(e)
+        return out
+
+
+def _server(ex, budget, **kw):
+    return Server(ex, budget, **kw)
+
+
+def test_results_and_budget():
+    budget = 3 * 8 * (1 << 20) * 2        # room for two 20-qubit instances
+    ex = MockExecutor(budget)
+    srv = _server(ex, budget, n_workers=3)
+    for i, n in enumerate([12, 16, 20, 20, 20, 12]):
+        srv.add_instance(i, n, None, None)
+    futs = [(i, k, srv.submit(i, np.full(3, float(10 * i + k)))) for k in range(4) for i in range(6)]
+    for i, k, f in futs:
+        E, g = f.result(timeout=20)
+        assert E == 3 * (10 * i + k)
+    srv.close()
+    assert srv.peak_used <= budget
+    assert ex.resident == 0
+    assert ex.max_running >= 2                 # large requests overlapped
+
+
+def test_small_requests_are_batched_while_busy():
+    ex = MockExecutor(1 << 30, dur=0.05)
+    srv = _server(ex, 1 << 30, n_workers=1, max_batch=64)
+    for i in range(10):
+        srv.add_instance(i, 12, None, None)
+    futs = [srv.submit(i % 10, np.array([float(i)])) for i in range(40)]
+    for f in futs:
+        f.result(timeout=20)
+    srv.close()
+    assert max(srv.batches) > 1
+    assert sum(srv.batches) == 40
+
+
+def test_continuous_admission():
+    """Requests that arrive while others are running start before those finish."""
+    budget = 1 << 30
+    ex = MockExecutor(budget, dur=0.2)
+    srv = _server(ex, budget, n_workers=4)
+    for i in range(4):
+        srv.add_instance(i, 16, None, None)
+    f0 = srv.submit(0, np.zeros(2))
+    time.sleep(0.05)
+    f1 = srv.submit(1, np.zeros(2))
+    f1.result(timeout=10)
+    f0.result(timeout=10)
+    srv.close()
+    r0, r1 = srv.completed[0], srv.completed[1]
+    assert ex.max_running == 2
+
+
+def test_failure_isolation():
+    ex = MockExecutor(1 << 30, fail_theta=-1.0)
+    srv = _server(ex, 1 << 30, n_workers=2)
+    srv.add_instance(0, 12, None, None)
+    srv.add_instance(1, 16, None, None)
+    good = [srv.submit(i % 2, np.array([float(i)])) for i in range(6)]
+    bad = [srv.submit(0, np.array([-1.0])), srv.submit(1, np.array([-1.0]))]
+    more = [srv.submit(i % 2, np.array([float(i)])) for i in range(6)]
+    for f in good + more:
+        assert f.result(timeout=10)[0] >= 0
+    for f in bad:
+        with pytest.raises(RuntimeError):
+            f.result(timeout=10)
+    srv.close()
+
+
+def test_no_starvation_of_large_instance():
+    """A 20-qubit instance needing the whole budget runs although smaller
+    instances keep the memory busy."""
+    big = 3 * 8 * (1 << 20)
+    budget = big
+    ex = MockExecutor(budget, dur=0.01)
+    srv = _server(ex, budget, n_workers=3, max_wait=0.1)
+    srv.add_instance(0, 20, None, None)
+    for i in range(1, 4):
+        srv.add_instance(i, 16, None, None)
+    stop = threading.Event()
+
+    def spam():
+        k = 0
+        while not stop.is_set():
+            srv.submit(1 + k % 3, np.zeros(1))
+            k += 1
+            time.sleep(0.002)
+
+    t = threading.Thread(target=spam)
+    t.start()
+    time.sleep(0.05)
+    f = srv.submit(0, np.ones(1))
+    f.result(timeout=10)
+    stop.set()
+    t.join()
+    srv.close()
+    assert srv.peak_used <= budget
+
+
+def test_oversized_instance_rejected():
+    ex = MockExecutor(1 << 20)
+    srv = _server(ex, 1 << 20)
+    with pytest.raises(ValueError):
+        srv.add_instance(0, 20, None, None)
+    srv.close()
+
+
+def test_percentile_matches_numpy():
+    rng = np.random.default_rng(0)
+    v = rng.exponential(size=101).tolist()
+    for q in (50, 90, 99):
+        assert abs(percentile(v, q) - np.percentile(v, q)) < 1e-12
