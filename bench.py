@@ -118,6 +118,128 @@ def cpu_baseline(wl_name):
                 sample_seconds=t, host_cpus=os.cpu_count())
 
 
+def serving_bench(args):
+    """Served stream of 32 optimiser instances (complex64, adjoint gradients,
+    continuous batching) against one-at-a-time complex128 per-term energies
+    with parameter-shift gradients on the same GPU."""
+    import torch
+    import synth
+    from paper_2402_11878_amd import _lib as L, hamiltonians as hm
+    from paper_2402_11878_amd.core import Circuit, Hamiltonian
+    from paper_2402_11878_amd.serving import GpuExecutor, Server, percentile
+
+    n_inst = args.instances
+    insts = []
+    for i in range(n_inst):
+        n, (kind, src), layers, rng = synth.serving_instance(i)
+        if kind == "hubbard":
+            x, z, w = hm.from_lattice(src)
+        else:
+            h, g = synth.molecule_integrals(*src)
+            x, z, w = hm.molecule(h, g)
+            keep, _, _ = L.vqe_slim_hamiltonian(x, z, w, L.SLIM_THRESHOLD, args.slim)
+            k = keep.astype(bool)
+            x, z, w = x[k], z[k], w[k]
+        insts.append(dict(i=i, n=n, kind=kind, layers=layers, rng=rng, C=Circuit.layered(n, layers),
+                          H=Hamiltonian(n, x, z, w)))
+    log(f"[serving] {n_inst} instances built")
+    ex = GpuExecutor("c64", n_ckpt=0)
+    budget = int(args.budget_gib * (1 << 30))
+
+    def new_server():
+        srv = Server(ex, budget, n_workers=args.workers)
+        for d in insts:
+            srv.add_instance(d["i"], d["n"], d["C"], d["H"])
+        return srv
+
+    def draw(d):
+        return d["rng"].uniform(-np.pi, np.pi, size=d["C"].n_params)
+
+    srv = new_server()
+    for f in [srv.submit(d["i"], draw(d)) for d in insts]:      # warm-up, makes instances resident
+        f.result()
+    torch.cuda.synchronize()
+    # capacity: every instance submits `reps` requests at once
+    reqs = [(d["i"], draw(d)) for _ in range(args.reps) for d in insts]
+    t0 = time.perf_counter()
+    for f in [srv.submit(i, th) for i, th in reqs]:
+        f.result()
+    cap = len(reqs) / (time.perf_counter() - t0)
+    log(f"[serving] capacity {cap:.2f} evals/s")
+    srv.close()
+    loads = {}
+    for frac in (0.5, 0.8, 0.95):
+        srv = new_server()
+        for f in [srv.submit(d["i"], draw(d)) for d in insts]:
+            f.result()
+        srv.completed.clear()
+        rate = frac * cap
+        arr_rng = np.random.default_rng(int(frac * 100))
+        order = arr_rng.integers(0, n_inst, size=args.requests)
+        gaps = arr_rng.exponential(1.0 / rate, size=args.requests)
+        futs = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for k in range(args.requests):
+            t_next += gaps[k]
+            while time.perf_counter() < t_next:
+                time.sleep(min(0.001, max(t_next - time.perf_counter(), 0)))
+            d = insts[order[k]]
+            futs.append(srv.submit(d["i"], draw(d)))
+        for f in futs:
+            f.result()
+        t_end = time.perf_counter()
+        lat = srv.latencies()
+        loads[str(frac)] = dict(offered=rate, achieved=len(futs) / (t_end - t_start),
+                                p50_ms=percentile(lat, 50) * 1e3, p99_ms=percentile(lat, 99) * 1e3,
+                                batches=len(srv.batches), mean_batch=float(np.mean(srv.batches)) if srv.batches else 0)
+        log(f"[serving] load {frac}: {loads[str(frac)]}")
+        srv.close()
+    ex.close()
+    # baseline: complex128, per-term energy, parameter shift, one request at a time
+    base_t = []
+    acc = []
+    for d in insts:
+        n = d["n"]
+        bufs = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+        st = torch.cuda.current_stream().cuda_stream
+        s = L.vqe_state_alloc(n, L.VQE_C128, bufs.data_ptr(), bufs.numel() * 16, st)
+        th = draw(d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.vqe_state_set_basis(s, 0)
+        L.vqe_apply_circuit(s, d["C"].handle, th)
+        E_pt, _ = L.vqe_expect_pauli(s, d["H"].handle, L.EXPECT_PER_TERM)
+        t_e = time.perf_counter() - t0
+        base_t.append((2 * d["C"].n_params + 1) * t_e)
+        if n <= 12:   # full baseline evaluation vs the served form at small n
+            Eb, gb = L.vqe_energy_grad(s, None, d["C"].handle, th, d["H"].handle, method=L.GRAD_PARAM_SHIFT,
+                                       expect_mode=L.EXPECT_PER_TERM)
+            b = L.vqe_batch_create(L.VQE_C64, st)
+            (Es, gs), = L.vqe_batch_energy_grad(b, [(d["C"].handle, d["H"].handle, th)])
+            L.vqe_batch_free(b)
+            acc.append(dict(n=n, energy_rel=abs(Es - Eb) / max(abs(Eb), 1),
+                            grad_rel=float(np.max(np.abs(gs - gb)) / max(np.max(np.abs(gb)), 1))))
+        L.vqe_state_free(s)
+        del bufs
+    torch.cuda.empty_cache()
+    base_rate = 1.0 / float(np.mean(base_t))
+    out = {
+        "metric": "served energy+gradient evals/s (32 optimiser instances) and p50/p99 latency",
+        "value": cap, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32 state, f64 reductions", "data": "synthetic",
+        "config": {"workload": f"{n_inst} instances: n in {{12,16,20,24,28}}, 1-D/2-D Hubbard and molecule-shaped "
+                               f"(slimmed at {args.slim}) Hamiltonians, 4-16 layers, seeds 10000+i",
+                   "workers": args.workers, "budget_gib": args.budget_gib},
+        "loads": loads,
+        "baseline_per_term_param_shift_f64": {"evals_per_s": base_rate,
+                                              "method": "one request at a time: (2P+1) x measured per-term energy time"},
+        "speedup_vs_baseline": cap / base_rate,
+        "accuracy_vs_baseline_small": acc,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +249,14 @@ def main():
     ap.add_argument("--skip-c64", action="store_true")
     ap.add_argument("--skip-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="step", choices=["step", "serving"],
+                    help="step: the 32-qubit energy+gradient step (default); serving: the served stream")
+    ap.add_argument("--instances", type=int, default=32)
+    ap.add_argument("--requests", type=int, default=96)
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--budget-gib", type=float, default=160.0)
+    ap.add_argument("--slim", type=float, default=1e-3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (the path is single-device; "
@@ -140,6 +270,9 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     L.lib()
+    if args.mode == "serving":
+        serving_bench(args)
+        return
     wl = synth.WORKLOADS[args.workload]
     theta = wl.thetas()[0]
     res = {}
