@@ -39,6 +39,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel="window_rev", record="profiles/window_rev_hubbard4x4_32q_c128_traffic.txt"):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record (copy-calibrated), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, record)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2402_11878_amd", "csrc", "kernels.hip")
+    now = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("kernel") != kernel or kv.get("kernels_sha256") != now:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def run_dtype(torch, L, core, wl, dtype, n_ckpt, steps, warmup, theta):
     """Times `steps` energy+gradient evaluations; returns a result dict."""
     from paper_2402_11878_amd import hamiltonians as hm
@@ -240,6 +261,23 @@ def serving_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration(args):
+    """A plain device copy of known size (8 GiB read + 8 GiB written, 3 times):
+    the reference that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    nbytes = 8 << 30
+    a = torch.zeros(nbytes // 16, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": 3, "gbs": 2 * nbytes / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,8 +287,9 @@ def main():
     ap.add_argument("--skip-c64", action="store_true")
     ap.add_argument("--skip-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "serving"],
-                    help="step: the 32-qubit energy+gradient step (default); serving: the served stream")
+    ap.add_argument("--mode", default="step", choices=["step", "serving", "copy"],
+                    help="step: the 32-qubit energy+gradient step (default); serving: the served stream; "
+                         "copy: a plain 8 GiB device copy (counter calibration)")
     ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--requests", type=int, default=96)
     ap.add_argument("--reps", type=int, default=2)
@@ -272,6 +311,9 @@ def main():
     L.lib()
     if args.mode == "serving":
         serving_bench(args)
+        return
+    if args.mode == "copy":
+        copy_calibration(args)
         return
     wl = synth.WORKLOADS[args.workload]
     theta = wl.thetas()[0]
@@ -322,7 +364,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic() if head["name"] == "c128" else None,
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms,
         },
