@@ -99,7 +99,7 @@ def run_dtype(torch, L, core, wl, dtype, n_ckpt, steps, warmup, theta):
         torch.cuda.empty_cache()
     sec = (t1 - t0) / steps
     return dict(name=name, sec=sec, E=energies[-1], grad=g, energies=energies, prof=prof,
-                n_gates=len(circ.gates), n_passes_adj=circ.passes_count(L.VQE_C128), n_terms=H.n_terms,
+                n_gates=len(circ.gates), n_passes_adj=circ.passes_count(dtype), n_terms=H.n_terms,
                 n_groups=H.n_groups,
                 state_bytes=(1 << n) * (8 if dtype == L.VQE_C64 else 16), n_ckpt=n_ckpt)
 

@@ -148,9 +148,8 @@ int vqe_circuit_free(vqe_circuit* c);
  * state sweeps per application. */
 int vqe_circuit_info(const vqe_circuit* c, size_t* n_params, size_t* n_passes);
 
-/* Inspection of the fused plan used by forward-only sweeps of states of
- * `dtype` (adjoint evaluations use the VQE_C128 plan for both dtypes, whose
- * windows hold at most 4 qubits): pass `pass` has a
+/* Inspection of the fused plan used for states of `dtype` (windows of at
+ * most 5 qubits for VQE_C64, 4 for VQE_C128): pass `pass` has a
  * window of *window qubits (listed ascending in qubits[0..*window-1], at most
  * 5 entries) and applies *n_gates gates whose indices into the circuit's
  * gate list, in execution order, are written to gate_index (capacity

@@ -78,11 +78,9 @@ struct vqe_circuit {
     std::vector<BatchGate> bgates;  // gate table of the batched small-state kernel
     uint32_t n_mats = 0;            // matrices per evaluation (gates with a 2x2 matrix)
     Plan plan[2];  // [0]: kWindowC64-qubit windows, [1]: kWindowC128-qubit windows
-    // Forward-only sweeps (vqe_apply_circuit, parameter shift).
+    // The reverse kernel holds psi and lam: 2 x 2^K amplitudes per thread.
+    // complex64 fits 5-qubit windows in the register budget, complex128 4.
     const Plan& for_dtype(int dtype) const { return plan[dtype == VQE_C64 ? 0 : 1]; }
-    // Adjoint evaluations: the reverse kernel holds psi and lam, so both
-    // precisions use the smaller window (register budget of the reverse pass).
-    const Plan& for_adjoint() const { return plan[1]; }
 };
 
 struct vqe_hamiltonian {
@@ -464,7 +462,7 @@ int expect_impl(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy
 template <typename T>
 int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const double* params,
                  const vqe_hamiltonian* h, const vqe_grad_opts* o, double* energy, double* grad) {
-    const Plan& pl = c->for_adjoint();
+    const Plan& pl = c->for_dtype(psi->dtype);
     if (int rc0 = upload_plan(pl)) return rc0;
     const size_t P = pl.passes.size();
     std::vector<size_t> bounds;
