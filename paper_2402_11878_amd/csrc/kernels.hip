@@ -252,6 +252,234 @@ __device__ __forceinline__ void run_ops(const PassArgs<T>& a, T (&re)[NV][1 << K
     }
 }
 
+// ---------------------------------------------------------------- lane-split ops
+// In the lane-split layout a wave holds 32 cosets: lanes l and l+32 hold the
+// two halves of the same coset, split by the window's top local bit KL (lane
+// half `hi` = value of that bit).  Ops on bits < KL run in registers as above;
+// ops on bit KL exchange halves with v_permlane32_swap: swap(x, x) returns the
+// bit-0 half's value and the bit-1 half's value in every lane.
+
+template <typename T>
+__device__ __forceinline__ void halves(T x, T& h0, T& h1);
+
+template <>
+__device__ __forceinline__ void halves<float>(float x, float& h0, float& h1) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    h0 = __uint_as_float(r[0]);
+    h1 = __uint_as_float(r[1]);
+}
+
+template <>
+__device__ __forceinline__ void halves<double>(double x, double& h0, double& h1) {
+    const unsigned long long u = __double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    h0 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    h1 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+// 2x2 complex matrix on the split bit: out = c0 * a0 + c1 * a1 with this
+// lane's matrix row (row 0 for hi = 0, row 1 for hi = 1).
+template <int KL, int NV, typename T>
+__device__ __forceinline__ void xop_u2(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], const T* m, bool hi, bool real) {
+    const T c0r = hi ? m[4] : m[0], c0i = real ? T(0) : (hi ? m[5] : m[1]);
+    const T c1r = hi ? m[6] : m[2], c1i = real ? T(0) : (hi ? m[7] : m[3]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << KL); ++i) {
+            T a0r, a1r, a0i, a1i;
+            halves<T>(re[v][i], a0r, a1r);
+            halves<T>(im[v][i], a0i, a1i);
+            re[v][i] = c0r * a0r - c0i * a0i + c1r * a1r - c1i * a1i;
+            im[v][i] = c0r * a0i + c0i * a0r + c1r * a1i + c1i * a1r;
+        }
+    }
+}
+
+template <int KL, int NV, typename T>
+__device__ __forceinline__ void xop_diag(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], const T* m, bool hi) {
+    const T pr = hi ? m[6] : m[0], pi = hi ? m[7] : m[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << KL); ++i) {
+            const T ar = re[v][i], ai = im[v][i];
+            re[v][i] = pr * ar - pi * ai;
+            im[v][i] = pr * ai + pi * ar;
+        }
+    }
+}
+
+// X on the split bit: each half takes the other half's value.
+template <int KL, int NV, typename T>
+__device__ __forceinline__ void xop_xflip(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << KL); ++i) {
+            T a0, a1, b0, b1;
+            halves<T>(re[v][i], a0, a1);
+            halves<T>(im[v][i], b0, b1);
+            re[v][i] = hi ? a0 : a1;
+            im[v][i] = hi ? b0 : b1;
+        }
+    }
+}
+
+// CNOT with the split bit as target and register bit C as control.
+template <int KL, int C, int NV, typename T>
+__device__ __forceinline__ void xop_cnot_tgt(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << KL); ++i) {
+            if (!(i & (1 << C))) continue;
+            T a0, a1, b0, b1;
+            halves<T>(re[v][i], a0, a1);
+            halves<T>(im[v][i], b0, b1);
+            re[v][i] = hi ? a0 : a1;
+            im[v][i] = hi ? b0 : b1;
+        }
+    }
+}
+
+// CNOT with the split bit as control and register bit Tg as target: the
+// upper half swaps its Tg-pairs.
+template <int KL, int Tg, int NV, typename T>
+__device__ __forceinline__ void xop_cnot_ctl(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << KL); ++i) {
+            if (i & (1 << Tg)) continue;
+            const int j = i | (1 << Tg);
+            const T r0 = re[v][i], i0 = im[v][i], r1 = re[v][j], i1 = im[v][j];
+            re[v][i] = hi ? r1 : r0;
+            im[v][i] = hi ? i1 : i0;
+            re[v][j] = hi ? r0 : r1;
+            im[v][j] = hi ? i0 : i1;
+        }
+    }
+}
+
+// CZ between the split bit and register bit B: the upper half negates where B is set.
+template <int KL, int B, int NV, typename T>
+__device__ __forceinline__ void xop_cz(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
+    const T sg = hi ? T(-1) : T(1);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < (1 << KL); ++i) {
+            if (!(i & (1 << B))) continue;
+            re[v][i] *= sg;
+            im[v][i] *= sg;
+        }
+    }
+}
+
+// Gradient Im<lam|G|psi> for G on the split bit; each pair counted once (by the lower half).
+template <int KL, int G, typename T>
+__device__ __forceinline__ T xop_grad(T (&re)[2][1 << KL], T (&im)[2][1 << KL], bool hi) {
+    T acc = 0;
+    if constexpr (G == OP_GZ) {
+#pragma unroll
+        for (int i = 0; i < (1 << KL); ++i) acc += re[1][i] * im[0][i] - im[1][i] * re[0][i];
+        return hi ? -acc : acc;
+    } else {
+#pragma unroll
+        for (int i = 0; i < (1 << KL); ++i) {
+            T p0r, p1r, p0i, p1i, l0r, l1r, l0i, l1i;
+            halves<T>(re[0][i], p0r, p1r);
+            halves<T>(im[0][i], p0i, p1i);
+            halves<T>(re[1][i], l0r, l1r);
+            halves<T>(im[1][i], l0i, l1i);
+            if constexpr (G == OP_GY)
+                acc += (l1r * p0r + l1i * p0i) - (l0r * p1r + l0i * p1i);
+            else
+                acc += (l0r * p1i - l0i * p1r) + (l1r * p0i - l1i * p0r);
+        }
+        return hi ? T(0) : acc;
+    }
+}
+
+#define VQE_LBIT_CASES(CALL)                                              \
+    case 0: if constexpr (KL > 0) { constexpr int B = 0; CALL; } break;   \
+    case 1: if constexpr (KL > 1) { constexpr int B = 1; CALL; } break;   \
+    case 2: if constexpr (KL > 2) { constexpr int B = 2; CALL; } break;   \
+    case 3: if constexpr (KL > 3) { constexpr int B = 3; CALL; } break;   \
+    default: break;
+
+template <int KL, int NV, typename T>
+__device__ __forceinline__ void d_xcnot_tgt(int c, T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
+    switch (c) { VQE_LBIT_CASES((xop_cnot_tgt<KL, B, NV, T>(re, im, hi))) }
+}
+template <int KL, int NV, typename T>
+__device__ __forceinline__ void d_xcnot_ctl(int t, T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
+    switch (t) { VQE_LBIT_CASES((xop_cnot_ctl<KL, B, NV, T>(re, im, hi))) }
+}
+template <int KL, int NV, typename T>
+__device__ __forceinline__ void d_xcz(int b, T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
+    switch (b) { VQE_LBIT_CASES((xop_cz<KL, B, NV, T>(re, im, hi))) }
+}
+
+// Op loop of the lane-split layout: window bits 0..KL-1 in registers, bit KL
+// across lane halves.
+template <int KL, int NV, typename T>
+__device__ __forceinline__ void run_ops_split(const PassArgs<T>& a, T (&re)[NV][1 << KL], T (&im)[NV][1 << KL],
+                                              double* gacc, int tid, bool hi) {
+    for (uint32_t o = 0; o < a.n_ops; ++o) {
+        const KOp op = a.ops[o];
+        const T* m = a.mats[op.slot].v;
+        const bool top_a = op.a == KL;
+        switch (op.type) {
+            case OP_U2:
+                if (top_a) xop_u2<KL, NV, T>(re, im, m, hi, false);
+                else d_u2<KL, NV, T>(op.a, re, im, m);
+                break;
+            case OP_R2:
+                if (top_a) xop_u2<KL, NV, T>(re, im, m, hi, true);
+                else d_r2<KL, NV, T>(op.a, re, im, m);
+                break;
+            case OP_DIAG:
+                if (top_a) xop_diag<KL, NV, T>(re, im, m, hi);
+                else d_diag<KL, NV, T>(op.a, re, im, m);
+                break;
+            case OP_XFLIP:
+                if (top_a) xop_xflip<KL, NV, T>(re, im, hi);
+                else d_xflip<KL, NV, T>(op.a, re, im);
+                break;
+            case OP_CNOT:
+                if (top_a) d_xcnot_ctl<KL, NV, T>(op.b, re, im, hi);
+                else if (op.b == KL) d_xcnot_tgt<KL, NV, T>(op.a, re, im, hi);
+                else d_cnot<KL, NV, T>(op.a, op.b, re, im);
+                break;
+            case OP_CZ:
+                if (top_a) d_xcz<KL, NV, T>(op.b, re, im, hi);
+                else if (op.b == KL) d_xcz<KL, NV, T>(op.a, re, im, hi);
+                else d_cz<KL, NV, T>(op.a, op.b, re, im);
+                break;
+            case OP_GX:
+                if constexpr (NV == 2)
+                    gacc[op.slot * kBlock + tid] +=
+                        (double)(top_a ? xop_grad<KL, OP_GX, T>(re, im, hi) : d_grad<KL, OP_GX, T>(op.a, re, im));
+                break;
+            case OP_GY:
+                if constexpr (NV == 2)
+                    gacc[op.slot * kBlock + tid] +=
+                        (double)(top_a ? xop_grad<KL, OP_GY, T>(re, im, hi) : d_grad<KL, OP_GY, T>(op.a, re, im));
+                break;
+            case OP_GZ:
+                if constexpr (NV == 2)
+                    gacc[op.slot * kBlock + tid] +=
+                        (double)(top_a ? xop_grad<KL, OP_GZ, T>(re, im, hi) : d_grad<KL, OP_GZ, T>(op.a, re, im));
+                break;
+            default:
+                break;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- window pass
 // Loads / stores of one coset (the 2^K amplitudes of a window) to / from
 // registers.  `base` is the coset's lowest index; offsets are wave-uniform.
@@ -335,6 +563,93 @@ window_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t m
                 v1.x = re[NV - 1][p];
                 v1.y = im[NV - 1][p];
                 out1[idx] = v1;
+            }
+        }
+    }
+    if constexpr (NV == 2) {
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (tid < w)
+                for (uint32_t s = 0; s < a.n_gslots; ++s)
+                    gacc[s * kBlock + tid] += gacc[s * kBlock + tid + w];
+            __syncthreads();
+        }
+        if (tid < (int)a.n_gslots) gpart[(uint64_t)blockIdx.x * a.n_gslots + tid] = gacc[tid * kBlock];
+    }
+}
+
+// Lane-split direct mode (K >= 2): a wave holds 32 cosets; lane s and s+32
+// hold the halves of coset s split by the top window bit.  Half the registers
+// per thread of the plain direct mode, for windows whose full coset would not
+// fit the register budget (the reverse pass holds psi and lam).
+template <typename T, int K, int NV>
+__global__ void __launch_bounds__(kBlock)
+window_split_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t mlog,
+                    const typename VecOf<T>::type* __restrict__ in0, typename VecOf<T>::type* __restrict__ out0,
+                    const typename VecOf<T>::type* __restrict__ in1, typename VecOf<T>::type* __restrict__ out1,
+                    double* __restrict__ gpart) {
+    using V = typename VecOf<T>::type;
+    constexpr int KL = K - 1;
+    constexpr int N = 1 << KL;
+    constexpr int PER_BLOCK = kBlock / 2;  // cosets per block and iteration
+    __shared__ double gacc[NV == 2 ? kMaxGradSlots * kBlock : 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const bool hi = lane >= 32;
+    const int sub = (tid >> 6) * 32 + (lane & 31);
+    if constexpr (NV == 2) {
+        for (uint32_t s = 0; s < a.n_gslots; ++s) gacc[s * kBlock + tid] = 0.0;
+    }
+    uint64_t bitval[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) bitval[j] = 1ull << a.pos[j];
+    const uint64_t half_off = hi ? bitval[KL] : 0;
+    for (uint32_t it = 0; it < cpt; ++it) {
+        const uint64_t blk = xcd_order(
+            interleave ? (uint64_t)it * gridDim.x + blockIdx.x : (uint64_t)blockIdx.x * cpt + it, mlog);
+        const uint64_t c = blk * PER_BLOCK + sub;
+        if (c >= a.n_cosets) break;
+        uint64_t base = c;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint64_t low = base & (bitval[j] - 1);
+            base = ((base ^ low) << 1) | low;
+        }
+        base += half_off;
+        T re[NV][N], im[NV][N];
+        uint64_t sbase = base;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            uint64_t off = 0;
+#pragma unroll
+            for (int j = 0; j < KL; ++j)
+                if (p & (1 << j)) off += bitval[j];
+            const V v0 = in0[base + off];
+            re[0][p] = v0.x;
+            im[0][p] = v0.y;
+            if constexpr (NV == 2) {
+                const V v1 = in1[base + off];
+                re[NV - 1][p] = v1.x;
+                im[NV - 1][p] = v1.y;
+            }
+        }
+        run_ops_split<KL, NV, T>(a, re, im, gacc, tid, hi);
+        asm volatile("" : "+v"(sbase));
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            uint64_t off = 0;
+#pragma unroll
+            for (int j = 0; j < KL; ++j)
+                if (p & (1 << j)) off += bitval[j];
+            V v0;
+            v0.x = re[0][p];
+            v0.y = im[0][p];
+            out0[sbase + off] = v0;
+            if constexpr (NV == 2) {
+                V v1;
+                v1.x = re[NV - 1][p];
+                v1.y = im[NV - 1][p];
+                out1[sbase + off] = v1;
             }
         }
     }
@@ -698,10 +1013,18 @@ hipError_t launch_copy(int dtype, const void* src, void* dst, uint64_t dim, hipS
 // Launch shape of a window pass.  LDS mode for forward passes whose window
 // includes a lane qubit (< 6), when the state has at least K + 6 qubits.
 struct WinShape {
-    bool lds;
+    bool lds, split;
     LdsMap m;
     uint32_t cpt, grid, interleave, mlog;
 };
+
+// Lane-split layout where a full 5-qubit coset does not fit the register
+// budget at useful occupancy: the reverse pass (psi and lam) of both
+// precisions and the complex128 forward pass.
+template <typename T>
+bool use_split(int K, bool two_vectors) {
+    return K == 5 && (two_vectors || sizeof(T) == 8);
+}
 
 // Reverse passes (with per-block gradient partials) use a persistent grid of
 // at most kRevBlocks blocks; forward passes a one-shot grid.
@@ -725,12 +1048,13 @@ template <typename T>
 WinShape window_shape(const PassArgs<T>& a, int n, bool with_partials) {
     WinShape w{};
     const int K = (int)a.K;
+    w.split = use_split<T>(K, with_partials);
     bool low = false;
     for (int j = 0; j < K; ++j) low |= a.pos[j] < 6;
     // Measured on MI355X: staging pays for forward passes (one vector) but
     // not for reverse passes, whose two-vector chunks and barriers cost more
     // than the partly coalesced direct loads they replace.
-    if (low && n >= K + 6 && !with_partials) {
+    if (low && n >= K + 6 && !with_partials && !w.split) {
         w.lds = true;
         uint64_t wmask = 0;
         for (int j = 0; j < K; ++j) wmask |= 1ull << a.pos[j];
@@ -759,7 +1083,8 @@ WinShape window_shape(const PassArgs<T>& a, int n, bool with_partials) {
         return w;
     }
     w.lds = false;
-    grid_for_units((a.n_cosets + kBlock - 1) / kBlock, with_partials, w);
+    const uint64_t per_unit = w.split ? kBlock / 2 : kBlock;
+    grid_for_units((a.n_cosets + per_unit - 1) / per_unit, with_partials, w);
     return w;
 }
 
@@ -779,7 +1104,11 @@ hipError_t launch_window(const PassArgs<T>& a, int n, const void* in0, void* out
     V* o1 = (V*)out1;
 #define VQE_WIN(KK)                                                                                      \
     case KK:                                                                                             \
-        if (w.lds)                                                                                       \
+        if (w.split) {                                                                                   \
+            if constexpr (KK == 5)                                                                       \
+                hipLaunchKernelGGL((window_split_kernel<T, KK, NV>), dim3(w.grid), dim3(kBlock), 0, st, a, \
+                                   w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);                  \
+        } else if (w.lds)                                                                                \
             hipLaunchKernelGGL((window_lds_kernel<T, KK, NV>), dim3(w.grid), dim3(kBlock), 0, st, a, w.m, \
                                w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);                      \
         else                                                                                             \

@@ -15,7 +15,7 @@ namespace vqe {
 // ---------------------------------------------------------------- limits
 constexpr int kMaxWindow = 5;     // qubits fused per pass (2^5 amplitudes per thread)
 constexpr int kWindowC64 = 5;     // window used for complex64 states
-constexpr int kWindowC128 = 4;    // window used for complex128 states (register budget)
+constexpr int kWindowC128 = 5;    // window used for complex128 states
 constexpr int kMaxOps = 64;       // kernel ops per pass
 constexpr int kMaxMats = 32;      // 2x2 matrices per pass
 constexpr int kMaxGradSlots = 16; // parameterised gates per pass

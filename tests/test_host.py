@@ -172,7 +172,7 @@ def test_plan_is_valid_reordering(n, kind, seed):
         og = _oracle_gates(arr)
         th = synth.theta(seed, max(P, 1))
         ref = osv.run(n, og, th)
-        for dtype, kmax in ((_lib.VQE_C64, 5), (_lib.VQE_C128, 4)):
+        for dtype, kmax in ((_lib.VQE_C64, 5), (_lib.VQE_C128, 5)):
             order = []
             p = 0
             while True:
