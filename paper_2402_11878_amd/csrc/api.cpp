@@ -56,10 +56,17 @@ struct vqe_state {
     double* h_res = nullptr;   // pinned host mirror of d_res
 };
 
+// Physical op list of a pass in the lane-split layout with S split bits.
+struct SplitOps {
+    std::vector<KOp> ops;
+    uint8_t map_in[kMaxWindow] = {0}, map_out[kMaxWindow] = {0};  // physical slot -> window local bit
+};
+
 struct PassOps {
     std::vector<KOp> fwd, rev;
     std::vector<int> fwd_mat_gate, rev_mat_gate;  // matrix slot -> gate index
     std::vector<int32_t> slot_param;              // reverse gradient slot -> parameter
+    SplitOps fwd_split[3], rev_split[3];          // [S] for S = 1, 2
 };
 
 // A fused pass plan for one window size.
@@ -195,6 +202,7 @@ int ensure_res(vqe_state* s, size_t count) {
 }
 
 int upload_plan(const Plan& cpl);
+bool lower_split(const std::vector<KOp>& ops, int K, int S, SplitOps& out);
 
 // Uploads the grouped term tables to the current device (once).
 int upload_hamiltonian(const vqe_hamiltonian* ch) {
@@ -317,10 +325,22 @@ void build_args(const vqe_circuit* c, const Plan& pl, size_t pi, const double* p
     a.K = (uint32_t)p.K;
     a.n_cosets = 1ull << (c->n - p.K);
     for (int j = 0; j < p.K; ++j) a.pos[j] = (uint32_t)p.pos[j];
-    const auto& ops = reverse ? po.rev : po.fwd;
+    const int S = split_bits_for(sizeof(T) == 8, p.K, reverse);
+    a.split = (uint32_t)S;
     const auto& mg = reverse ? po.rev_mat_gate : po.fwd_mat_gate;
-    a.n_ops = (uint32_t)ops.size();
-    for (size_t i = 0; i < ops.size(); ++i) a.ops[i] = ops[i];
+    if (S == 0) {
+        const auto& ops = reverse ? po.rev : po.fwd;
+        a.n_ops = (uint32_t)ops.size();
+        for (size_t i = 0; i < ops.size(); ++i) a.ops[i] = ops[i];
+    } else {
+        const SplitOps& so = reverse ? po.rev_split[S] : po.fwd_split[S];
+        a.n_ops = (uint32_t)so.ops.size();
+        for (size_t i = 0; i < so.ops.size(); ++i) a.ops[i] = so.ops[i];
+        for (int sl = 0; sl < p.K; ++sl) {
+            a.pos_in[sl] = (uint32_t)p.pos[so.map_in[sl]];
+            a.pos_out[sl] = (uint32_t)p.pos[so.map_out[sl]];
+        }
+    }
     for (size_t i = 0; i < mg.size(); ++i) {
         const Gate& g = c->gates[mg[i]];
         fill_matrix(a.mats[i], g, angle_of(g, params), reverse);
@@ -599,8 +619,98 @@ int build_plan(vqe_circuit* c, int kwin, Plan& pl) {
         }
         pl.slot_off.push_back(slotmap.size());
         slotmap.insert(slotmap.end(), po.slot_param.begin(), po.slot_param.end());
+        for (int S = 1; S <= 2; ++S) {
+            if (p.K <= S + 1) continue;
+            if (!lower_split(po.fwd, p.K, S, po.fwd_split[S]) || !lower_split(po.rev, p.K, S, po.rev_split[S])) {
+                set_error("vqe_circuit_create: too many ops in a pass after lane transposes (internal limit)");
+                return VQE_ERR_STATE;
+            }
+        }
     }
     return VQE_OK;
+}
+
+
+// Window bits an op needs in registers (the others it can apply per lane).
+uint32_t reg_needs(const KOp& op) {
+    switch (op.type) {
+        case OP_U2:
+        case OP_R2:
+        case OP_XFLIP:
+        case OP_GX:
+        case OP_GY:
+            return 1u << op.a;
+        case OP_CNOT:
+            return (1u << op.a) | (1u << op.b);
+        default:  // OP_DIAG, OP_CZ, OP_GZ act per lane on a lane-resident bit
+            return 0;
+    }
+}
+
+// Lowers a logical op list (window local bits 0..K-1) to the lane-split layout
+// with S of the K bits in lane slots.  The S bits needed in registers least
+// often start in the lanes; before an op that needs a lane-resident bit in
+// registers, a TPOSE swaps it with the register bit whose next use is
+// furthest away.  Returns false if the op capacity would be exceeded.
+bool lower_split(const std::vector<KOp>& ops, int K, int S, SplitOps& out) {
+    const int KL = K - S;
+    int cost[kMaxWindow] = {0};
+    for (const auto& op : ops)
+        for (int w = 0; w < K; ++w)
+            if (reg_needs(op) >> w & 1) cost[w]++;
+    int order[kMaxWindow];
+    for (int w = 0; w < K; ++w) order[w] = w;
+    std::sort(order, order + K, [&](int x, int y) { return cost[x] != cost[y] ? cost[x] < cost[y] : x > y; });
+    int bit_at[kMaxWindow], slot_of[kMaxWindow];
+    std::vector<int> regs;
+    for (int j = 0; j < S; ++j) bit_at[KL + j] = order[j];
+    for (int j = S; j < K; ++j) regs.push_back(order[j]);
+    std::sort(regs.begin(), regs.end());
+    for (int r = 0; r < KL; ++r) bit_at[r] = regs[r];
+    for (int sl = 0; sl < K; ++sl) slot_of[bit_at[sl]] = sl;
+    for (int sl = 0; sl < K; ++sl) out.map_in[sl] = (uint8_t)bit_at[sl];
+    out.ops.clear();
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const KOp& op = ops[i];
+        const uint32_t need = reg_needs(op);
+        for (int w = 0; w < K; ++w) {
+            if (!(need >> w & 1) || slot_of[w] < KL) continue;
+            // evict the register bit (not needed by this op) used furthest in the future
+            int best_r = -1;
+            size_t best_next = 0;
+            for (int r = 0; r < KL; ++r) {
+                const int wb = bit_at[r];
+                if (need >> wb & 1) continue;
+                size_t nxt = ops.size();
+                for (size_t k = i + 1; k < ops.size(); ++k)
+                    if (reg_needs(ops[k]) >> wb & 1) {
+                        nxt = k;
+                        break;
+                    }
+                if (best_r < 0 || nxt > best_next) {
+                    best_r = r;
+                    best_next = nxt;
+                }
+            }
+            const int lane_slot = slot_of[w];
+            KOp t{};
+            t.type = OP_TPOSE;
+            t.a = (uint8_t)best_r;
+            t.b = (uint8_t)(lane_slot - KL);
+            out.ops.push_back(t);
+            const int wr = bit_at[best_r];
+            bit_at[best_r] = w;
+            bit_at[lane_slot] = wr;
+            slot_of[w] = best_r;
+            slot_of[wr] = lane_slot;
+        }
+        KOp ph = op;
+        ph.a = (uint8_t)slot_of[op.a];
+        if (op.type == OP_CNOT || op.type == OP_CZ) ph.b = (uint8_t)slot_of[op.b];
+        out.ops.push_back(ph);
+    }
+    for (int sl = 0; sl < K; ++sl) out.map_out[sl] = (uint8_t)bit_at[sl];
+    return out.ops.size() <= (size_t)kMaxPhysOps;
 }
 
 // Uploads the gradient slot maps of a plan to the current device (once).

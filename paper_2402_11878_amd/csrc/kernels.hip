@@ -253,53 +253,66 @@ __device__ __forceinline__ void run_ops(const PassArgs<T>& a, T (&re)[NV][1 << K
 }
 
 // ---------------------------------------------------------------- lane-split ops
-// In the lane-split layout a wave holds 32 cosets: lanes l and l+32 hold the
-// two halves of the same coset, split by the window's top local bit KL (lane
-// half `hi` = value of that bit).  Ops on bits < KL run in registers as above;
-// ops on bit KL exchange halves with v_permlane32_swap: swap(x, x) returns the
-// bit-0 half's value and the bit-1 half's value in every lane.
+// In the lane-split layout a wave holds 64 >> S cosets and S of the K window
+// bits live in lane bits: lane slot 0 is lane bit 5 (S = 1) or 4 (S = 2),
+// lane slot 1 is lane bit 5.  Which window bit sits in which register bit or
+// lane slot is planned on the host per pass (pos_in / pos_out give the qubit
+// of every slot at load and store).  Diagonal ops (phases, CZ, Z gradients)
+// act on a lane-resident bit per lane; any other op first gets its bits into
+// registers with OP_TPOSE: for each pair of register entries (i, i + 2^r),
+// v_permlane{32,16}_swap(a, b) turns (a, b) into (a_lo | b_lo, a_hi | b_hi)
+// (lanes with the lane bit 0 | 1), which swaps the roles of register bit r
+// and the lane bit, one instruction per dword and no copies.
 
-template <typename T>
-__device__ __forceinline__ void halves(T x, T& h0, T& h1);
-
-template <>
-__device__ __forceinline__ void halves<float>(float x, float& h0, float& h1) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    h0 = __uint_as_float(r[0]);
-    h1 = __uint_as_float(r[1]);
+template <int LB>
+__device__ __forceinline__ void tpose32(unsigned& a, unsigned& b) {
+    if constexpr (LB == 5) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    }
 }
 
-template <>
-__device__ __forceinline__ void halves<double>(double x, double& h0, double& h1) {
-    const unsigned long long u = __double_as_longlong(x);
-    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
-    h0 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-    h1 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+template <int LB>
+__device__ __forceinline__ void tpose(float& a, float& b) {
+    unsigned x = __float_as_uint(a), y = __float_as_uint(b);
+    tpose32<LB>(x, y);
+    a = __uint_as_float(x);
+    b = __uint_as_float(y);
 }
 
-// 2x2 complex matrix on the split bit: out = c0 * a0 + c1 * a1 with this
-// lane's matrix row (row 0 for hi = 0, row 1 for hi = 1).
-template <int KL, int NV, typename T>
-__device__ __forceinline__ void xop_u2(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], const T* m, bool hi, bool real) {
-    const T c0r = hi ? m[4] : m[0], c0i = real ? T(0) : (hi ? m[5] : m[1]);
-    const T c1r = hi ? m[6] : m[2], c1i = real ? T(0) : (hi ? m[7] : m[3]);
+template <int LB>
+__device__ __forceinline__ void tpose(double& a, double& b) {
+    const unsigned long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+    unsigned xl = (unsigned)x, xh = (unsigned)(x >> 32), yl = (unsigned)y, yh = (unsigned)(y >> 32);
+    tpose32<LB>(xl, yl);
+    tpose32<LB>(xh, yh);
+    a = __longlong_as_double((long long)(((unsigned long long)xh << 32) | xl));
+    b = __longlong_as_double((long long)(((unsigned long long)yh << 32) | yl));
+}
+
+template <int LB, int KL, int R, int NV, typename T>
+__device__ __forceinline__ void xop_tpose(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL]) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
         for (int i = 0; i < (1 << KL); ++i) {
-            T a0r, a1r, a0i, a1i;
-            halves<T>(re[v][i], a0r, a1r);
-            halves<T>(im[v][i], a0i, a1i);
-            re[v][i] = c0r * a0r - c0i * a0i + c1r * a1r - c1i * a1i;
-            im[v][i] = c0r * a0i + c0i * a0r + c1r * a1i + c1i * a1r;
+            if (i & (1 << R)) continue;
+            const int j = i | (1 << R);
+            tpose<LB>(re[v][i], re[v][j]);
+            tpose<LB>(im[v][i], im[v][j]);
         }
     }
 }
 
+// Phase diag(d0, d1) on a lane-resident bit (hb = this lane's value of it).
 template <int KL, int NV, typename T>
-__device__ __forceinline__ void xop_diag(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], const T* m, bool hi) {
-    const T pr = hi ? m[6] : m[0], pi = hi ? m[7] : m[1];
+__device__ __forceinline__ void xop_diag(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], const T* m, bool hb) {
+    const T pr = hb ? m[6] : m[0], pi = hb ? m[7] : m[1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
@@ -311,96 +324,28 @@ __device__ __forceinline__ void xop_diag(T (&re)[NV][1 << KL], T (&im)[NV][1 << 
     }
 }
 
-// X on the split bit: each half takes the other half's value.
-template <int KL, int NV, typename T>
-__device__ __forceinline__ void xop_xflip(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
+// Sign flip of the register entries with (i & MASK) == MASK where `neg` holds (CZ with a lane bit).
+template <int KL, int MASK, int NV, typename T>
+__device__ __forceinline__ void xop_neg(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool neg) {
+    const T sg = neg ? T(-1) : T(1);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
         for (int i = 0; i < (1 << KL); ++i) {
-            T a0, a1, b0, b1;
-            halves<T>(re[v][i], a0, a1);
-            halves<T>(im[v][i], b0, b1);
-            re[v][i] = hi ? a0 : a1;
-            im[v][i] = hi ? b0 : b1;
-        }
-    }
-}
-
-// CNOT with the split bit as target and register bit C as control.
-template <int KL, int C, int NV, typename T>
-__device__ __forceinline__ void xop_cnot_tgt(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-#pragma unroll
-        for (int i = 0; i < (1 << KL); ++i) {
-            if (!(i & (1 << C))) continue;
-            T a0, a1, b0, b1;
-            halves<T>(re[v][i], a0, a1);
-            halves<T>(im[v][i], b0, b1);
-            re[v][i] = hi ? a0 : a1;
-            im[v][i] = hi ? b0 : b1;
-        }
-    }
-}
-
-// CNOT with the split bit as control and register bit Tg as target: the
-// upper half swaps its Tg-pairs.
-template <int KL, int Tg, int NV, typename T>
-__device__ __forceinline__ void xop_cnot_ctl(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-#pragma unroll
-        for (int i = 0; i < (1 << KL); ++i) {
-            if (i & (1 << Tg)) continue;
-            const int j = i | (1 << Tg);
-            const T r0 = re[v][i], i0 = im[v][i], r1 = re[v][j], i1 = im[v][j];
-            re[v][i] = hi ? r1 : r0;
-            im[v][i] = hi ? i1 : i0;
-            re[v][j] = hi ? r0 : r1;
-            im[v][j] = hi ? i0 : i1;
-        }
-    }
-}
-
-// CZ between the split bit and register bit B: the upper half negates where B is set.
-template <int KL, int B, int NV, typename T>
-__device__ __forceinline__ void xop_cz(T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
-    const T sg = hi ? T(-1) : T(1);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-#pragma unroll
-        for (int i = 0; i < (1 << KL); ++i) {
-            if (!(i & (1 << B))) continue;
+            if ((i & MASK) != MASK) continue;
             re[v][i] *= sg;
             im[v][i] *= sg;
         }
     }
 }
 
-// Gradient Im<lam|G|psi> for G on the split bit; each pair counted once (by the lower half).
-template <int KL, int G, typename T>
-__device__ __forceinline__ T xop_grad(T (&re)[2][1 << KL], T (&im)[2][1 << KL], bool hi) {
+// Im<lam|Z|psi> for Z on a lane-resident bit: the lanes with the bit set count negatively.
+template <int KL, typename T>
+__device__ __forceinline__ T xop_gz(T (&re)[2][1 << KL], T (&im)[2][1 << KL], bool hb) {
     T acc = 0;
-    if constexpr (G == OP_GZ) {
 #pragma unroll
-        for (int i = 0; i < (1 << KL); ++i) acc += re[1][i] * im[0][i] - im[1][i] * re[0][i];
-        return hi ? -acc : acc;
-    } else {
-#pragma unroll
-        for (int i = 0; i < (1 << KL); ++i) {
-            T p0r, p1r, p0i, p1i, l0r, l1r, l0i, l1i;
-            halves<T>(re[0][i], p0r, p1r);
-            halves<T>(im[0][i], p0i, p1i);
-            halves<T>(re[1][i], l0r, l1r);
-            halves<T>(im[1][i], l0i, l1i);
-            if constexpr (G == OP_GY)
-                acc += (l1r * p0r + l1i * p0i) - (l0r * p1r + l0i * p1i);
-            else
-                acc += (l0r * p1i - l0i * p1r) + (l1r * p0i - l1i * p0r);
-        }
-        return hi ? T(0) : acc;
-    }
+    for (int i = 0; i < (1 << KL); ++i) acc += re[1][i] * im[0][i] - im[1][i] * re[0][i];
+    return hb ? -acc : acc;
 }
 
 #define VQE_LBIT_CASES(CALL)                                              \
@@ -410,69 +355,48 @@ __device__ __forceinline__ T xop_grad(T (&re)[2][1 << KL], T (&im)[2][1 << KL], 
     case 3: if constexpr (KL > 3) { constexpr int B = 3; CALL; } break;   \
     default: break;
 
-template <int KL, int NV, typename T>
-__device__ __forceinline__ void d_xcnot_tgt(int c, T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
-    switch (c) { VQE_LBIT_CASES((xop_cnot_tgt<KL, B, NV, T>(re, im, hi))) }
-}
-template <int KL, int NV, typename T>
-__device__ __forceinline__ void d_xcnot_ctl(int t, T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
-    switch (t) { VQE_LBIT_CASES((xop_cnot_ctl<KL, B, NV, T>(re, im, hi))) }
-}
-template <int KL, int NV, typename T>
-__device__ __forceinline__ void d_xcz(int b, T (&re)[NV][1 << KL], T (&im)[NV][1 << KL], bool hi) {
-    switch (b) { VQE_LBIT_CASES((xop_cz<KL, B, NV, T>(re, im, hi))) }
-}
-
-// Op loop of the lane-split layout: window bits 0..KL-1 in registers, bit KL
-// across lane halves.
-template <int KL, int NV, typename T>
+// Op loop of the lane-split layout (ops already lowered to physical slots).
+template <int KL, int S, int NV, typename T>
 __device__ __forceinline__ void run_ops_split(const PassArgs<T>& a, T (&re)[NV][1 << KL], T (&im)[NV][1 << KL],
-                                              double* gacc, int tid, bool hi) {
+                                              double* gacc, int tid, int lane) {
+    constexpr int LB0 = (S == 1) ? 5 : 4;
+    const bool h0 = (lane >> LB0) & 1;
+    const bool h1 = (lane >> 5) & 1;
     for (uint32_t o = 0; o < a.n_ops; ++o) {
         const KOp op = a.ops[o];
         const T* m = a.mats[op.slot].v;
-        const bool top_a = op.a == KL;
+        const bool la = op.a >= KL, lb = op.b >= KL;
+        const bool ha = (op.a - KL) == 0 ? h0 : h1;
+        const bool hbb = (op.b - KL) == 0 ? h0 : h1;
         switch (op.type) {
-            case OP_U2:
-                if (top_a) xop_u2<KL, NV, T>(re, im, m, hi, false);
-                else d_u2<KL, NV, T>(op.a, re, im, m);
-                break;
-            case OP_R2:
-                if (top_a) xop_u2<KL, NV, T>(re, im, m, hi, true);
-                else d_r2<KL, NV, T>(op.a, re, im, m);
-                break;
+            case OP_U2: d_u2<KL, NV, T>(op.a, re, im, m); break;
+            case OP_R2: d_r2<KL, NV, T>(op.a, re, im, m); break;
+            case OP_XFLIP: d_xflip<KL, NV, T>(op.a, re, im); break;
+            case OP_CNOT: d_cnot<KL, NV, T>(op.a, op.b, re, im); break;
             case OP_DIAG:
-                if (top_a) xop_diag<KL, NV, T>(re, im, m, hi);
+                if (la) xop_diag<KL, NV, T>(re, im, m, ha);
                 else d_diag<KL, NV, T>(op.a, re, im, m);
                 break;
-            case OP_XFLIP:
-                if (top_a) xop_xflip<KL, NV, T>(re, im, hi);
-                else d_xflip<KL, NV, T>(op.a, re, im);
-                break;
-            case OP_CNOT:
-                if (top_a) d_xcnot_ctl<KL, NV, T>(op.b, re, im, hi);
-                else if (op.b == KL) d_xcnot_tgt<KL, NV, T>(op.a, re, im, hi);
-                else d_cnot<KL, NV, T>(op.a, op.b, re, im);
-                break;
             case OP_CZ:
-                if (top_a) d_xcz<KL, NV, T>(op.b, re, im, hi);
-                else if (op.b == KL) d_xcz<KL, NV, T>(op.a, re, im, hi);
+                if (la && lb) xop_neg<KL, 0, NV, T>(re, im, ha && hbb);
+                else if (la) { switch (op.b) { VQE_LBIT_CASES((xop_neg<KL, (1 << B), NV, T>(re, im, ha))) } }
+                else if (lb) { switch (op.a) { VQE_LBIT_CASES((xop_neg<KL, (1 << B), NV, T>(re, im, hbb))) } }
                 else d_cz<KL, NV, T>(op.a, op.b, re, im);
                 break;
+            case OP_TPOSE:
+                if (op.b == 0) { switch (op.a) { VQE_LBIT_CASES((xop_tpose<LB0, KL, B, NV, T>(re, im))) } }
+                else { if constexpr (S == 2) { switch (op.a) { VQE_LBIT_CASES((xop_tpose<5, KL, B, NV, T>(re, im))) } } }
+                break;
             case OP_GX:
-                if constexpr (NV == 2)
-                    gacc[op.slot * kBlock + tid] +=
-                        (double)(top_a ? xop_grad<KL, OP_GX, T>(re, im, hi) : d_grad<KL, OP_GX, T>(op.a, re, im));
+                if constexpr (NV == 2) gacc[op.slot * kBlock + tid] += (double)d_grad<KL, OP_GX, T>(op.a, re, im);
                 break;
             case OP_GY:
-                if constexpr (NV == 2)
-                    gacc[op.slot * kBlock + tid] +=
-                        (double)(top_a ? xop_grad<KL, OP_GY, T>(re, im, hi) : d_grad<KL, OP_GY, T>(op.a, re, im));
+                if constexpr (NV == 2) gacc[op.slot * kBlock + tid] += (double)d_grad<KL, OP_GY, T>(op.a, re, im);
                 break;
             case OP_GZ:
                 if constexpr (NV == 2)
                     gacc[op.slot * kBlock + tid] +=
-                        (double)(top_a ? xop_grad<KL, OP_GZ, T>(re, im, hi) : d_grad<KL, OP_GZ, T>(op.a, re, im));
+                        (double)(la ? xop_gz<KL, T>(re, im, ha) : d_grad<KL, OP_GZ, T>(op.a, re, im));
                 break;
             default:
                 break;
@@ -578,32 +502,43 @@ window_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t m
     }
 }
 
-// Lane-split direct mode (K >= 2): a wave holds 32 cosets; lane s and s+32
-// hold the halves of coset s split by the top window bit.  Half the registers
-// per thread of the plain direct mode, for windows whose full coset would not
-// fit the register budget (the reverse pass holds psi and lam).
-template <typename T, int K, int NV>
+// Lane-split direct mode: a wave holds 64 >> S cosets, the S top window bits
+// of each coset spread over lane bits (see run_ops_split).  2^S times fewer
+// registers per thread than the plain direct mode, for windows whose full
+// coset would not fit the register budget (the reverse pass holds psi and lam).
+template <typename T, int K, int S, int NV>
 __global__ void __launch_bounds__(kBlock)
 window_split_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t mlog,
                     const typename VecOf<T>::type* __restrict__ in0, typename VecOf<T>::type* __restrict__ out0,
                     const typename VecOf<T>::type* __restrict__ in1, typename VecOf<T>::type* __restrict__ out1,
                     double* __restrict__ gpart) {
     using V = typename VecOf<T>::type;
-    constexpr int KL = K - 1;
+    constexpr int KL = K - S;
     constexpr int N = 1 << KL;
-    constexpr int PER_BLOCK = kBlock / 2;  // cosets per block and iteration
+    constexpr int CPW = 64 >> S;               // cosets per wave
+    constexpr int PER_BLOCK = kBlock >> S;     // cosets per block and iteration
     __shared__ double gacc[NV == 2 ? kMaxGradSlots * kBlock : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const bool hi = lane >= 32;
-    const int sub = (tid >> 6) * 32 + (lane & 31);
+    const int sub = (tid >> 6) * CPW + (lane & (CPW - 1));
     if constexpr (NV == 2) {
         for (uint32_t s = 0; s < a.n_gslots; ++s) gacc[s * kBlock + tid] = 0.0;
     }
-    uint64_t bitval[K];
+    uint64_t bitval[K], bv_in[K], bv_out[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) bitval[j] = 1ull << a.pos[j];
-    const uint64_t half_off = hi ? bitval[KL] : 0;
+    for (int j = 0; j < K; ++j) {
+        bitval[j] = 1ull << a.pos[j];
+        bv_in[j] = 1ull << a.pos_in[j];
+        bv_out[j] = 1ull << a.pos_out[j];
+    }
+    // this lane's values of the lane slots, at load and at store
+    uint64_t half_in = 0, half_out = 0;
+    if constexpr (S == 1) {
+        if ((lane >> 5) & 1) half_in += bv_in[KL], half_out += bv_out[KL];
+    } else {
+        if ((lane >> 4) & 1) half_in += bv_in[KL], half_out += bv_out[KL];
+        if ((lane >> 5) & 1) half_in += bv_in[KL + 1], half_out += bv_out[KL + 1];
+    }
     for (uint32_t it = 0; it < cpt; ++it) {
         const uint64_t blk = xcd_order(
             interleave ? (uint64_t)it * gridDim.x + blockIdx.x : (uint64_t)blockIdx.x * cpt + it, mlog);
@@ -615,15 +550,15 @@ window_split_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint
             const uint64_t low = base & (bitval[j] - 1);
             base = ((base ^ low) << 1) | low;
         }
-        base += half_off;
         T re[NV][N], im[NV][N];
-        uint64_t sbase = base;
+        uint64_t sbase = base + half_out;
+        base += half_in;
 #pragma unroll
         for (int p = 0; p < N; ++p) {
             uint64_t off = 0;
 #pragma unroll
             for (int j = 0; j < KL; ++j)
-                if (p & (1 << j)) off += bitval[j];
+                if (p & (1 << j)) off += bv_in[j];
             const V v0 = in0[base + off];
             re[0][p] = v0.x;
             im[0][p] = v0.y;
@@ -633,14 +568,14 @@ window_split_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint
                 im[NV - 1][p] = v1.y;
             }
         }
-        run_ops_split<KL, NV, T>(a, re, im, gacc, tid, hi);
+        run_ops_split<KL, S, NV, T>(a, re, im, gacc, tid, lane);
         asm volatile("" : "+v"(sbase));
 #pragma unroll
         for (int p = 0; p < N; ++p) {
             uint64_t off = 0;
 #pragma unroll
             for (int j = 0; j < KL; ++j)
-                if (p & (1 << j)) off += bitval[j];
+                if (p & (1 << j)) off += bv_out[j];
             V v0;
             v0.x = re[0][p];
             v0.y = im[0][p];
@@ -1013,18 +948,13 @@ hipError_t launch_copy(int dtype, const void* src, void* dst, uint64_t dim, hipS
 // Launch shape of a window pass.  LDS mode for forward passes whose window
 // includes a lane qubit (< 6), when the state has at least K + 6 qubits.
 struct WinShape {
-    bool lds, split;
+    bool lds;
+    int split;  // lane-split bits S (0: plain direct or LDS mode)
     LdsMap m;
     uint32_t cpt, grid, interleave, mlog;
 };
 
-// Lane-split layout where a full 5-qubit coset does not fit the register
-// budget at useful occupancy: the reverse pass (psi and lam) of both
-// precisions and the complex128 forward pass.
-template <typename T>
-bool use_split(int K, bool two_vectors) {
-    return K == 5 && (two_vectors || sizeof(T) == 8);
-}
+
 
 // Reverse passes (with per-block gradient partials) use a persistent grid of
 // at most kRevBlocks blocks; forward passes a one-shot grid.
@@ -1048,7 +978,7 @@ template <typename T>
 WinShape window_shape(const PassArgs<T>& a, int n, bool with_partials) {
     WinShape w{};
     const int K = (int)a.K;
-    w.split = use_split<T>(K, with_partials);
+    w.split = (int)a.split;
     bool low = false;
     for (int j = 0; j < K; ++j) low |= a.pos[j] < 6;
     // Measured on MI355X: staging pays for forward passes (one vector) but
@@ -1083,7 +1013,7 @@ WinShape window_shape(const PassArgs<T>& a, int n, bool with_partials) {
         return w;
     }
     w.lds = false;
-    const uint64_t per_unit = w.split ? kBlock / 2 : kBlock;
+    const uint64_t per_unit = (uint64_t)kBlock >> w.split;
     grid_for_units((a.n_cosets + per_unit - 1) / per_unit, with_partials, w);
     return w;
 }
@@ -1104,10 +1034,14 @@ hipError_t launch_window(const PassArgs<T>& a, int n, const void* in0, void* out
     V* o1 = (V*)out1;
 #define VQE_WIN(KK)                                                                                      \
     case KK:                                                                                             \
-        if (w.split) {                                                                                   \
+        if (w.split == 1) {                                                                              \
             if constexpr (KK == 5)                                                                       \
-                hipLaunchKernelGGL((window_split_kernel<T, KK, NV>), dim3(w.grid), dim3(kBlock), 0, st, a, \
-                                   w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);                  \
+                hipLaunchKernelGGL((window_split_kernel<T, KK, 1, NV>), dim3(w.grid), dim3(kBlock), 0, st, \
+                                   a, w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);               \
+        } else if (w.split == 2) {                                                                       \
+            if constexpr (KK == 5)                                                                       \
+                hipLaunchKernelGGL((window_split_kernel<T, KK, 2, NV>), dim3(w.grid), dim3(kBlock), 0, st, \
+                                   a, w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);               \
         } else if (w.lds)                                                                                \
             hipLaunchKernelGGL((window_lds_kernel<T, KK, NV>), dim3(w.grid), dim3(kBlock), 0, st, a, w.m, \
                                w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);                      \

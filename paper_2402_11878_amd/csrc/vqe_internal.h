@@ -16,7 +16,8 @@ namespace vqe {
 constexpr int kMaxWindow = 5;     // qubits fused per pass (2^5 amplitudes per thread)
 constexpr int kWindowC64 = 5;     // window used for complex64 states
 constexpr int kWindowC128 = 5;    // window used for complex128 states
-constexpr int kMaxOps = 64;       // kernel ops per pass
+constexpr int kMaxOps = 64;       // logical kernel ops per pass (planner limit)
+constexpr int kMaxPhysOps = 160;  // ops per pass after inserting lane transposes
 constexpr int kMaxMats = 32;      // 2x2 matrices per pass
 constexpr int kMaxGradSlots = 16; // parameterised gates per pass
 constexpr int kBlock = 256;       // threads per block of every streaming kernel
@@ -36,6 +37,7 @@ enum OpType : uint8_t {
     OP_GX = 6,    // gradient slot += Im<lam| X_a |psi>
     OP_GY = 7,    // gradient slot += Im<lam| Y_a |psi>
     OP_GZ = 8,    // gradient slot += Im<lam| Z_a |psi>
+    OP_TPOSE = 9, // lane-split layout: swap the roles of register bit a and lane slot b
 };
 
 struct KOp {
@@ -54,10 +56,24 @@ struct PassArgs {
     uint32_t K;
     uint32_t n_ops;
     uint32_t n_gslots;
+    uint32_t split;            // lane-split bits S (0: every window bit in registers)
     uint32_t pos[kMaxWindow];  // window qubits, ascending
-    KOp ops[kMaxOps];
+    // Lane-split layout: qubit held by physical slot s at load / at store
+    // (slots 0..K-S-1 are register bits, K-S.. lane slots).
+    uint32_t pos_in[kMaxWindow];
+    uint32_t pos_out[kMaxWindow];
+    KOp ops[kMaxPhysOps];
     Mat2<T> mats[kMaxMats];
 };
+
+// Lane-split bits of a window pass, chosen so that the coset held per thread
+// (two vectors in the reverse pass) fits the register budget at >= 3 waves
+// per SIMD: 5-qubit windows split 0 (complex64 forward), 1 (complex64
+// reverse, complex128 forward) or 2 (complex128 reverse) bits.
+inline int split_bits_for(bool is_double, int K, bool two_vectors) {
+    if (K != 5) return 0;
+    return (is_double ? 1 : 0) + (two_vectors ? 1 : 0);
+}
 
 // ---------------------------------------------------------------- Hamiltonian tables
 // Terms grouped by x mask.  For group g, terms [begin, end) carry z masks and
