@@ -246,6 +246,29 @@ int vqe_profile_enable(int on);
 int vqe_profile_reset(void);
 int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* bytes);
 
+/* ------------------------------------------------------------------ kernel form
+ * Window passes of the ansatz (eq. 6) and of the adjoint sweep run either as
+ * interpreted kernels (one compiled kernel per window size that reads the
+ * pass's op list at run time) or as specialised kernels: straight-line code
+ * generated for each distinct op list and compiled at run time (hiprtc,
+ * gfx950) the first time a circuit runs on a device, then cached for the
+ * process.  Both compute the same pass; specialised kernels spend no
+ * instructions on op dispatch or on permutation gates (CNOT, X), which
+ * matters when a pass is bound by vector instructions.
+ *   VQE_SPECIALIZE_NEVER   interpreted kernels only
+ *   VQE_SPECIALIZE_AUTO    specialised kernels for circuits of at least
+ *                          VQE_SPECIALIZE_AUTO_MIN_QUBITS qubits (default)
+ *   VQE_SPECIALIZE_ALWAYS  specialised kernels for every circuit
+ * Process-wide; takes effect at the next evaluation of a circuit.  Returns
+ * the previous mode, or VQE_ERR_ARG for an unknown mode.  A specialised
+ * kernel that fails to compile or load makes the evaluation fail with
+ * VQE_ERR_STATE / VQE_ERR_DEVICE (message in vqe_last_error). */
+#define VQE_SPECIALIZE_NEVER   0
+#define VQE_SPECIALIZE_AUTO    1
+#define VQE_SPECIALIZE_ALWAYS  2
+#define VQE_SPECIALIZE_AUTO_MIN_QUBITS 20
+int vqe_set_specialize(int mode);
+
 /* ------------------------------------------------------------------ slimming
  * Hamiltonian cutoff (Sec. II-D; terms sorted by |w|, small ones dropped).
  * Host only.  The identity term (x = z = 0) is always kept.  The order of

@@ -78,6 +78,7 @@ _SIGS = {
     "vqe_batch_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "vqe_batch_free": (C.c_int, [_P]),
     "vqe_batch_energy_grad": (C.c_int, [_P, _SZ, C.POINTER(vqe_batch_item)]),
+    "vqe_set_specialize": (C.c_int, [C.c_int]),
     "vqe_profile_enable": (C.c_int, [C.c_int]),
     "vqe_profile_reset": (C.c_int, []),
     "vqe_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -247,6 +248,18 @@ def vqe_slim_hamiltonian(x, z, w, mode, value):
         xp, zp, wp, len(w), mode, float(value), keep.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(nk),
         C.byref(dropped)))
     return keep, nk.value, dropped.value
+
+
+SPECIALIZE_NEVER, SPECIALIZE_AUTO, SPECIALIZE_ALWAYS = 0, 1, 2
+SPECIALIZE_AUTO_MIN_QUBITS = 20
+
+
+def vqe_set_specialize(mode):
+    """Kernel form of window passes (interpreted / specialised); returns the previous mode."""
+    r = lib().vqe_set_specialize(int(mode))
+    if r < 0:
+        check("vqe_set_specialize", r)
+    return r
 
 
 def vqe_profile_enable(on=True):

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libvqe.so")
-SOURCES = ["kernels.hip", "batch.hip", "api.cpp", "plan.cpp", "slim.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "api.cpp", "plan.cpp", "slim.cpp", "jit.cpp"]
 ARCH = "gfx950"
 
 
@@ -64,7 +64,7 @@ def build(verbose: bool = False) -> str:
         msg = "\n".join(f"--- {s}\n{t}" for s, t in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
     tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lhiprtc", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)

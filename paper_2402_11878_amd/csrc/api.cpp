@@ -76,6 +76,10 @@ struct Plan {
     std::vector<int32_t> slotmap;   // all passes' gradient slot -> parameter maps
     int32_t* d_slotmap = nullptr;   // uploaded on first use on a device
     std::vector<size_t> slot_off;
+    // Specialised kernels per pass ([0] forward, [1] reverse; nullptr where the
+    // pass runs interpreted), built on first use on device jit_dev.
+    std::vector<void*> jit[2];
+    int jit_dev = -1;
 };
 
 struct vqe_circuit {
@@ -84,9 +88,7 @@ struct vqe_circuit {
     size_t n_params = 0;
     std::vector<BatchGate> bgates;  // gate table of the batched small-state kernel
     uint32_t n_mats = 0;            // matrices per evaluation (gates with a 2x2 matrix)
-    Plan plan[2];  // [0]: kWindowC64-qubit windows, [1]: kWindowC128-qubit windows
-    // The reverse kernel holds psi and lam: 2 x 2^K amplitudes per thread.
-    // complex64 fits 5-qubit windows in the register budget, complex128 4.
+    Plan plan[2];  // [0]: complex64 (kWindowC64-qubit windows), [1]: complex128 (kWindowC128)
     const Plan& for_dtype(int dtype) const { return plan[dtype == VQE_C64 ? 0 : 1]; }
 };
 
@@ -332,6 +334,7 @@ void build_args(const vqe_circuit* c, const Plan& pl, size_t pi, const double* p
         const auto& ops = reverse ? po.rev : po.fwd;
         a.n_ops = (uint32_t)ops.size();
         for (size_t i = 0; i < ops.size(); ++i) a.ops[i] = ops[i];
+        for (int sl = 0; sl < p.K; ++sl) a.pos_in[sl] = a.pos_out[sl] = (uint32_t)p.pos[sl];
     } else {
         const SplitOps& so = reverse ? po.rev_split[S] : po.fwd_split[S];
         a.n_ops = (uint32_t)so.ops.size();
@@ -374,12 +377,63 @@ int check_params(const vqe_circuit* c, const double* params, size_t n_params, co
     return VQE_OK;
 }
 
+std::mutex g_jit_plan_mu;
+
+// Specialised kernels of every pass of a plan (see vqe_set_specialize), built
+// on the first evaluation on the current device.  *fwd / *rev stay null when
+// the interpreted kernels are to run.
+template <typename T>
+int ensure_jit(const vqe_circuit* c, const Plan& cpl, const std::vector<void*>** fwd,
+               const std::vector<void*>** rev) {
+    *fwd = *rev = nullptr;
+    const int mode = jit_mode();
+    if (mode == VQE_SPECIALIZE_NEVER || (mode == VQE_SPECIALIZE_AUTO && c->n < VQE_SPECIALIZE_AUTO_MIN_QUBITS))
+        return VQE_OK;
+    Plan& pl = const_cast<Plan&>(cpl);
+    int dev = 0;
+    VQE_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_jit_plan_mu);
+    const size_t P = pl.passes.size();
+    if (pl.jit_dev != dev || pl.jit[0].size() != P) {
+        std::vector<std::string> srcs(2 * P);
+        std::vector<double> zeros(c->n_params + 1, 0.0);
+        PassArgs<T> a;
+        for (size_t pi = 0; pi < P; ++pi)
+            for (int dir = 0; dir < 2; ++dir) {
+                build_args<T>(c, pl, pi, zeros.data(), dir == 1, a);
+                if (window_uses_lds<T>(a, c->n, dir == 1)) continue;
+                srcs[2 * pi + dir] = jit_source(sizeof(T) == 8, (int)a.K, (int)a.split, dir == 1 ? 2 : 1,
+                                                std::vector<KOp>(a.ops, a.ops + a.n_ops), a.n_gslots);
+            }
+        std::vector<void*> fns;
+        std::string err;
+        const int rc = jit_prepare(srcs, fns, err);
+        if (rc) {
+            set_error(err);
+            return rc;
+        }
+        pl.jit[0].assign(P, nullptr);
+        pl.jit[1].assign(P, nullptr);
+        for (size_t pi = 0; pi < P; ++pi) {
+            pl.jit[0][pi] = fns[2 * pi];
+            pl.jit[1][pi] = fns[2 * pi + 1];
+        }
+        pl.jit_dev = dev;
+    }
+    *fwd = &pl.jit[0];
+    *rev = &pl.jit[1];
+    return VQE_OK;
+}
+
 // Forward passes from |b0> (or in place on the current state when reset is false).
 // ckpt_ptr[k] receives the state at boundary bounds[k] (pass index + 1).
 template <typename T>
 int forward(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* params,
             const std::vector<size_t>& bounds, const std::vector<void*>& ckpt_ptr) {
     void* cur = s->data;
+    const std::vector<void*>*jf = nullptr, *jr = nullptr;
+    const int rc = ensure_jit<T>(c, pl, &jf, &jr);
+    if (rc) return rc;
     PassArgs<T> a;
     for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
         void* out = s->data;
@@ -387,7 +441,7 @@ int forward(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* pa
             if (bounds[k] == pi + 1) out = ckpt_ptr[k];
         build_args<T>(c, pl, pi, params, false, a);
         ProfScope ps(VQE_KERNEL_WINDOW_FWD, 2.0 * (double)s->bytes, s->stream);
-        VQE_HIP(launch_window_fwd<T>(a, s->n, cur, out, s->stream));
+        VQE_HIP(launch_window_fwd<T>(a, s->n, cur, out, jf ? (*jf)[pi] : nullptr, s->stream));
         ps.end();
         cur = out;
     }
@@ -511,6 +565,9 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
     }
     VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, d_e, 0, st));
     VQE_HIP(launch_zero(d_g, c->n_params, st));
+    const std::vector<void*>*jf = nullptr, *jr = nullptr;
+    rc = ensure_jit<T>(c, pl, &jf, &jr);
+    if (rc) return rc;
     PassArgs<T> a;
     for (size_t pi = P; pi-- > 0;) {
         const void* pin = psi->data;
@@ -519,7 +576,8 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
         build_args<T>(c, pl, pi, params, true, a);
         uint32_t gb = 0;
         ProfScope ps(VQE_KERNEL_WINDOW_REV, 4.0 * (double)psi->bytes, st);
-        VQE_HIP(launch_window_rev<T>(a, psi->n, pin, psi->data, lam->data, lam->data, psi->d_part, &gb, st));
+        VQE_HIP(launch_window_rev<T>(a, psi->n, pin, psi->data, lam->data, lam->data, psi->d_part, &gb,
+                                     jr ? (*jr)[pi] : nullptr, st));
         ps.end();
         if (a.n_gslots)
             VQE_HIP(launch_reduce(psi->d_part, gb, a.n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, 1, st));
@@ -1343,6 +1401,14 @@ int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* it
     VQE_HIP(hipSetDevice(b->device));
     return b->dtype == VQE_C64 ? batch_impl<float>(b, n_items, items) : batch_impl<double>(b, n_items, items);
     VQE_GUARD_END
+}
+
+int vqe_set_specialize(int mode) {
+    if (mode != VQE_SPECIALIZE_NEVER && mode != VQE_SPECIALIZE_AUTO && mode != VQE_SPECIALIZE_ALWAYS) {
+        vqe::set_error("vqe_set_specialize: unknown mode");
+        return VQE_ERR_ARG;
+    }
+    return vqe::jit_set_mode(mode);
 }
 
 int vqe_profile_enable(int on) {

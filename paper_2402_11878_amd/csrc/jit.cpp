@@ -1,0 +1,389 @@
+// Specialised window pass kernels, generated per op list and compiled at run
+// time with hiprtc for gfx950.
+//
+// The interpreted window kernels (kernels.hip) read each op from the pass
+// arguments and branch on its type and bits.  Every branch writes the whole
+// register-resident coset, so the compiler merges the branches through copies
+// of the full coset: on complex128 reverse passes about two thirds of the
+// vector instructions are such moves and the pass is VALU-bound.  A generated
+// kernel instead spells out the pass as straight-line code with every bit a
+// constant:
+//   * permutation ops (CNOT, Pauli X) only rename registers at generation
+//     time and cost no instruction;
+//   * 2x2 ops, phases and gradient terms are written per register pair with
+//     the pair indices known;
+//   * lane-split transposes are single permlane swaps on named registers.
+// Window positions and matrices stay kernel arguments (the same PassArgs as
+// the interpreted kernels), so passes with equal op lists share one kernel.
+// The load/store addressing, work order, grid and gradient reduction are the
+// interpreted kernels', so both forms give the same results up to rounding
+// of fused multiply-adds.
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <thread>
+
+#include "vqe_internal.h"
+
+namespace vqe {
+namespace {
+
+std::atomic<int> g_mode{VQE_SPECIALIZE_AUTO};
+
+struct Entry {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+};
+std::mutex g_mu;
+std::map<std::pair<int, std::string>, Entry> g_cache;  // (device, source) -> loaded kernel
+
+// Text of the kernel argument types; must match PassArgs / Mat2 / KOp.
+std::string prelude(bool dbl) {
+    const char* T = dbl ? "double" : "float";
+    std::ostringstream o;
+    o << "typedef unsigned long long u64;\ntypedef unsigned int u32;\n"
+      << "typedef " << T << " T;\n"
+      << "struct KOp { unsigned char type, a, b, slot; };\n"
+      << "struct Mat2 { T v[8]; };\n"
+      << "struct PassArgs { u64 n_cosets; u32 K, n_ops, n_gslots, split; u32 pos[" << kMaxWindow << "]; u32 pos_in["
+      << kMaxWindow << "]; u32 pos_out[" << kMaxWindow << "]; KOp ops[" << kMaxPhysOps << "]; Mat2 mats["
+      << kMaxMats << "]; };\n"
+      << "struct __attribute__((aligned(" << (dbl ? 16 : 8) << "))) V { T x, y; };\n"
+      << "__device__ __forceinline__ u64 xcd_order(u64 u, u32 m) {\n"
+      << "  if (m < 3) return u;\n  return (u >> 3) | ((u & 7ull) << (m - 3));\n}\n";
+    // lane transposes: (a, b) -> (a_lo | b_lo, a_hi | b_hi) over the lane bit
+    o << "template <int LB> __device__ __forceinline__ void tp32(u32& a, u32& b) {\n"
+      << "  if constexpr (LB == 5) { const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false); a = r[0]; b = r[1]; }\n"
+      << "  else { const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false); a = r[0]; b = r[1]; }\n}\n";
+    if (dbl)
+        o << "template <int LB> __device__ __forceinline__ void tp(T& a, T& b) {\n"
+          << "  u64 x = __builtin_bit_cast(u64, a), y = __builtin_bit_cast(u64, b);\n"
+          << "  u32 xl = (u32)x, xh = (u32)(x >> 32), yl = (u32)y, yh = (u32)(y >> 32);\n"
+          << "  tp32<LB>(xl, yl); tp32<LB>(xh, yh);\n"
+          << "  a = __builtin_bit_cast(T, ((u64)xh << 32) | xl); b = __builtin_bit_cast(T, ((u64)yh << 32) | yl);\n}\n";
+    else
+        o << "template <int LB> __device__ __forceinline__ void tp(T& a, T& b) {\n"
+          << "  u32 x = __builtin_bit_cast(u32, a), y = __builtin_bit_cast(u32, b);\n"
+          << "  tp32<LB>(x, y);\n  a = __builtin_bit_cast(T, x); b = __builtin_bit_cast(T, y);\n}\n";
+    return o.str();
+}
+
+// Straight-line body generator.  loc[p] = variable holding register entry p.
+struct Gen {
+    int K, S, NV, KL, N;
+    std::vector<int> loc;
+    std::ostringstream o;
+    std::string R(int v, int p) const { return "r" + std::to_string(v) + "_" + std::to_string(loc[p]); }
+    std::string I(int v, int p) const { return "i" + std::to_string(v) + "_" + std::to_string(loc[p]); }
+    std::string H(int lane_slot) const { return lane_slot == 0 ? "h0" : "h1"; }
+    int lane_bit(int lane_slot) const { return (S == 1 || lane_slot == 1) ? 5 : 4; }
+
+    void mats(int s, bool all) {
+        o << "  { const T* m = a.mats[" << s << "].v;\n";
+        if (all)
+            o << "    const T m0r = m[0], m0i = m[1], m1r = m[2], m1i = m[3], m2r = m[4], m2i = m[5], m3r = m[6], "
+                 "m3i = m[7];\n";
+    }
+
+    void op(const KOp& k) {
+        const int A = k.a, B = k.b;
+        const bool la = A >= KL, lb = B >= KL;
+        switch (k.type) {
+            case OP_U2:
+                mats(k.slot, true);
+                for (int p = 0; p < N; ++p) {
+                    if (p & (1 << A)) continue;
+                    const int q = p | (1 << A);
+                    for (int v = 0; v < NV; ++v) {
+                        o << "    { const T ar = " << R(v, p) << ", ai = " << I(v, p) << ", br = " << R(v, q)
+                          << ", bi = " << I(v, q) << ";\n"
+                          << "      " << R(v, p) << " = m0r * ar - m0i * ai + m1r * br - m1i * bi;\n"
+                          << "      " << I(v, p) << " = m0r * ai + m0i * ar + m1r * bi + m1i * br;\n"
+                          << "      " << R(v, q) << " = m2r * ar - m2i * ai + m3r * br - m3i * bi;\n"
+                          << "      " << I(v, q) << " = m2r * ai + m2i * ar + m3r * bi + m3i * br; }\n";
+                    }
+                }
+                o << "  }\n";
+                break;
+            case OP_R2:
+                mats(k.slot, false);
+                o << "    const T ca = m[0], cb = m[2], cc = m[4], cd = m[6];\n";
+                for (int p = 0; p < N; ++p) {
+                    if (p & (1 << A)) continue;
+                    const int q = p | (1 << A);
+                    for (int v = 0; v < NV; ++v) {
+                        o << "    { const T ar = " << R(v, p) << ", ai = " << I(v, p) << ", br = " << R(v, q)
+                          << ", bi = " << I(v, q) << ";\n"
+                          << "      " << R(v, p) << " = ca * ar + cb * br; " << I(v, p) << " = ca * ai + cb * bi;\n"
+                          << "      " << R(v, q) << " = cc * ar + cd * br; " << I(v, q) << " = cc * ai + cd * bi; }\n";
+                    }
+                }
+                o << "  }\n";
+                break;
+            case OP_DIAG:
+                mats(k.slot, false);
+                if (la)
+                    o << "    const T p0r = " << H(A - KL) << " ? m[6] : m[0], p0i = " << H(A - KL)
+                      << " ? m[7] : m[1];\n";
+                else
+                    o << "    const T p0r = m[0], p0i = m[1], p1r = m[6], p1i = m[7];\n";
+                for (int p = 0; p < N; ++p) {
+                    const char* pr = (!la && (p & (1 << A))) ? "p1r" : "p0r";
+                    const char* pi = (!la && (p & (1 << A))) ? "p1i" : "p0i";
+                    for (int v = 0; v < NV; ++v)
+                        o << "    { const T ar = " << R(v, p) << ", ai = " << I(v, p) << "; " << R(v, p) << " = "
+                          << pr << " * ar - " << pi << " * ai; " << I(v, p) << " = " << pr << " * ai + " << pi
+                          << " * ar; }\n";
+                }
+                o << "  }\n";
+                break;
+            case OP_CNOT:
+                // control A, target B, both register bits: rename
+                for (int p = 0; p < N; ++p)
+                    if ((p & (1 << A)) && !(p & (1 << B))) std::swap(loc[p], loc[p | (1 << B)]);
+                break;
+            case OP_XFLIP:
+                for (int p = 0; p < N; ++p)
+                    if (!(p & (1 << A))) std::swap(loc[p], loc[p | (1 << A)]);
+                break;
+            case OP_CZ: {
+                if (la && lb) {
+                    o << "  { const T sg = (" << H(A - KL) << " && " << H(B - KL) << ") ? T(-1) : T(1);\n";
+                    for (int p = 0; p < N; ++p)
+                        for (int v = 0; v < NV; ++v)
+                            o << "    " << R(v, p) << " *= sg; " << I(v, p) << " *= sg;\n";
+                    o << "  }\n";
+                } else if (la || lb) {
+                    const int rb = la ? B : A;
+                    const int ls = la ? A - KL : B - KL;
+                    o << "  { const T sg = " << H(ls) << " ? T(-1) : T(1);\n";
+                    for (int p = 0; p < N; ++p)
+                        if (p & (1 << rb))
+                            for (int v = 0; v < NV; ++v)
+                                o << "    " << R(v, p) << " *= sg; " << I(v, p) << " *= sg;\n";
+                    o << "  }\n";
+                } else {
+                    for (int p = 0; p < N; ++p)
+                        if ((p & (1 << A)) && (p & (1 << B)))
+                            for (int v = 0; v < NV; ++v)
+                                o << "  " << R(v, p) << " = -" << R(v, p) << "; " << I(v, p) << " = -" << I(v, p)
+                                  << ";\n";
+                }
+                break;
+            }
+            case OP_TPOSE: {
+                const int lb_ = lane_bit(B);
+                for (int p = 0; p < N; ++p) {
+                    if (p & (1 << A)) continue;
+                    const int q = p | (1 << A);
+                    for (int v = 0; v < NV; ++v)
+                        o << "  tp<" << lb_ << ">(" << R(v, p) << ", " << R(v, q) << "); tp<" << lb_ << ">(" << I(v, p)
+                          << ", " << I(v, q) << ");\n";
+                }
+                break;
+            }
+            case OP_GX:
+            case OP_GY:
+            case OP_GZ: {
+                if (NV != 2) break;
+                o << "  { T acc = 0;\n";
+                if (k.type == OP_GZ && la) {
+                    for (int p = 0; p < N; ++p)
+                        o << "    acc += " << R(1, p) << " * " << I(0, p) << " - " << I(1, p) << " * " << R(0, p)
+                          << ";\n";
+                    o << "    g" << (int)k.slot << " += (double)(" << H(A - KL) << " ? -acc : acc); }\n";
+                    break;
+                }
+                for (int p = 0; p < N; ++p) {
+                    if (p & (1 << A)) continue;
+                    const int q = p | (1 << A);
+                    const std::string p0r = R(0, p), p0i = I(0, p), p1r = R(0, q), p1i = I(0, q);
+                    const std::string l0r = R(1, p), l0i = I(1, p), l1r = R(1, q), l1i = I(1, q);
+                    if (k.type == OP_GZ)
+                        o << "    acc += (" << l0r << " * " << p0i << " - " << l0i << " * " << p0r << ") - (" << l1r
+                          << " * " << p1i << " - " << l1i << " * " << p1r << ");\n";
+                    else if (k.type == OP_GY)
+                        o << "    acc += (" << l1r << " * " << p0r << " + " << l1i << " * " << p0i << ") - (" << l0r
+                          << " * " << p1r << " + " << l0i << " * " << p1i << ");\n";
+                    else
+                        o << "    acc += (" << l0r << " * " << p1i << " - " << l0i << " * " << p1r << ") + (" << l1r
+                          << " * " << p0i << " - " << l1i << " * " << p0r << ");\n";
+                }
+                o << "    g" << (int)k.slot << " += (double)acc; }\n";
+                break;
+            }
+            default:
+                break;
+        }
+    }
+};
+
+std::string offset_expr(const char* arr, int p, int KL) {
+    std::string e;
+    for (int j = 0; j < KL; ++j)
+        if (p & (1 << j)) e += (e.empty() ? "" : " + ") + std::string(arr) + "[" + std::to_string(j) + "]";
+    return e.empty() ? "0" : e;
+}
+
+bool compile(const std::string& src, std::vector<char>& code, std::string& log) {
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "vqe_pass.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+        log = "hiprtcCreateProgram failed";
+        return false;
+    }
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=fast",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    log.assign(ls, '\0');
+    if (ls) hiprtcGetProgramLog(prog, &log[0]);
+    bool ok = r == HIPRTC_SUCCESS;
+    if (ok) {
+        size_t cs = 0;
+        ok = hiprtcGetCodeSize(prog, &cs) == HIPRTC_SUCCESS && cs > 0;
+        if (ok) {
+            code.resize(cs);
+            ok = hiprtcGetCode(prog, code.data()) == HIPRTC_SUCCESS;
+        }
+    }
+    hiprtcDestroyProgram(&prog);
+    return ok;
+}
+
+}  // namespace
+
+int jit_mode() { return g_mode.load(); }
+
+int jit_set_mode(int mode) { return g_mode.exchange(mode); }
+
+std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& ops, uint32_t n_gslots) {
+    Gen g;
+    g.K = K;
+    g.S = S;
+    g.NV = NV;
+    g.KL = K - S;
+    g.N = 1 << g.KL;
+    g.loc.resize(g.N);
+    for (int p = 0; p < g.N; ++p) g.loc[p] = p;
+    const int CPW = 64 >> S, PER_BLOCK = kBlock >> S;
+    std::ostringstream& o = g.o;
+    o << prelude(dbl);
+    o << "extern \"C\" __global__ void __launch_bounds__(" << kBlock << ")\n"
+      << "vqe_pass(const PassArgs a, u32 cpt, u32 interleave, u32 mlog, const V* __restrict__ in0, V* __restrict__ "
+         "out0, const V* __restrict__ in1, V* __restrict__ out1, double* __restrict__ gpart) {\n"
+      << "  const int tid = threadIdx.x;\n  const int lane = tid & 63;\n"
+      << "  const int sub = (tid >> 6) * " << CPW << " + (lane & " << (CPW - 1) << ");\n"
+      << "  const bool h0 = (lane >> " << (S == 1 ? 5 : 4) << ") & 1, h1 = (lane >> 5) & 1;\n"
+      << "  (void)h0; (void)h1;\n"
+      << "  u64 bitval[" << K << "], bv_in[" << K << "], bv_out[" << K << "];\n"
+      << "#pragma unroll\n  for (int j = 0; j < " << K
+      << "; ++j) { bitval[j] = 1ull << a.pos[j]; bv_in[j] = 1ull << a.pos_in[j]; bv_out[j] = 1ull << a.pos_out[j]; }\n"
+      << "  u64 half_in = 0, half_out = 0;\n";
+    for (int j = 0; j < S; ++j)
+        o << "  if (" << (j == 0 ? "h0" : "h1") << ") { half_in += bv_in[" << g.KL + j << "]; half_out += bv_out["
+          << g.KL + j << "]; }\n";
+    for (uint32_t s = 0; s < n_gslots; ++s) o << "  double g" << s << " = 0.0;\n";
+    o << "  for (u32 it = 0; it < cpt; ++it) {\n"
+      << "    const u64 blk = xcd_order(interleave ? (u64)it * gridDim.x + blockIdx.x : (u64)blockIdx.x * cpt + it, "
+         "mlog);\n"
+      << "    const u64 c = blk * " << PER_BLOCK << " + sub;\n"
+      << "    if (c >= a.n_cosets) break;\n"
+      << "    u64 base = c;\n"
+      << "#pragma unroll\n    for (int j = 0; j < " << K
+      << "; ++j) { const u64 low = base & (bitval[j] - 1); base = ((base ^ low) << 1) | low; }\n"
+      << "    u64 sbase = base + half_out;\n    base += half_in;\n";
+    for (int p = 0; p < g.N; ++p) {
+        for (int v = 0; v < NV; ++v)
+            o << "    const V l" << v << "_" << p << " = in" << v << "[base + " << offset_expr("bv_in", p, g.KL)
+              << "];\n";
+    }
+    for (int p = 0; p < g.N; ++p)
+        for (int v = 0; v < NV; ++v)
+            o << "    T r" << v << "_" << p << " = l" << v << "_" << p << ".x, i" << v << "_" << p << " = l" << v << "_"
+              << p << ".y;\n";
+    for (const KOp& k : ops) g.op(k);
+    o << "    asm volatile(\"\" : \"+v\"(sbase));\n";
+    for (int p = 0; p < g.N; ++p)
+        for (int v = 0; v < NV; ++v)
+            o << "    out" << v << "[sbase + " << offset_expr("bv_out", p, g.KL) << "] = V{" << g.R(v, p) << ", "
+              << g.I(v, p) << "};\n";
+    o << "  }\n";
+    if (NV == 2 && n_gslots) {
+        // fixed-tree block reduction of every gradient slot (same order as the interpreted kernels)
+        o << "  __shared__ double gacc[" << n_gslots * kBlock << "];\n";
+        for (uint32_t s = 0; s < n_gslots; ++s) o << "  gacc[" << s * kBlock << " + tid] = g" << s << ";\n";
+        o << "  __syncthreads();\n"
+          << "  for (int w = " << kBlock / 2 << "; w > 0; w >>= 1) {\n"
+          << "    if (tid < w) {\n";
+        for (uint32_t s = 0; s < n_gslots; ++s)
+            o << "      gacc[" << s * kBlock << " + tid] += gacc[" << s * kBlock << " + tid + w];\n";
+        o << "    }\n    __syncthreads();\n  }\n"
+          << "  if (tid < " << n_gslots << ") gpart[(u64)blockIdx.x * " << n_gslots << " + tid] = gacc[tid * "
+          << kBlock << "];\n";
+    }
+    o << "}\n";
+    return o.str();
+}
+
+int jit_prepare(const std::vector<std::string>& srcs, std::vector<void*>& fns, std::string& err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "no HIP device for specialised kernels";
+        return VQE_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    // unique sources not yet loaded on this device
+    std::vector<const std::string*> todo;
+    {
+        std::map<std::string, int> seen;
+        for (const auto& s : srcs)
+            if (!s.empty() && !g_cache.count({dev, s}) && !seen.count(s)) {
+                seen[s] = 1;
+                todo.push_back(&s);
+            }
+    }
+    std::vector<std::vector<char>> codes(todo.size());
+    std::vector<std::string> logs(todo.size());
+    std::vector<char> ok(todo.size(), 0);
+    if (!todo.empty()) {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const size_t nt = std::min<size_t>(todo.size(), std::min(16u, hw));
+        std::atomic<size_t> next{0};
+        auto work = [&]() {
+            for (size_t i; (i = next.fetch_add(1)) < todo.size();) ok[i] = compile(*todo[i], codes[i], logs[i]);
+        };
+        std::vector<std::thread> th;
+        for (size_t t = 1; t < nt; ++t) th.emplace_back(work);
+        work();
+        for (auto& t : th) t.join();
+    }
+    for (size_t i = 0; i < todo.size(); ++i) {
+        if (!ok[i]) {
+            err = "specialised pass kernel failed to compile: " + logs[i].substr(0, 2000);
+            return VQE_ERR_STATE;
+        }
+        Entry e;
+        if (hipModuleLoadData(&e.mod, codes[i].data()) != hipSuccess ||
+            hipModuleGetFunction(&e.fn, e.mod, "vqe_pass") != hipSuccess) {
+            err = "loading a specialised pass kernel failed";
+            return VQE_ERR_DEVICE;
+        }
+        g_cache[{dev, *todo[i]}] = e;
+    }
+    fns.assign(srcs.size(), nullptr);
+    for (size_t i = 0; i < srcs.size(); ++i)
+        if (!srcs[i].empty()) fns[i] = (void*)g_cache[{dev, srcs[i]}].fn;
+    return VQE_OK;
+}
+
+size_t jit_cached() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_cache.size();
+}
+
+}  // namespace vqe

@@ -1025,13 +1025,19 @@ uint32_t window_blocks(const PassArgs<T>& a, int n, bool with_partials) {
 
 template <typename T, int NV>
 hipError_t launch_window(const PassArgs<T>& a, int n, const void* in0, void* out0, const void* in1, void* out1,
-                         double* gpart, hipStream_t st) {
+                         double* gpart, void* jit, hipStream_t st) {
     using V = typename VecOf<T>::type;
     const WinShape w = window_shape<T>(a, n, NV == 2);
     const V* i0 = (const V*)in0;
     V* o0 = (V*)out0;
     const V* i1 = (const V*)in1;
     V* o1 = (V*)out1;
+    if (jit && !w.lds) {
+        PassArgs<T> ka = a;
+        uint32_t cpt = w.cpt, interleave = w.interleave, mlog = w.mlog;
+        void* params[] = {&ka, &cpt, &interleave, &mlog, (void*)&i0, (void*)&o0, (void*)&i1, (void*)&o1, &gpart};
+        return hipModuleLaunchKernel((hipFunction_t)jit, w.grid, 1, 1, kBlock, 1, 1, 0, st, params, nullptr);
+    }
 #define VQE_WIN(KK)                                                                                      \
     case KK:                                                                                             \
         if (w.split == 1) {                                                                              \
@@ -1063,15 +1069,20 @@ hipError_t launch_window(const PassArgs<T>& a, int n, const void* in0, void* out
 }
 
 template <typename T>
-hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, hipStream_t st) {
-    return launch_window<T, 1>(a, n, in, out, nullptr, nullptr, nullptr, st);
+hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, void* jit, hipStream_t st) {
+    return launch_window<T, 1>(a, n, in, out, nullptr, nullptr, nullptr, jit, st);
 }
 
 template <typename T>
 hipError_t launch_window_rev(const PassArgs<T>& a, int n, const void* psi_in, void* psi_out, const void* lam_in,
-                             void* lam_out, double* gpart, uint32_t* nblocks, hipStream_t st) {
+                             void* lam_out, double* gpart, uint32_t* nblocks, void* jit, hipStream_t st) {
     *nblocks = window_blocks<T>(a, n, true);
-    return launch_window<T, 2>(a, n, psi_in, psi_out, lam_in, lam_out, gpart, st);
+    return launch_window<T, 2>(a, n, psi_in, psi_out, lam_in, lam_out, gpart, jit, st);
+}
+
+template <typename T>
+bool window_uses_lds(const PassArgs<T>& a, int n, bool reverse) {
+    return window_shape<T>(a, n, reverse).lds;
 }
 
 template <typename T>
@@ -1125,10 +1136,12 @@ hipError_t launch_reduce(const double* part, uint32_t nblocks, uint32_t nslots, 
     return hipGetLastError();
 }
 
-template hipError_t launch_window_fwd<float>(const PassArgs<float>&, int, const void*, void*, hipStream_t);
-template hipError_t launch_window_fwd<double>(const PassArgs<double>&, int, const void*, void*, hipStream_t);
-template hipError_t launch_window_rev<float>(const PassArgs<float>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
-template hipError_t launch_window_rev<double>(const PassArgs<double>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_window_fwd<float>(const PassArgs<float>&, int, const void*, void*, void*, hipStream_t);
+template hipError_t launch_window_fwd<double>(const PassArgs<double>&, int, const void*, void*, void*, hipStream_t);
+template hipError_t launch_window_rev<float>(const PassArgs<float>&, int, const void*, void*, const void*, void*, double*, uint32_t*, void*, hipStream_t);
+template hipError_t launch_window_rev<double>(const PassArgs<double>&, int, const void*, void*, const void*, void*, double*, uint32_t*, void*, hipStream_t);
+template bool window_uses_lds<float>(const PassArgs<float>&, int, bool);
+template bool window_uses_lds<double>(const PassArgs<double>&, int, bool);
 template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_expect_term<float>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);

@@ -125,16 +125,33 @@ hipError_t launch_set_basis(int dtype, void* psi, uint64_t dim, uint64_t b, hipS
 hipError_t launch_zero(double* p, uint64_t n, hipStream_t st);
 hipError_t launch_copy(int dtype, const void* src, void* dst, uint64_t dim, hipStream_t st);
 
-// in == out allowed (in place).  n = qubits of the state.
+// in == out allowed (in place).  n = qubits of the state.  jit: specialised
+// kernel for this pass (hipFunction_t, see jit.cpp) or nullptr for the
+// interpreted kernel; passes that stage through LDS always run interpreted.
 template <typename T>
-hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, hipStream_t st);
+hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, void* jit, hipStream_t st);
 
 // Reverse pass on (psi, lam); writes per-block gradient partials
 // [blocks][n_gslots] into gpart.  Returns the block count used via *nblocks.
 template <typename T>
 hipError_t launch_window_rev(const PassArgs<T>& a, int n, const void* psi_in, void* psi_out,
                              const void* lam_in, void* lam_out, double* gpart,
-                             uint32_t* nblocks, hipStream_t st);
+                             uint32_t* nblocks, void* jit, hipStream_t st);
+
+// True if the pass runs in the LDS-staged mode (never specialised).
+template <typename T>
+bool window_uses_lds(const PassArgs<T>& a, int n, bool reverse);
+
+// ---------------------------------------------------------------- specialised kernels (jit.cpp)
+int jit_mode();
+int jit_set_mode(int mode);
+// HIP source of the specialised kernel of one pass: K window bits, S lane-split
+// bits, NV = 1 (forward) or 2 (reverse, psi and lam), ops on physical slots.
+std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& ops, uint32_t n_gslots);
+// Compiles (in parallel) and loads on the current device every source not yet
+// cached; fns[i] = kernel of srcs[i] (nullptr for an empty source).
+int jit_prepare(const std::vector<std::string>& srcs, std::vector<void*>& fns, std::string& err);
+size_t jit_cached();
 
 // H psi tile kernel.  mode 0: lam = H psi and (Re<psi|lam>, <psi|psi>) partials.
 // mode 1: energy partials only, off-tile groups visited once per pair.
