@@ -145,15 +145,18 @@ int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_
 int vqe_circuit_free(vqe_circuit* c);
 
 /* n_params = 1 + the largest param_index used (0 if none); n_passes = fused
- * state sweeps per application. */
+ * state sweeps per application under the current kernel form. */
 int vqe_circuit_info(const vqe_circuit* c, size_t* n_params, size_t* n_passes);
 
-/* Inspection of the fused plan used for states of `dtype` (windows of at
- * most 5 qubits for VQE_C64, 4 for VQE_C128): pass `pass` has a
- * window of *window qubits (listed ascending in qubits[0..*window-1], at most
- * 5 entries) and applies *n_gates gates whose indices into the circuit's
- * gate list, in execution order, are written to gate_index (capacity
- * entries; may be NULL to query the count).  Host only. */
+/* Inspection of the fused plan that an evaluation would use now (it depends
+ * on the kernel form, see vqe_set_specialize: windows of at most 5 qubits for
+ * interpreted kernels, VQE_MAX_WINDOW for specialised ones; the same plan for
+ * both dtypes, which are only checked): pass `pass` has a window of *window
+ * qubits (listed ascending in qubits[0..*window-1]; the caller provides
+ * VQE_MAX_WINDOW entries) and applies *n_gates gates whose indices into the
+ * circuit's gate list, in execution order, are written to gate_index
+ * (capacity entries; may be NULL to query the count).  Host only. */
+#define VQE_MAX_WINDOW 7
 int vqe_circuit_pass(const vqe_circuit* c, int dtype, size_t pass, int* window, int* qubits,
                      size_t* n_gates, int32_t* gate_index, size_t capacity);
 

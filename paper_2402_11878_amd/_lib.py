@@ -19,6 +19,9 @@ GATE_RY, GATE_RZ, GATE_RX, GATE_H, GATE_X, GATE_CNOT, GATE_CZ = range(7)
 EXPECT_GROUPED, EXPECT_PER_TERM = 0, 1
 GRAD_ADJOINT, GRAD_PARAM_SHIFT = 0, 1
 SLIM_THRESHOLD, SLIM_REMOVE_PERCENT, SLIM_BUDGET = 0, 1, 2
+SPECIALIZE_NEVER, SPECIALIZE_AUTO, SPECIALIZE_ALWAYS = 0, 1, 2
+SPECIALIZE_AUTO_MIN_QUBITS = 20
+MAX_WINDOW = 7
 KERNEL_WINDOW_FWD, KERNEL_WINDOW_REV, KERNEL_HPSI, KERNEL_EXPECT_HALF, KERNEL_PER_TERM = range(5)
 
 
@@ -183,7 +186,7 @@ def vqe_circuit_info(c):
 
 def vqe_circuit_pass(c, dtype, p):
     K = C.c_int()
-    q = (C.c_int * 5)()
+    q = (C.c_int * MAX_WINDOW)()
     ng = _SZ()
     check("vqe_circuit_pass", lib().vqe_circuit_pass(c, dtype, p, C.byref(K), q, C.byref(ng), None, 0))
     idx = (C.c_int32 * max(ng.value, 1))()
@@ -248,10 +251,6 @@ def vqe_slim_hamiltonian(x, z, w, mode, value):
         xp, zp, wp, len(w), mode, float(value), keep.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(nk),
         C.byref(dropped)))
     return keep, nk.value, dropped.value
-
-
-SPECIALIZE_NEVER, SPECIALIZE_AUTO, SPECIALIZE_ALWAYS = 0, 1, 2
-SPECIALIZE_AUTO_MIN_QUBITS = 20
 
 
 def vqe_set_specialize(mode):

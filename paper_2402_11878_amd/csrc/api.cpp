@@ -54,6 +54,10 @@ struct vqe_state {
     double* d_res = nullptr;   // results (energies, gradients), grown on demand
     size_t res_cap = 0;
     double* h_res = nullptr;   // pinned host mirror of d_res
+    void* d_mats = nullptr;    // matrix table of the specialised kernels, filled per evaluation
+    void* h_mats = nullptr;    // pinned staging of d_mats
+    size_t mats_cap = 0;
+    hipEvent_t mats_ev = nullptr;  // completion of the last upload from h_mats
 };
 
 // Physical op list of a pass in the lane-split layout with S split bits.
@@ -66,20 +70,26 @@ struct PassOps {
     std::vector<KOp> fwd, rev;
     std::vector<int> fwd_mat_gate, rev_mat_gate;  // matrix slot -> gate index
     std::vector<int32_t> slot_param;              // reverse gradient slot -> parameter
-    SplitOps fwd_split[3], rev_split[3];          // [S] for S = 1, 2
+    // Per dtype (0: complex64, 1: complex128): lane-split bits of the forward
+    // and reverse pass and, where S > 0, the ops lowered to physical slots.
+    int S_f[2] = {0, 0}, S_r[2] = {0, 0};
+    SplitOps fwd_l[2], rev_l[2];
 };
 
-// A fused pass plan for one window size.
+// A fused pass plan: interpreted (windows <= kInterpWindow qubits, ops and
+// matrices as kernel arguments) or specialised (windows <= kMaxWindow, one
+// run-time compiled kernel per pass, matrices from a per-evaluation table).
 struct Plan {
+    bool jit = false;
     std::vector<PlannedPass> passes;
     std::vector<PassOps> ops;
     std::vector<int32_t> slotmap;   // all passes' gradient slot -> parameter maps
     int32_t* d_slotmap = nullptr;   // uploaded on first use on a device
     std::vector<size_t> slot_off;
-    // Specialised kernels per pass ([0] forward, [1] reverse; nullptr where the
-    // pass runs interpreted), built on first use on device jit_dev.
-    std::vector<void*> jit[2];
-    int jit_dev = -1;
+    std::vector<size_t> mat_off;    // [2 pass + dir]: first matrix of the pass in the table
+    size_t mat_total = 0;
+    std::vector<void*> jfn[2][2];   // [dtype][dir] specialised kernels, built on first use
+    int jit_dev[2] = {-1, -1};      // device they are loaded on
 };
 
 struct vqe_circuit {
@@ -88,8 +98,7 @@ struct vqe_circuit {
     size_t n_params = 0;
     std::vector<BatchGate> bgates;  // gate table of the batched small-state kernel
     uint32_t n_mats = 0;            // matrices per evaluation (gates with a 2x2 matrix)
-    Plan plan[2];  // [0]: complex64 (kWindowC64-qubit windows), [1]: complex128 (kWindowC128)
-    const Plan& for_dtype(int dtype) const { return plan[dtype == VQE_C64 ? 0 : 1]; }
+    Plan plan[2];  // [0]: interpreted, [1]: specialised
 };
 
 struct vqe_hamiltonian {
@@ -204,7 +213,7 @@ int ensure_res(vqe_state* s, size_t count) {
 }
 
 int upload_plan(const Plan& cpl);
-bool lower_split(const std::vector<KOp>& ops, int K, int S, SplitOps& out);
+bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps& out);
 
 // Uploads the grouped term tables to the current device (once).
 int upload_hamiltonian(const vqe_hamiltonian* ch) {
@@ -327,7 +336,8 @@ void build_args(const vqe_circuit* c, const Plan& pl, size_t pi, const double* p
     a.K = (uint32_t)p.K;
     a.n_cosets = 1ull << (c->n - p.K);
     for (int j = 0; j < p.K; ++j) a.pos[j] = (uint32_t)p.pos[j];
-    const int S = split_bits_for(sizeof(T) == 8, p.K, reverse);
+    const int d = sizeof(T) == 8 ? 1 : 0;
+    const int S = reverse ? po.S_r[d] : po.S_f[d];
     a.split = (uint32_t)S;
     const auto& mg = reverse ? po.rev_mat_gate : po.fwd_mat_gate;
     if (S == 0) {
@@ -336,7 +346,7 @@ void build_args(const vqe_circuit* c, const Plan& pl, size_t pi, const double* p
         for (size_t i = 0; i < ops.size(); ++i) a.ops[i] = ops[i];
         for (int sl = 0; sl < p.K; ++sl) a.pos_in[sl] = a.pos_out[sl] = (uint32_t)p.pos[sl];
     } else {
-        const SplitOps& so = reverse ? po.rev_split[S] : po.fwd_split[S];
+        const SplitOps& so = reverse ? po.rev_l[d] : po.fwd_l[d];
         a.n_ops = (uint32_t)so.ops.size();
         for (size_t i = 0; i < so.ops.size(); ++i) a.ops[i] = so.ops[i];
         for (int sl = 0; sl < p.K; ++sl) {
@@ -379,49 +389,105 @@ int check_params(const vqe_circuit* c, const double* params, size_t n_params, co
 
 std::mutex g_jit_plan_mu;
 
-// Specialised kernels of every pass of a plan (see vqe_set_specialize), built
-// on the first evaluation on the current device.  *fwd / *rev stay null when
-// the interpreted kernels are to run.
-template <typename T>
-int ensure_jit(const vqe_circuit* c, const Plan& cpl, const std::vector<void*>** fwd,
-               const std::vector<void*>** rev) {
-    *fwd = *rev = nullptr;
+// True if evaluations of c run the specialised plan (see vqe_set_specialize).
+bool use_specialised(const vqe_circuit* c) {
     const int mode = jit_mode();
-    if (mode == VQE_SPECIALIZE_NEVER || (mode == VQE_SPECIALIZE_AUTO && c->n < VQE_SPECIALIZE_AUTO_MIN_QUBITS))
-        return VQE_OK;
+    return mode == VQE_SPECIALIZE_ALWAYS ||
+           (mode == VQE_SPECIALIZE_AUTO && c->n >= VQE_SPECIALIZE_AUTO_MIN_QUBITS);
+}
+
+const Plan& plan_now(const vqe_circuit* c) { return c->plan[use_specialised(c) ? 1 : 0]; }
+
+// Physical ops, lane-split bits and slot positions of one specialised pass.
+const std::vector<KOp>& jit_ops(const Plan& pl, size_t pi, int d, bool reverse, int* S, JitArgs* a, int n) {
+    const PlannedPass& p = pl.passes[pi];
+    const PassOps& po = pl.ops[pi];
+    *S = reverse ? po.S_r[d] : po.S_f[d];
+    if (a) {
+        std::memset(a, 0, sizeof(*a));
+        a->n_cosets = 1ull << (n - p.K);
+        for (int j = 0; j < p.K; ++j) a->pos[j] = (uint32_t)p.pos[j];
+    }
+    if (*S == 0) {
+        if (a)
+            for (int j = 0; j < p.K; ++j) a->pos_in[j] = a->pos_out[j] = (uint32_t)p.pos[j];
+        return reverse ? po.rev : po.fwd;
+    }
+    const SplitOps& so = reverse ? po.rev_l[d] : po.fwd_l[d];
+    if (a)
+        for (int sl = 0; sl < p.K; ++sl) {
+            a->pos_in[sl] = (uint32_t)p.pos[so.map_in[sl]];
+            a->pos_out[sl] = (uint32_t)p.pos[so.map_out[sl]];
+        }
+    return so.ops;
+}
+
+// Compiles and loads the specialised kernels of every pass of a specialised
+// plan for dtype index d on the current device (once; cached).
+int ensure_jit(const vqe_circuit* c, const Plan& cpl, int d) {
     Plan& pl = const_cast<Plan&>(cpl);
     int dev = 0;
     VQE_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> g(g_jit_plan_mu);
     const size_t P = pl.passes.size();
-    if (pl.jit_dev != dev || pl.jit[0].size() != P) {
-        std::vector<std::string> srcs(2 * P);
-        std::vector<double> zeros(c->n_params + 1, 0.0);
-        PassArgs<T> a;
-        for (size_t pi = 0; pi < P; ++pi)
-            for (int dir = 0; dir < 2; ++dir) {
-                build_args<T>(c, pl, pi, zeros.data(), dir == 1, a);
-                if (window_uses_lds<T>(a, c->n, dir == 1)) continue;
-                srcs[2 * pi + dir] = jit_source(sizeof(T) == 8, (int)a.K, (int)a.split, dir == 1 ? 2 : 1,
-                                                std::vector<KOp>(a.ops, a.ops + a.n_ops), a.n_gslots);
-            }
-        std::vector<void*> fns;
-        std::string err;
-        const int rc = jit_prepare(srcs, fns, err);
-        if (rc) {
-            set_error(err);
-            return rc;
+    if (pl.jit_dev[d] == dev && pl.jfn[d][0].size() == P) return VQE_OK;
+    std::vector<std::string> srcs(2 * P);
+    for (size_t pi = 0; pi < P; ++pi)
+        for (int dir = 0; dir < 2; ++dir) {
+            int S = 0;
+            const auto& ops = jit_ops(pl, pi, d, dir == 1, &S, nullptr, c->n);
+            srcs[2 * pi + dir] = jit_source(d == 1, pl.passes[pi].K, S, dir == 1 ? 2 : 1, ops,
+                                            dir == 1 ? (uint32_t)pl.ops[pi].slot_param.size() : 0);
         }
-        pl.jit[0].assign(P, nullptr);
-        pl.jit[1].assign(P, nullptr);
-        for (size_t pi = 0; pi < P; ++pi) {
-            pl.jit[0][pi] = fns[2 * pi];
-            pl.jit[1][pi] = fns[2 * pi + 1];
-        }
-        pl.jit_dev = dev;
+    std::vector<void*> fns;
+    std::string err;
+    const int rc = jit_prepare(srcs, fns, err);
+    if (rc) {
+        set_error(err);
+        return rc;
     }
-    *fwd = &pl.jit[0];
-    *rev = &pl.jit[1];
+    for (int dir = 0; dir < 2; ++dir) {
+        pl.jfn[d][dir].assign(P, nullptr);
+        for (size_t pi = 0; pi < P; ++pi) pl.jfn[d][dir][pi] = fns[2 * pi + dir];
+    }
+    pl.jit_dev[d] = dev;
+    return VQE_OK;
+}
+
+// Fills the matrix table of a specialised plan (every pass, both directions)
+// for these parameters and uploads it on the state's stream.  The pinned
+// staging buffer is reused only after its previous upload has completed.
+template <typename T>
+int upload_mats(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* params, const Mat2<T>** out) {
+    const size_t bytes = std::max<size_t>(pl.mat_total, 1) * sizeof(Mat2<T>);
+    if (!s->mats_ev) VQE_HIP(hipEventCreateWithFlags(&s->mats_ev, hipEventDisableTiming));
+    if (bytes > s->mats_cap) {
+        VQE_HIP(hipStreamSynchronize(s->stream));
+        if (s->d_mats) VQE_HIP(hipFree(s->d_mats));
+        if (s->h_mats) VQE_HIP(hipHostFree(s->h_mats));
+        s->d_mats = s->h_mats = nullptr;
+        s->mats_cap = 0;
+        if (hipMalloc(&s->d_mats, bytes) != hipSuccess || hipHostMalloc(&s->h_mats, bytes) != hipSuccess) {
+            set_error("allocation of the matrix table failed");
+            return VQE_ERR_OOM;
+        }
+        s->mats_cap = bytes;
+    } else {
+        VQE_HIP(hipEventSynchronize(s->mats_ev));
+    }
+    Mat2<T>* h = (Mat2<T>*)s->h_mats;
+    for (size_t pi = 0; pi < pl.passes.size(); ++pi)
+        for (int dir = 0; dir < 2; ++dir) {
+            const auto& mg = dir ? pl.ops[pi].rev_mat_gate : pl.ops[pi].fwd_mat_gate;
+            Mat2<T>* m = h + pl.mat_off[2 * pi + dir];
+            for (size_t i = 0; i < mg.size(); ++i) {
+                const Gate& g = c->gates[mg[i]];
+                fill_matrix(m[i], g, angle_of(g, params), dir == 1);
+            }
+        }
+    VQE_HIP(hipMemcpyAsync(s->d_mats, s->h_mats, bytes, hipMemcpyHostToDevice, s->stream));
+    VQE_HIP(hipEventRecord(s->mats_ev, s->stream));
+    *out = (const Mat2<T>*)s->d_mats;
     return VQE_OK;
 }
 
@@ -431,17 +497,29 @@ template <typename T>
 int forward(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* params,
             const std::vector<size_t>& bounds, const std::vector<void*>& ckpt_ptr) {
     void* cur = s->data;
-    const std::vector<void*>*jf = nullptr, *jr = nullptr;
-    const int rc = ensure_jit<T>(c, pl, &jf, &jr);
-    if (rc) return rc;
+    const int d = sizeof(T) == 8 ? 1 : 0;
+    const Mat2<T>* mats = nullptr;
+    if (pl.jit) {
+        int rc = ensure_jit(c, pl, d);
+        if (!rc) rc = upload_mats<T>(s, c, pl, params, &mats);
+        if (rc) return rc;
+    }
     PassArgs<T> a;
+    JitArgs ja;
     for (size_t pi = 0; pi < pl.passes.size(); ++pi) {
         void* out = s->data;
         for (size_t k = 0; k < bounds.size(); ++k)
             if (bounds[k] == pi + 1) out = ckpt_ptr[k];
-        build_args<T>(c, pl, pi, params, false, a);
         ProfScope ps(VQE_KERNEL_WINDOW_FWD, 2.0 * (double)s->bytes, s->stream);
-        VQE_HIP(launch_window_fwd<T>(a, s->n, cur, out, jf ? (*jf)[pi] : nullptr, s->stream));
+        if (pl.jit) {
+            int S = 0;
+            jit_ops(pl, pi, d, false, &S, &ja, s->n);
+            VQE_HIP(launch_window_jit(pl.jfn[d][0][pi], ja, S, mats + pl.mat_off[2 * pi], false, cur, out, nullptr,
+                                      nullptr, nullptr, nullptr, s->stream));
+        } else {
+            build_args<T>(c, pl, pi, params, false, a);
+            VQE_HIP(launch_window_fwd<T>(a, s->n, cur, out, s->stream));
+        }
         ps.end();
         cur = out;
     }
@@ -536,7 +614,7 @@ int expect_impl(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy
 template <typename T>
 int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const double* params,
                  const vqe_hamiltonian* h, const vqe_grad_opts* o, double* energy, double* grad) {
-    const Plan& pl = c->for_dtype(psi->dtype);
+    const Plan& pl = plan_now(c);
     if (int rc0 = upload_plan(pl)) return rc0;
     const size_t P = pl.passes.size();
     std::vector<size_t> bounds;
@@ -565,22 +643,29 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
     }
     VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, d_e, 0, st));
     VQE_HIP(launch_zero(d_g, c->n_params, st));
-    const std::vector<void*>*jf = nullptr, *jr = nullptr;
-    rc = ensure_jit<T>(c, pl, &jf, &jr);
-    if (rc) return rc;
+    const int d = sizeof(T) == 8 ? 1 : 0;
+    const Mat2<T>* mats = (const Mat2<T>*)psi->d_mats;  // uploaded by forward()
     PassArgs<T> a;
+    JitArgs ja;
     for (size_t pi = P; pi-- > 0;) {
         const void* pin = psi->data;
         for (size_t k = 0; k < bounds.size(); ++k)
             if (bounds[k] == pi + 1) pin = ck[k];
-        build_args<T>(c, pl, pi, params, true, a);
         uint32_t gb = 0;
+        const uint32_t n_gslots = (uint32_t)pl.ops[pi].slot_param.size();
         ProfScope ps(VQE_KERNEL_WINDOW_REV, 4.0 * (double)psi->bytes, st);
-        VQE_HIP(launch_window_rev<T>(a, psi->n, pin, psi->data, lam->data, lam->data, psi->d_part, &gb,
-                                     jr ? (*jr)[pi] : nullptr, st));
+        if (pl.jit) {
+            int S = 0;
+            jit_ops(pl, pi, d, true, &S, &ja, psi->n);
+            VQE_HIP(launch_window_jit(pl.jfn[d][1][pi], ja, S, mats + pl.mat_off[2 * pi + 1], true, pin, psi->data,
+                                      lam->data, lam->data, psi->d_part, &gb, st));
+        } else {
+            build_args<T>(c, pl, pi, params, true, a);
+            VQE_HIP(launch_window_rev<T>(a, psi->n, pin, psi->data, lam->data, lam->data, psi->d_part, &gb, st));
+        }
         ps.end();
-        if (a.n_gslots)
-            VQE_HIP(launch_reduce(psi->d_part, gb, a.n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, 1, st));
+        if (n_gslots)
+            VQE_HIP(launch_reduce(psi->d_part, gb, n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, 1, st));
     }
     VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, (2 + c->n_params) * sizeof(double), hipMemcpyDeviceToHost, st));
     VQE_HIP(hipStreamSynchronize(st));
@@ -609,7 +694,7 @@ int param_shift_impl(vqe_state* psi, const vqe_circuit* c, const double* params,
             th[k] += (e % 2 == 1) ? M_PI / 2 : -M_PI / 2;
         }
         VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, psi->stream));
-        rc = forward<T>(psi, c, c->for_dtype(psi->dtype), th.data(), nob, nock);
+        rc = forward<T>(psi, c, plan_now(c), th.data(), nob, nock);
         if (rc) return rc;
         rc = mode == VQE_EXPECT_PER_TERM ? energy_per_term<T>(psi, h, e * per) : energy_grouped<T>(psi, h, e * per);
         if (rc) return rc;
@@ -640,11 +725,13 @@ void free_circuit(vqe_circuit* c) {
     delete c;
 }
 
-// Plans fused passes with windows of at most kwin qubits and lowers them to
-// kernel op lists (forward, and reverse with gradient ops).
-int build_plan(vqe_circuit* c, int kwin, Plan& pl) {
+// Plans fused passes within the given limits and lowers them to kernel op
+// lists (forward, and reverse with gradient ops), per dtype also to the
+// lane-split layout.
+int build_plan(vqe_circuit* c, const PlanLimits& lim, bool jit, Plan& pl) {
     std::string msg;
-    if (!plan_passes(c->n, c->gates, kwin, pl.passes, msg)) {
+    pl.jit = jit;
+    if (!plan_passes(c->n, c->gates, lim, pl.passes, msg)) {
         set_error("vqe_circuit_create: " + msg);
         return VQE_ERR_STATE;
     }
@@ -677,9 +764,17 @@ int build_plan(vqe_circuit* c, int kwin, Plan& pl) {
         }
         pl.slot_off.push_back(slotmap.size());
         slotmap.insert(slotmap.end(), po.slot_param.begin(), po.slot_param.end());
-        for (int S = 1; S <= 2; ++S) {
-            if (p.K <= S + 1) continue;
-            if (!lower_split(po.fwd, p.K, S, po.fwd_split[S]) || !lower_split(po.rev, p.K, S, po.rev_split[S])) {
+        pl.mat_off.push_back(pl.mat_total);
+        pl.mat_total += po.fwd_mat_gate.size();
+        pl.mat_off.push_back(pl.mat_total);
+        pl.mat_total += po.rev_mat_gate.size();
+        // interpreted kernels hold the lowered ops in their arguments
+        const size_t cap = jit ? (size_t)-1 : (size_t)kMaxPhysOps;
+        for (int d = 0; d < 2; ++d) {
+            po.S_f[d] = split_bits_for(jit, d == 1, p.K, false);
+            po.S_r[d] = split_bits_for(jit, d == 1, p.K, true);
+            if ((po.S_f[d] && !lower_split(po.fwd, p.K, po.S_f[d], cap, po.fwd_l[d])) ||
+                (po.S_r[d] && !lower_split(po.rev, p.K, po.S_r[d], cap, po.rev_l[d]))) {
                 set_error("vqe_circuit_create: too many ops in a pass after lane transposes (internal limit)");
                 return VQE_ERR_STATE;
             }
@@ -710,7 +805,7 @@ uint32_t reg_needs(const KOp& op) {
 // often start in the lanes; before an op that needs a lane-resident bit in
 // registers, a TPOSE swaps it with the register bit whose next use is
 // furthest away.  Returns false if the op capacity would be exceeded.
-bool lower_split(const std::vector<KOp>& ops, int K, int S, SplitOps& out) {
+bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps& out) {
     const int KL = K - S;
     int cost[kMaxWindow] = {0};
     for (const auto& op : ops)
@@ -768,7 +863,7 @@ bool lower_split(const std::vector<KOp>& ops, int K, int S, SplitOps& out) {
         out.ops.push_back(ph);
     }
     for (int sl = 0; sl < K; ++sl) out.map_out[sl] = (uint8_t)bit_at[sl];
-    return out.ops.size() <= (size_t)kMaxPhysOps;
+    return out.ops.size() <= cap;
 }
 
 // Uploads the gradient slot maps of a plan to the current device (once).
@@ -960,6 +1055,9 @@ int vqe_state_free(vqe_state* s) {
     if (s->d_part) (void)hipFree(s->d_part);
     if (s->d_res) (void)hipFree(s->d_res);
     if (s->h_res) (void)hipHostFree(s->h_res);
+    if (s->d_mats) (void)hipFree(s->d_mats);
+    if (s->h_mats) (void)hipHostFree(s->h_mats);
+    if (s->mats_ev) (void)hipEventDestroy(s->mats_ev);
     delete s;
     return VQE_OK;
 }
@@ -1075,9 +1173,8 @@ int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_
         }
         c->bgates.push_back(bg);
     }
-    const int windows[2] = {kWindowC64, kWindowC128};
     for (int v = 0; v < 2; ++v) {
-        int rc = build_plan(c, windows[v], c->plan[v]);
+        int rc = build_plan(c, v ? kJitLimits : kInterpLimits, v == 1, c->plan[v]);
         if (rc) {
             free_circuit(c);
             return rc;
@@ -1099,7 +1196,7 @@ int vqe_circuit_info(const vqe_circuit* c, size_t* n_params, size_t* n_passes) {
         return VQE_ERR_ARG;
     }
     if (n_params) *n_params = c->n_params;
-    if (n_passes) *n_passes = c->plan[0].passes.size();
+    if (n_passes) *n_passes = plan_now(c).passes.size();
     return VQE_OK;
 }
 
@@ -1109,7 +1206,7 @@ int vqe_circuit_pass(const vqe_circuit* c, int dtype, size_t pass, int* window, 
         set_error("vqe_circuit_pass: null circuit or bad dtype");
         return VQE_ERR_ARG;
     }
-    const Plan& pl = c->for_dtype(dtype);
+    const Plan& pl = plan_now(c);
     if (pass >= pl.passes.size()) {
         set_error("vqe_circuit_pass: pass index out of range");
         return VQE_ERR_ARG;
@@ -1140,7 +1237,7 @@ int vqe_apply_circuit(vqe_state* s, const vqe_circuit* c, const double* params, 
     VQE_HIP(hipSetDevice(s->device));
     const std::vector<size_t> nob;
     const std::vector<void*> nock;
-    const Plan& pl = c->for_dtype(s->dtype);
+    const Plan& pl = plan_now(c);
     return s->dtype == VQE_C64 ? forward<float>(s, c, pl, params, nob, nock) : forward<double>(s, c, pl, params, nob, nock);
     VQE_GUARD_END
 }

@@ -13,11 +13,12 @@
 //   * 2x2 ops, phases and gradient terms are written per register pair with
 //     the pair indices known;
 //   * lane-split transposes are single permlane swaps on named registers.
-// Window positions and matrices stay kernel arguments (the same PassArgs as
-// the interpreted kernels), so passes with equal op lists share one kernel.
-// The load/store addressing, work order, grid and gradient reduction are the
-// interpreted kernels', so both forms give the same results up to rounding
-// of fused multiply-adds.
+// Window positions stay kernel arguments and matrices come from a device
+// table filled per evaluation, so passes with equal op lists share a kernel.
+// Windows of up to 7 qubits are split over lane bits 2..5 (see split_bits_for).
+// The load/store addressing, work order and grid follow the interpreted
+// kernels, so both forms give the same results up to the rounding of fused
+// multiply-adds and of the gradient sums.
 #include <hip/hiprtc.h>
 
 #include <algorithm>
@@ -41,24 +42,39 @@ struct Entry {
 std::mutex g_mu;
 std::map<std::pair<int, std::string>, Entry> g_cache;  // (device, source) -> loaded kernel
 
-// Text of the kernel argument types; must match PassArgs / Mat2 / KOp.
+// Text of the kernel argument types; must match JitArgs / Mat2.
 std::string prelude(bool dbl) {
     const char* T = dbl ? "double" : "float";
     std::ostringstream o;
     o << "typedef unsigned long long u64;\ntypedef unsigned int u32;\n"
       << "typedef " << T << " T;\n"
-      << "struct KOp { unsigned char type, a, b, slot; };\n"
       << "struct Mat2 { T v[8]; };\n"
-      << "struct PassArgs { u64 n_cosets; u32 K, n_ops, n_gslots, split; u32 pos[" << kMaxWindow << "]; u32 pos_in["
-      << kMaxWindow << "]; u32 pos_out[" << kMaxWindow << "]; KOp ops[" << kMaxPhysOps << "]; Mat2 mats["
-      << kMaxMats << "]; };\n"
+      << "struct JitArgs { u64 n_cosets; u32 pos[" << kMaxWindow << "]; u32 pos_in[" << kMaxWindow
+      << "]; u32 pos_out[" << kMaxWindow << "]; };\n"
       << "struct __attribute__((aligned(" << (dbl ? 16 : 8) << "))) V { T x, y; };\n"
       << "__device__ __forceinline__ u64 xcd_order(u64 u, u32 m) {\n"
       << "  if (m < 3) return u;\n  return (u >> 3) | ((u & 7ull) << (m - 3));\n}\n";
-    // lane transposes: (a, b) -> (a_lo | b_lo, a_hi | b_hi) over the lane bit
+    // Lane transpose over lane bit LB (mask m = 2^LB) of the register pair
+    // (a, b): a' = a on lanes with the bit clear, b(lane - m) on lanes with it
+    // set; b' = a(lane + m) on lanes with the bit clear, b on lanes with it set.
+    // Lane bits 5 and 4: one v_permlane{32,16}_swap per dword.  Lane bits 3
+    // and 2: DPP row_ror:8 (lane ^ 8) or row_shr:4 / row_shl:4 (lane - 4 /
+    // lane + 4 within a row of 16) and a per-lane select.
     o << "template <int LB> __device__ __forceinline__ void tp32(u32& a, u32& b) {\n"
-      << "  if constexpr (LB == 5) { const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false); a = r[0]; b = r[1]; }\n"
-      << "  else { const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false); a = r[0]; b = r[1]; }\n}\n";
+      << "  if constexpr (LB == 5) { const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false); a = r[0]; "
+         "b = r[1]; }\n"
+      << "  else if constexpr (LB == 4) { const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false); a = "
+         "r[0]; b = r[1]; }\n"
+      << "  else {\n"
+      << "    constexpr int DN = LB == 3 ? 0x128 : 0x114;\n"
+      << "    constexpr int UP = LB == 3 ? 0x128 : 0x104;\n"
+      << "    const bool hb = (threadIdx.x >> LB) & 1;\n"
+      << "    const u32 bd = (u32)__builtin_amdgcn_update_dpp(0, (int)b, DN, 0xF, 0xF, false);\n"
+      << "    const u32 au = (u32)__builtin_amdgcn_update_dpp(0, (int)a, UP, 0xF, 0xF, false);\n"
+      << "    const u32 na = hb ? bd : a;\n"
+      << "    b = hb ? b : au;\n"
+      << "    a = na;\n"
+      << "  }\n}\n";
     if (dbl)
         o << "template <int LB> __device__ __forceinline__ void tp(T& a, T& b) {\n"
           << "  u64 x = __builtin_bit_cast(u64, a), y = __builtin_bit_cast(u64, b);\n"
@@ -79,11 +95,11 @@ struct Gen {
     std::ostringstream o;
     std::string R(int v, int p) const { return "r" + std::to_string(v) + "_" + std::to_string(loc[p]); }
     std::string I(int v, int p) const { return "i" + std::to_string(v) + "_" + std::to_string(loc[p]); }
-    std::string H(int lane_slot) const { return lane_slot == 0 ? "h0" : "h1"; }
-    int lane_bit(int lane_slot) const { return (S == 1 || lane_slot == 1) ? 5 : 4; }
+    std::string H(int lane_slot) const { return "h" + std::to_string(lane_slot); }
+    int lane_bit(int lane_slot) const { return 6 - S + lane_slot; }
 
     void mats(int s, bool all) {
-        o << "  { const T* m = a.mats[" << s << "].v;\n";
+        o << "  { const T* m = mats[" << s << "].v;\n";
         if (all)
             o << "    const T m0r = m[0], m0i = m[1], m1r = m[2], m1i = m[3], m2r = m[4], m2i = m[5], m3r = m[6], "
                  "m3i = m[7];\n";
@@ -274,19 +290,18 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
     std::ostringstream& o = g.o;
     o << prelude(dbl);
     o << "extern \"C\" __global__ void __launch_bounds__(" << kBlock << ")\n"
-      << "vqe_pass(const PassArgs a, u32 cpt, u32 interleave, u32 mlog, const V* __restrict__ in0, V* __restrict__ "
-         "out0, const V* __restrict__ in1, V* __restrict__ out1, double* __restrict__ gpart) {\n"
+      << "vqe_pass(const JitArgs a, const Mat2* __restrict__ mats, u32 cpt, u32 interleave, u32 mlog, "
+         "const V* __restrict__ in0, V* __restrict__ out0, const V* __restrict__ in1, V* __restrict__ out1, "
+         "double* __restrict__ gpart) {\n"
       << "  const int tid = threadIdx.x;\n  const int lane = tid & 63;\n"
       << "  const int sub = (tid >> 6) * " << CPW << " + (lane & " << (CPW - 1) << ");\n"
-      << "  const bool h0 = (lane >> " << (S == 1 ? 5 : 4) << ") & 1, h1 = (lane >> 5) & 1;\n"
-      << "  (void)h0; (void)h1;\n"
       << "  u64 bitval[" << K << "], bv_in[" << K << "], bv_out[" << K << "];\n"
       << "#pragma unroll\n  for (int j = 0; j < " << K
       << "; ++j) { bitval[j] = 1ull << a.pos[j]; bv_in[j] = 1ull << a.pos_in[j]; bv_out[j] = 1ull << a.pos_out[j]; }\n"
       << "  u64 half_in = 0, half_out = 0;\n";
     for (int j = 0; j < S; ++j)
-        o << "  if (" << (j == 0 ? "h0" : "h1") << ") { half_in += bv_in[" << g.KL + j << "]; half_out += bv_out["
-          << g.KL + j << "]; }\n";
+        o << "  const bool h" << j << " = (lane >> " << g.lane_bit(j) << ") & 1;\n"
+          << "  if (h" << j << ") { half_in += bv_in[" << g.KL + j << "]; half_out += bv_out[" << g.KL + j << "]; }\n";
     for (uint32_t s = 0; s < n_gslots; ++s) o << "  double g" << s << " = 0.0;\n";
     o << "  for (u32 it = 0; it < cpt; ++it) {\n"
       << "    const u64 blk = xcd_order(interleave ? (u64)it * gridDim.x + blockIdx.x : (u64)blockIdx.x * cpt + it, "
@@ -314,17 +329,17 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
               << g.I(v, p) << "};\n";
     o << "  }\n";
     if (NV == 2 && n_gslots) {
-        // fixed-tree block reduction of every gradient slot (same order as the interpreted kernels)
-        o << "  __shared__ double gacc[" << n_gslots * kBlock << "];\n";
-        for (uint32_t s = 0; s < n_gslots; ++s) o << "  gacc[" << s * kBlock << " + tid] = g" << s << ";\n";
-        o << "  __syncthreads();\n"
-          << "  for (int w = " << kBlock / 2 << "; w > 0; w >>= 1) {\n"
-          << "    if (tid < w) {\n";
-        for (uint32_t s = 0; s < n_gslots; ++s)
-            o << "      gacc[" << s * kBlock << " + tid] += gacc[" << s * kBlock << " + tid + w];\n";
-        o << "    }\n    __syncthreads();\n  }\n"
-          << "  if (tid < " << n_gslots << ") gpart[(u64)blockIdx.x * " << n_gslots << " + tid] = gacc[tid * "
-          << kBlock << "];\n";
+        // fixed-tree block reduction, one gradient slot at a time
+        o << "  __shared__ double red[" << kBlock << "];\n"
+          << "  const double gv[" << n_gslots << "] = {";
+        for (uint32_t s = 0; s < n_gslots; ++s) o << (s ? ", " : "") << "g" << s;
+        o << "};\n"
+          << "#pragma unroll\n  for (int s = 0; s < " << n_gslots << "; ++s) {\n"
+          << "    red[tid] = gv[s];\n    __syncthreads();\n"
+          << "    for (int w = " << kBlock / 2 << "; w > 0; w >>= 1) {\n"
+          << "      if (tid < w) red[tid] += red[tid + w];\n      __syncthreads();\n    }\n"
+          << "    if (tid == 0) gpart[(u64)blockIdx.x * " << n_gslots << " + s] = red[0];\n"
+          << "    __syncthreads();\n  }\n";
     }
     o << "}\n";
     return o.str();

@@ -436,7 +436,7 @@ window_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t m
               typename VecOf<T>::type* __restrict__ out1, double* __restrict__ gpart) {
     using V = typename VecOf<T>::type;
     constexpr int N = 1 << K;
-    __shared__ double gacc[NV == 2 ? kMaxGradSlots * kBlock : 1];
+    __shared__ double gacc[NV == 2 ? kInterpGradSlots * kBlock : 1];
     const int tid = threadIdx.x;
     if constexpr (NV == 2) {
         for (uint32_t s = 0; s < a.n_gslots; ++s) gacc[s * kBlock + tid] = 0.0;
@@ -517,7 +517,7 @@ window_split_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint
     constexpr int N = 1 << KL;
     constexpr int CPW = 64 >> S;               // cosets per wave
     constexpr int PER_BLOCK = kBlock >> S;     // cosets per block and iteration
-    __shared__ double gacc[NV == 2 ? kMaxGradSlots * kBlock : 1];
+    __shared__ double gacc[NV == 2 ? kInterpGradSlots * kBlock : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int sub = (tid >> 6) * CPW + (lane & (CPW - 1));
@@ -630,7 +630,7 @@ window_lds_kernel(const PassArgs<T> a, const LdsMap m, uint32_t cpt, uint32_t in
     constexpr int CH = 1 << NU;       // amplitudes per chunk
     constexpr int WAVES = kBlock / 64;
     __shared__ V chunk[WAVES][CH];
-    __shared__ double gacc[NV == 2 ? kMaxGradSlots * kBlock : 1];
+    __shared__ double gacc[NV == 2 ? kInterpGradSlots * kBlock : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
@@ -1025,19 +1025,13 @@ uint32_t window_blocks(const PassArgs<T>& a, int n, bool with_partials) {
 
 template <typename T, int NV>
 hipError_t launch_window(const PassArgs<T>& a, int n, const void* in0, void* out0, const void* in1, void* out1,
-                         double* gpart, void* jit, hipStream_t st) {
+                         double* gpart, hipStream_t st) {
     using V = typename VecOf<T>::type;
     const WinShape w = window_shape<T>(a, n, NV == 2);
     const V* i0 = (const V*)in0;
     V* o0 = (V*)out0;
     const V* i1 = (const V*)in1;
     V* o1 = (V*)out1;
-    if (jit && !w.lds) {
-        PassArgs<T> ka = a;
-        uint32_t cpt = w.cpt, interleave = w.interleave, mlog = w.mlog;
-        void* params[] = {&ka, &cpt, &interleave, &mlog, (void*)&i0, (void*)&o0, (void*)&i1, (void*)&o1, &gpart};
-        return hipModuleLaunchKernel((hipFunction_t)jit, w.grid, 1, 1, kBlock, 1, 1, 0, st, params, nullptr);
-    }
 #define VQE_WIN(KK)                                                                                      \
     case KK:                                                                                             \
         if (w.split == 1) {                                                                              \
@@ -1069,21 +1063,31 @@ hipError_t launch_window(const PassArgs<T>& a, int n, const void* in0, void* out
 }
 
 template <typename T>
-hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, void* jit, hipStream_t st) {
-    return launch_window<T, 1>(a, n, in, out, nullptr, nullptr, nullptr, jit, st);
+hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, hipStream_t st) {
+    return launch_window<T, 1>(a, n, in, out, nullptr, nullptr, nullptr, st);
 }
 
 template <typename T>
 hipError_t launch_window_rev(const PassArgs<T>& a, int n, const void* psi_in, void* psi_out, const void* lam_in,
-                             void* lam_out, double* gpart, uint32_t* nblocks, void* jit, hipStream_t st) {
+                             void* lam_out, double* gpart, uint32_t* nblocks, hipStream_t st) {
     *nblocks = window_blocks<T>(a, n, true);
-    return launch_window<T, 2>(a, n, psi_in, psi_out, lam_in, lam_out, gpart, jit, st);
+    return launch_window<T, 2>(a, n, psi_in, psi_out, lam_in, lam_out, gpart, st);
 }
 
-template <typename T>
-bool window_uses_lds(const PassArgs<T>& a, int n, bool reverse) {
-    return window_shape<T>(a, n, reverse).lds;
+hipError_t launch_window_jit(void* fn, const JitArgs& a, int S, const void* mats, bool reverse, const void* in0,
+                             void* out0, const void* in1, void* out1, double* gpart, uint32_t* nblocks,
+                             hipStream_t st) {
+    WinShape w{};
+    const uint64_t per_unit = (uint64_t)kBlock >> S;
+    grid_for_units((a.n_cosets + per_unit - 1) / per_unit, reverse, w);
+    if (nblocks) *nblocks = w.grid;
+    JitArgs ka = a;
+    uint32_t cpt = w.cpt, interleave = w.interleave, mlog = w.mlog;
+    void* params[] = {&ka, (void*)&mats, &cpt, &interleave, &mlog, (void*)&in0, (void*)&out0,
+                      (void*)&in1, (void*)&out1, (void*)&gpart};
+    return hipModuleLaunchKernel((hipFunction_t)fn, w.grid, 1, 1, kBlock, 1, 1, 0, st, params, nullptr);
 }
+
 
 template <typename T>
 hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* groups, uint32_t n_groups,
@@ -1136,12 +1140,10 @@ hipError_t launch_reduce(const double* part, uint32_t nblocks, uint32_t nslots, 
     return hipGetLastError();
 }
 
-template hipError_t launch_window_fwd<float>(const PassArgs<float>&, int, const void*, void*, void*, hipStream_t);
-template hipError_t launch_window_fwd<double>(const PassArgs<double>&, int, const void*, void*, void*, hipStream_t);
-template hipError_t launch_window_rev<float>(const PassArgs<float>&, int, const void*, void*, const void*, void*, double*, uint32_t*, void*, hipStream_t);
-template hipError_t launch_window_rev<double>(const PassArgs<double>&, int, const void*, void*, const void*, void*, double*, uint32_t*, void*, hipStream_t);
-template bool window_uses_lds<float>(const PassArgs<float>&, int, bool);
-template bool window_uses_lds<double>(const PassArgs<double>&, int, bool);
+template hipError_t launch_window_fwd<float>(const PassArgs<float>&, int, const void*, void*, hipStream_t);
+template hipError_t launch_window_fwd<double>(const PassArgs<double>&, int, const void*, void*, hipStream_t);
+template hipError_t launch_window_rev<float>(const PassArgs<float>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_window_rev<double>(const PassArgs<double>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_expect_term<float>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);

@@ -1,5 +1,5 @@
 // Fusion planner: partitions a gate list into passes, each pass a window of at
-// most kMaxWindow qubits whose gates are applied with one read and one write
+// most lim.kmax qubits whose gates are applied with one read and one write
 // of the state (one HBM sweep instead of one per gate).
 //
 // Gates on disjoint qubits commute, so a gate may run before any earlier gate
@@ -22,6 +22,7 @@ namespace {
 
 struct PlanState {
     int n;
+    const PlanLimits* lim;
     const std::vector<Gate>* gates;
     std::vector<std::vector<int>> chain;  // per qubit, gate indices in order
     std::vector<size_t> head;             // per qubit, position of next unscheduled gate
@@ -38,8 +39,10 @@ bool uses_matrix(const Gate& g) {
 
 // Closure of window W (bit mask over qubits) starting from `head`; appends the
 // scheduled gates to `out` (if non-null) and advances `head`.  Respects the
-// per-pass op / matrix / gradient-slot limits.
+// per-pass op / matrix / gradient-slot limits (a repeated parameter within a
+// pass shares its slot, counted here once per gate: a safe overestimate).
 int closure(const PlanState& ps, uint64_t W, std::vector<size_t>& head, std::vector<int>* out) {
+    const PlanLimits& L = *ps.lim;
     const auto& G = *ps.gates;
     int count = 0, ops_rev = 0, mats = 0, slots = 0;
     bool changed = true;
@@ -56,8 +59,7 @@ int closure(const PlanState& ps, uint64_t W, std::vector<size_t>& head, std::vec
                 int add_ops = 1 + (is_param(g) ? 1 : 0);
                 int add_mats = uses_matrix(g) ? 1 : 0;
                 int add_slots = is_param(g) ? 1 : 0;
-                if (ops_rev + add_ops > kMaxOps || mats + add_mats > kMaxMats ||
-                    slots + add_slots > kMaxGradSlots)
+                if (ops_rev + add_ops > L.ops || mats + add_mats > L.mats || slots + add_slots > L.slots)
                     return count;
                 ops_rev += add_ops;
                 mats += add_mats;
@@ -77,12 +79,13 @@ int popcount64(uint64_t v) { return __builtin_popcountll(v); }
 
 }  // namespace
 
-bool plan_passes(int n, const std::vector<Gate>& gates, int kmax, std::vector<PlannedPass>& out,
+bool plan_passes(int n, const std::vector<Gate>& gates, const PlanLimits& lim, std::vector<PlannedPass>& out,
                  std::string& msg) {
     out.clear();
-    const int K = std::min(n, std::min(kmax, kMaxWindow));
+    const int K = std::min(n, std::min(lim.kmax, kMaxWindow));
     PlanState ps;
     ps.n = n;
+    ps.lim = &lim;
     ps.gates = &gates;
     ps.chain.assign(n, {});
     ps.head.assign(n, 0);

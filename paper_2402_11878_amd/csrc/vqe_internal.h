@@ -13,17 +13,31 @@
 namespace vqe {
 
 // ---------------------------------------------------------------- limits
-constexpr int kMaxWindow = 5;     // qubits fused per pass (2^5 amplitudes per thread)
-constexpr int kWindowC64 = 5;     // window used for complex64 states
-constexpr int kWindowC128 = 5;    // window used for complex128 states
-constexpr int kMaxOps = 64;       // logical kernel ops per pass (planner limit)
-constexpr int kMaxPhysOps = 160;  // ops per pass after inserting lane transposes
-constexpr int kMaxMats = 32;      // 2x2 matrices per pass
-constexpr int kMaxGradSlots = 16; // parameterised gates per pass
+constexpr int kMaxWindow = 7;     // qubits fused per pass (specialised kernels)
+static_assert(kMaxWindow == VQE_MAX_WINDOW, "public and internal window limits differ");
+constexpr int kInterpWindow = 5;  // qubits fused per pass by the interpreted kernels
+constexpr int kMaxOps = 64;       // logical kernel ops per pass of an interpreted plan
+constexpr int kMaxPhysOps = 160;  // ops per interpreted pass after inserting lane transposes
+constexpr int kMaxMats = 32;      // 2x2 matrices per interpreted pass (kernel arguments)
+constexpr int kMaxGradSlots = 24; // parameterised gates per pass (any plan)
+constexpr int kInterpGradSlots = 16;  // ... of an interpreted pass (LDS accumulators)
 constexpr int kBlock = 256;       // threads per block of every streaming kernel
 constexpr int kMaxBlocks = 2048;  // grid-stride kernels use at most this many blocks
 constexpr int kMaxPartBlocks = 1 << 17;  // blocks writing per-block partial sums
 constexpr int kTileBits = 10;     // amplitudes per Hamiltonian tile = 2^kTileBits
+
+// Per-pass limits of the fusion planner.
+struct PlanLimits {
+    int kmax;   // window qubits
+    int ops;    // logical ops (gates + gradient terms)
+    int mats;   // gates carrying a 2x2 matrix
+    int slots;  // distinct parameters (gradient slots)
+};
+// Interpreted kernels: ops and matrices travel as kernel arguments.
+constexpr PlanLimits kInterpLimits = {kInterpWindow, kMaxOps, kMaxMats, kInterpGradSlots};
+// Specialised kernels: ops are compiled in, matrices read from a device table,
+// gradient slots accumulate in registers (2 VGPRs each in FP64).
+constexpr PlanLimits kJitLimits = {kMaxWindow, 96, 64, kMaxGradSlots};
 
 // ---------------------------------------------------------------- kernel ops
 // A fused pass is a list of ops on the local bits 0..K-1 of a window.
@@ -66,13 +80,28 @@ struct PassArgs {
     Mat2<T> mats[kMaxMats];
 };
 
-// Lane-split bits of a window pass, chosen so that the coset held per thread
-// (two vectors in the reverse pass) fits the register budget at >= 3 waves
-// per SIMD: 5-qubit windows split 0 (complex64 forward), 1 (complex64
-// reverse, complex128 forward) or 2 (complex128 reverse) bits.
-inline int split_bits_for(bool is_double, int K, bool two_vectors) {
-    if (K != 5) return 0;
-    return (is_double ? 1 : 0) + (two_vectors ? 1 : 0);
+// Arguments of a specialised (run-time compiled) window kernel; its ops are
+// compiled in and its matrices come from a device table.
+struct JitArgs {
+    uint64_t n_cosets;
+    uint32_t pos[kMaxWindow];      // window qubits, ascending
+    uint32_t pos_in[kMaxWindow];   // qubit held by physical slot s at load
+    uint32_t pos_out[kMaxWindow];  // ... and at store
+};
+
+// Lane-split bits S of a window pass: S of the K window bits live in lane bits
+// 6-S .. 5, the other K-S in registers.  Specialised kernels keep
+// K-S = 6 (complex64 forward), 5 (complex64 reverse, complex128 forward) or
+// 4 (complex128 reverse): 128 VGPRs of state per thread.  Measured at 32
+// qubits with 7-qubit windows, one more register bit (and one lane bit less)
+// than a 64-VGPR state is 13-15% faster per evaluation: fewer lane
+// transposes and longer contiguous runs per load outweigh the lower
+// occupancy.  Interpreted kernels split 5-qubit windows only, to
+// K-S = 5 / 4 / 4 / 3 (their op dispatch needs the smaller state).
+inline int split_bits_for(bool jit, bool is_double, int K, bool two_vectors) {
+    const int kl = (jit ? 6 : 5) - (is_double ? 1 : 0) - (two_vectors ? 1 : 0);
+    if (!jit && K != kInterpWindow) return 0;
+    return K > kl ? K - kl : 0;
 }
 
 // ---------------------------------------------------------------- Hamiltonian tables
@@ -125,22 +154,25 @@ hipError_t launch_set_basis(int dtype, void* psi, uint64_t dim, uint64_t b, hipS
 hipError_t launch_zero(double* p, uint64_t n, hipStream_t st);
 hipError_t launch_copy(int dtype, const void* src, void* dst, uint64_t dim, hipStream_t st);
 
-// in == out allowed (in place).  n = qubits of the state.  jit: specialised
-// kernel for this pass (hipFunction_t, see jit.cpp) or nullptr for the
-// interpreted kernel; passes that stage through LDS always run interpreted.
+// Interpreted window passes (K <= kInterpWindow).  in == out allowed (in
+// place).  n = qubits of the state.
 template <typename T>
-hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, void* jit, hipStream_t st);
+hipError_t launch_window_fwd(const PassArgs<T>& a, int n, const void* in, void* out, hipStream_t st);
 
 // Reverse pass on (psi, lam); writes per-block gradient partials
 // [blocks][n_gslots] into gpart.  Returns the block count used via *nblocks.
 template <typename T>
 hipError_t launch_window_rev(const PassArgs<T>& a, int n, const void* psi_in, void* psi_out,
                              const void* lam_in, void* lam_out, double* gpart,
-                             uint32_t* nblocks, void* jit, hipStream_t st);
+                             uint32_t* nblocks, hipStream_t st);
 
-// True if the pass runs in the LDS-staged mode (never specialised).
-template <typename T>
-bool window_uses_lds(const PassArgs<T>& a, int n, bool reverse);
+// Specialised kernel launch (fn = hipFunction_t of the pass, see jit.cpp):
+// S lane-split bits, mats = this pass's matrix table on the device; reverse
+// passes use the persistent grid and report its block count in *nblocks.
+hipError_t launch_window_jit(void* fn, const JitArgs& a, int S, const void* mats, bool reverse, const void* in0,
+                             void* out0, const void* in1, void* out1, double* gpart, uint32_t* nblocks,
+                             hipStream_t st);
+
 
 // ---------------------------------------------------------------- specialised kernels (jit.cpp)
 int jit_mode();
@@ -182,8 +214,8 @@ struct PlannedPass {
 };
 
 // Partition gates into fused passes.  Returns false (with msg) on failure.
-// kmax = largest window (<= kMaxWindow).
-bool plan_passes(int n, const std::vector<Gate>& gates, int kmax, std::vector<PlannedPass>& out,
+// lim.kmax = largest window (<= kMaxWindow).
+bool plan_passes(int n, const std::vector<Gate>& gates, const PlanLimits& lim, std::vector<PlannedPass>& out,
                  std::string& msg);
 
 // ---------------------------------------------------------------- errors

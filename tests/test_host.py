@@ -32,6 +32,20 @@ def test_library_exports_header_symbols():
     assert declared == set(_lib.exported_symbols())
 
 
+def test_binding_constants_match_header():
+    """Every #define VQE_<NAME> <int> of the header that the binding mirrors
+    (as <NAME> or VQE_<NAME>) has the same value there."""
+    hdr = open(os.path.join(ROOT, "include", "vqe.h")).read()
+    defs = dict(re.findall(r"^#define\s+VQE_(\w+)\s+(-?\d+)\b", hdr, flags=re.M))
+    checked = 0
+    for name, val in defs.items():
+        for py in (name, "VQE_" + name):
+            if hasattr(_lib, py):
+                assert getattr(_lib, py) == int(val), py
+                checked += 1
+    assert checked >= 15
+
+
 def _oracle_masks(H):
     return oham.to_masks(H)
 
@@ -159,9 +173,24 @@ def random_circuit(n, n_gates, seed):
     return ansatz.gates_array(gates), p
 
 
+@pytest.fixture
+def specialize_mode():
+    """Sets the kernel form for one test (plans differ: windows <= 5 qubits
+    interpreted, <= 7 specialised) and restores the default afterwards."""
+    modes = []
+
+    def set_mode(m):
+        modes.append(_lib.vqe_set_specialize(m))
+    yield set_mode
+    if modes:
+        _lib.vqe_set_specialize(modes[0])
+
+
+@pytest.mark.parametrize("mode,kmax", [(_lib.SPECIALIZE_NEVER, 5), (_lib.SPECIALIZE_ALWAYS, 7)])
 @pytest.mark.parametrize("n,kind,seed", [(8, "layered", 0), (13, "layered", 1), (7, "random", 2), (9, "random", 3),
                                          (1, "random", 4), (2, "random", 5)])
-def test_plan_is_valid_reordering(n, kind, seed):
+def test_plan_is_valid_reordering(n, kind, seed, mode, kmax, specialize_mode):
+    specialize_mode(mode)
     if kind == "layered":
         arr = ansatz.layered(n, 3)
         P = 6 * n
@@ -172,7 +201,7 @@ def test_plan_is_valid_reordering(n, kind, seed):
         og = _oracle_gates(arr)
         th = synth.theta(seed, max(P, 1))
         ref = osv.run(n, og, th)
-        for dtype, kmax in ((_lib.VQE_C64, 5), (_lib.VQE_C128, 5)):
+        for dtype in (_lib.VQE_C64, _lib.VQE_C128):
             order = []
             p = 0
             while True:
@@ -195,12 +224,21 @@ def test_plan_is_valid_reordering(n, kind, seed):
         _lib.vqe_circuit_free(c)
 
 
-def test_plan_pass_counts_beat_layerwise():
-    for n, L in ((20, 8), (28, 16), (32, 8)):
+def test_plan_pass_counts_beat_layerwise(specialize_mode):
+    """Layer-by-layer fusion needs ceil((n-1)/(K-1)) passes per layer for the
+    CNOT ladder; the planner pipelines layers.  Interpreted plans (K <= 5)
+    and specialised plans (K <= 7) of the layered ansatz, pass counts of the
+    planner as built (regression values)."""
+    expect = {(20, 8): (25, 15), (28, 16): (74, 43), (32, 8): (41, 23)}
+    for (n, L), (n_interp, n_spec) in expect.items():
         c = _lib.vqe_circuit_create(n, ansatz.layered(n, L))
-        _, npass = _lib.vqe_circuit_info(c)
+        specialize_mode(_lib.SPECIALIZE_NEVER)
+        _, np_i = _lib.vqe_circuit_info(c)
+        specialize_mode(_lib.SPECIALIZE_ALWAYS)
+        _, np_s = _lib.vqe_circuit_info(c)
         _lib.vqe_circuit_free(c)
-        assert npass <= L * math.ceil((n - 1) / 4)
+        assert np_i <= L * math.ceil((n - 1) / 4) and np_i <= n_interp
+        assert np_s <= L * math.ceil((n - 1) / 6) and np_s <= n_spec
 
 
 def test_abi_argument_errors():
