@@ -39,11 +39,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("kernels.hip", "jit.cpp", "api.cpp", "plan.cpp", "vqe_internal.h")
+
+
+def kernel_sources_sha256():
+    """Digest of every source that shapes the window kernels (the interpreted
+    kernels, the generator of the specialised ones, planning and lowering)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2402_11878_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel="window_rev", record="profiles/window_rev_hubbard4x4_32q_c128_traffic.txt"):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE record (copy-calibrated), or None when the kernel
+    FETCH_SIZE / WRITE_SIZE record (copy-calibrated), or None when a kernel
     source has changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, record)
     if not os.path.exists(path):
         return None
@@ -53,9 +65,7 @@ def measured_traffic(kernel="window_rev", record="profiles/window_rev_hubbard4x4
             continue
         k, v = line.split(":", 1)
         kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2402_11878_amd", "csrc", "kernels.hip")
-    now = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("kernel") != kernel or kv.get("kernels_sha256") != now:
+    if kv.get("kernel") != kernel or kv.get("sources_sha256") != kernel_sources_sha256():
         return None
     return float(kv["traffic_bytes_per_launch"])
 

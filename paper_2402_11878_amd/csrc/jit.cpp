@@ -12,7 +12,8 @@
 //     time and cost no instruction;
 //   * 2x2 ops, phases and gradient terms are written per register pair with
 //     the pair indices known;
-//   * lane-split transposes are single permlane swaps on named registers.
+//   * lane-split transposes are permlane swaps (lane bits 4, 5) or DPP moves
+//     with a select (lane bits 2, 3) on named registers.
 // Window positions stay kernel arguments and matrices come from a device
 // table filled per evaluation, so passes with equal op lists share a kernel.
 // Windows of up to 7 qubits are split over lane bits 2..5 (see split_bits_for).
@@ -247,7 +248,7 @@ std::string offset_expr(const char* arr, int p, int KL) {
 
 bool compile(const std::string& src, std::vector<char>& code, std::string& log) {
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "vqe_pass.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+    if (hiprtcCreateProgram(&prog, src.c_str(), "vqe_window.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
         log = "hiprtcCreateProgram failed";
         return false;
     }
@@ -273,6 +274,11 @@ bool compile(const std::string& src, std::vector<char>& code, std::string& log) 
 
 }  // namespace
 
+const char* jit_kernel_name(int NV, bool dbl) {
+    return NV == 2 ? (dbl ? "vqe_window_rev_c128" : "vqe_window_rev_c64")
+                   : (dbl ? "vqe_window_fwd_c128" : "vqe_window_fwd_c64");
+}
+
 int jit_mode() { return g_mode.load(); }
 
 int jit_set_mode(int mode) { return g_mode.exchange(mode); }
@@ -290,7 +296,7 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
     std::ostringstream& o = g.o;
     o << prelude(dbl);
     o << "extern \"C\" __global__ void __launch_bounds__(" << kBlock << ")\n"
-      << "vqe_pass(const JitArgs a, const Mat2* __restrict__ mats, u32 cpt, u32 interleave, u32 mlog, "
+      << jit_kernel_name(NV, dbl) << "(const JitArgs a, const Mat2* __restrict__ mats, u32 cpt, u32 interleave, u32 mlog, "
          "const V* __restrict__ in0, V* __restrict__ out0, const V* __restrict__ in1, V* __restrict__ out1, "
          "double* __restrict__ gpart) {\n"
       << "  const int tid = threadIdx.x;\n  const int lane = tid & 63;\n"
@@ -383,8 +389,17 @@ int jit_prepare(const std::vector<std::string>& srcs, std::vector<void*>& fns, s
             return VQE_ERR_STATE;
         }
         Entry e;
+        const char* name = nullptr;
+        for (int nv = 1; nv <= 2 && !name; ++nv)
+            for (int dbl = 0; dbl < 2 && !name; ++dbl)
+                if (todo[i]->find(std::string(jit_kernel_name(nv, dbl)) + "(") != std::string::npos)
+                    name = jit_kernel_name(nv, dbl);
+        if (!name) {
+            err = "specialised pass kernel without a known symbol (internal error)";
+            return VQE_ERR_STATE;
+        }
         if (hipModuleLoadData(&e.mod, codes[i].data()) != hipSuccess ||
-            hipModuleGetFunction(&e.fn, e.mod, "vqe_pass") != hipSuccess) {
+            hipModuleGetFunction(&e.fn, e.mod, name) != hipSuccess) {
             err = "loading a specialised pass kernel failed";
             return VQE_ERR_DEVICE;
         }

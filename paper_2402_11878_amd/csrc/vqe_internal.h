@@ -177,6 +177,8 @@ hipError_t launch_window_jit(void* fn, const JitArgs& a, int S, const void* mats
 // ---------------------------------------------------------------- specialised kernels (jit.cpp)
 int jit_mode();
 int jit_set_mode(int mode);
+// Kernel symbol of a generated pass: vqe_window_{fwd,rev}_{c64,c128}.
+const char* jit_kernel_name(int NV, bool dbl);
 // HIP source of the specialised kernel of one pass: K window bits, S lane-split
 // bits, NV = 1 (forward) or 2 (reverse, psi and lam), ops on physical slots.
 std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& ops, uint32_t n_gslots);
