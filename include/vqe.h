@@ -272,6 +272,15 @@ int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* byt
 #define VQE_SPECIALIZE_AUTO_MIN_QUBITS 20
 int vqe_set_specialize(int mode);
 
+/* Compiles and loads, on the calling thread's current HIP device, the
+ * specialised kernels that an evaluation of `dtype` (VQE_C64 / VQE_C128)
+ * would use under the current kernel form; returns VQE_OK at once when that
+ * form is interpreted or the kernels are already loaded.  Evaluations do this
+ * themselves on first use: call it to keep compilation (about a second per
+ * distinct pass, in parallel) out of a latency-sensitive first evaluation,
+ * e.g. when a served instance is registered.  Errors as for evaluations. */
+int vqe_circuit_prepare(const vqe_circuit* c, int dtype);
+
 /* ------------------------------------------------------------------ slimming
  * Hamiltonian cutoff (Sec. II-D; terms sorted by |w|, small ones dropped).
  * Host only.  The identity term (x = z = 0) is always kept.  The order of

@@ -82,6 +82,7 @@ _SIGS = {
     "vqe_batch_free": (C.c_int, [_P]),
     "vqe_batch_energy_grad": (C.c_int, [_P, _SZ, C.POINTER(vqe_batch_item)]),
     "vqe_set_specialize": (C.c_int, [C.c_int]),
+    "vqe_circuit_prepare": (C.c_int, [_P, C.c_int]),
     "vqe_profile_enable": (C.c_int, [C.c_int]),
     "vqe_profile_reset": (C.c_int, []),
     "vqe_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -259,6 +260,11 @@ def vqe_set_specialize(mode):
     if r < 0:
         check("vqe_set_specialize", r)
     return r
+
+
+def vqe_circuit_prepare(c, dtype):
+    """Compiles/loads the specialised kernels an evaluation of dtype would use (no-op otherwise)."""
+    check("vqe_circuit_prepare", lib().vqe_circuit_prepare(c, dtype))
 
 
 def vqe_profile_enable(on=True):

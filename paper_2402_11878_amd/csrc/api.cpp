@@ -1500,6 +1500,18 @@ int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* it
     VQE_GUARD_END
 }
 
+int vqe_circuit_prepare(const vqe_circuit* c, int dtype) {
+    VQE_GUARD_BEGIN
+    if (!c || (dtype != VQE_C64 && dtype != VQE_C128)) {
+        set_error("vqe_circuit_prepare: null circuit or bad dtype");
+        return VQE_ERR_ARG;
+    }
+    const Plan& pl = plan_now(c);
+    if (!pl.jit) return VQE_OK;
+    return ensure_jit(c, pl, dtype == VQE_C128 ? 1 : 0);
+    VQE_GUARD_END
+}
+
 int vqe_set_specialize(int mode) {
     if (mode != VQE_SPECIALIZE_NEVER && mode != VQE_SPECIALIZE_AUTO && mode != VQE_SPECIALIZE_ALWAYS) {
         vqe::set_error("vqe_set_specialize: unknown mode");

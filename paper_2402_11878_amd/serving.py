@@ -98,6 +98,9 @@ class Server:
         inst.footprint = self.ex.footprint(inst)
         if not self.ex.is_small(inst) and inst.footprint > self.budget:
             raise ValueError(f"instance {iid} needs {inst.footprint} bytes, more than the budget {self.budget}")
+        prepare = getattr(self.ex, "prepare", None)
+        if prepare is not None:
+            prepare(inst)  # kernel compilation stays out of the instance's first request
         with self._cv:
             self.instances[iid] = inst
         return inst
@@ -240,6 +243,10 @@ class GpuExecutor:
 
     def is_small(self, inst):
         return inst.n <= self.small_n_max
+
+    def prepare(self, inst):
+        if not self.is_small(inst):
+            self.L.vqe_circuit_prepare(inst.circuit.handle, self.dtype)
 
     def footprint(self, inst):
         # resident vectors: psi, lam and the checkpoints (8 * 2^n bytes per complex64 vector)

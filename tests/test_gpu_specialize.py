@@ -143,3 +143,32 @@ def test_auto_mode_at_20_qubits(dt):
         s.free(), l.free()
         _lib.vqe_circuit_free(c)
         _lib.vqe_hamiltonian_free(h)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_prepare_then_evaluate(dt):
+    """Kernels compiled ahead by vqe_circuit_prepare serve the evaluation:
+    same energy and gradient bits as an evaluation that compiles on first use."""
+    dtype = DT[dt]
+    n = 11
+    arr, P = random_circuit(n, 90, 77)
+    th = synth.theta(77, P)
+    H = _random_pauli_sum(n, 20, 77)
+    x, z, w = oham.to_masks(H)
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    _lib.vqe_set_specialize(_lib.SPECIALIZE_ALWAYS)
+    c1 = _lib.vqe_circuit_create(n, arr)
+    c2 = _lib.vqe_circuit_create(n, arr)
+    s, l = Dev(n, dtype), Dev(n, dtype)
+    say(f"case prepare n={n} {dt}")
+    try:
+        _lib.vqe_circuit_prepare(c1, dtype)
+        _lib.vqe_circuit_prepare(c1, dtype)  # second call: already loaded
+        E1, g1 = _lib.vqe_energy_grad(s.h, l.h, c1, th, h)
+        E2, g2 = _lib.vqe_energy_grad(s.h, l.h, c2, th, h)
+        assert E1 == E2 and np.array_equal(g1, g2)
+    finally:
+        s.free(), l.free()
+        _lib.vqe_circuit_free(c1)
+        _lib.vqe_circuit_free(c2)
+        _lib.vqe_hamiltonian_free(h)

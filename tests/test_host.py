@@ -224,6 +224,26 @@ def test_plan_is_valid_reordering(n, kind, seed, mode, kmax, specialize_mode):
         _lib.vqe_circuit_free(c)
 
 
+def test_circuit_prepare_host_paths(specialize_mode):
+    """vqe_circuit_prepare: bad dtype is an argument error; with interpreted
+    kernels it is a no-op that needs no device; with specialised kernels and
+    no device it reports the missing device."""
+    c = _lib.vqe_circuit_create(6, ansatz.layered(6, 2))
+    try:
+        with pytest.raises(_lib.VqeError) as e:
+            _lib.vqe_circuit_prepare(c, 7)
+        assert e.value.code == _lib.VQE_ERR_ARG
+        specialize_mode(_lib.SPECIALIZE_NEVER)
+        _lib.vqe_circuit_prepare(c, _lib.VQE_C64)
+        if _lib.vqe_device_count() == 0:
+            specialize_mode(_lib.SPECIALIZE_ALWAYS)
+            with pytest.raises(_lib.VqeError) as e:
+                _lib.vqe_circuit_prepare(c, _lib.VQE_C128)
+            assert e.value.code == _lib.VQE_ERR_DEVICE
+    finally:
+        _lib.vqe_circuit_free(c)
+
+
 def test_plan_pass_counts_beat_layerwise(specialize_mode):
     """Layer-by-layer fusion needs ceil((n-1)/(K-1)) passes per layer for the
     CNOT ladder; the planner pipelines layers.  Interpreted plans (K <= 5)
