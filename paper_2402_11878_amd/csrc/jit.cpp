@@ -296,7 +296,7 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
     std::ostringstream& o = g.o;
     o << prelude(dbl);
     o << "extern \"C\" __global__ void __launch_bounds__(" << kBlock << ")\n"
-      << jit_kernel_name(NV, dbl) << "(const JitArgs a, const Mat2* __restrict__ mats, u32 cpt, u32 interleave, u32 mlog, "
+      << jit_kernel_name(NV, dbl) << "(const JitArgs a, const Mat2* __restrict__ mats, u32 cpt, u32 mlog, "
          "const V* __restrict__ in0, V* __restrict__ out0, const V* __restrict__ in1, V* __restrict__ out1, "
          "double* __restrict__ gpart) {\n"
       << "  const int tid = threadIdx.x;\n  const int lane = tid & 63;\n"
@@ -310,8 +310,7 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
           << "  if (h" << j << ") { half_in += bv_in[" << g.KL + j << "]; half_out += bv_out[" << g.KL + j << "]; }\n";
     for (uint32_t s = 0; s < n_gslots; ++s) o << "  double g" << s << " = 0.0;\n";
     o << "  for (u32 it = 0; it < cpt; ++it) {\n"
-      << "    const u64 blk = xcd_order(interleave ? (u64)it * gridDim.x + blockIdx.x : (u64)blockIdx.x * cpt + it, "
-         "mlog);\n"
+      << "    const u64 blk = xcd_order((u64)blockIdx.x * cpt + it, mlog);\n"
       << "    const u64 c = blk * " << PER_BLOCK << " + sub;\n"
       << "    if (c >= a.n_cosets) break;\n"
       << "    u64 base = c;\n"

@@ -424,12 +424,12 @@ __device__ __forceinline__ uint64_t pattern_offset(const uint64_t (&bitval)[K], 
 
 // Direct mode: every window qubit is >= 6, so consecutive lanes hold
 // consecutive cosets at consecutive addresses.  Each thread handles cpt
-// cosets: block-contiguous for one-shot grids (forward passes), interleaved
-// across the grid for persistent grids (reverse passes, whose per-block
-// gradient reduction is amortised over many cosets).
+// cosets: one for one-shot grids (forward passes), a block-contiguous run for
+// persistent grids (reverse passes, whose per-block gradient reduction is
+// amortised over many cosets).
 template <typename T, int K, int NV>
 __global__ void __launch_bounds__(kBlock)
-window_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t mlog,
+window_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t mlog,
               const typename VecOf<T>::type* __restrict__ in0,
               typename VecOf<T>::type* __restrict__ out0,
               const typename VecOf<T>::type* __restrict__ in1,
@@ -445,10 +445,10 @@ window_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t m
 #pragma unroll
     for (int j = 0; j < K; ++j) bitval[j] = 1ull << a.pos[j];
     for (uint32_t it = 0; it < cpt; ++it) {
-        // block-contiguous (one-shot grids) or interleaved (persistent grids),
-        // then XCD-aware (mlog = log2 of the number of kBlock-coset units)
+        // block-contiguous units, then XCD-aware (mlog = log2 of the number
+        // of kBlock-coset units)
         const uint64_t blk = xcd_order(
-            interleave ? (uint64_t)it * gridDim.x + blockIdx.x : (uint64_t)blockIdx.x * cpt + it, mlog);
+(uint64_t)blockIdx.x * cpt + it, mlog);
         const uint64_t c = blk * kBlock + tid;
         if (c >= a.n_cosets) break;
         uint64_t base = c;
@@ -508,7 +508,7 @@ window_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t m
 // coset would not fit the register budget (the reverse pass holds psi and lam).
 template <typename T, int K, int S, int NV>
 __global__ void __launch_bounds__(kBlock)
-window_split_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint32_t mlog,
+window_split_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t mlog,
                     const typename VecOf<T>::type* __restrict__ in0, typename VecOf<T>::type* __restrict__ out0,
                     const typename VecOf<T>::type* __restrict__ in1, typename VecOf<T>::type* __restrict__ out1,
                     double* __restrict__ gpart) {
@@ -541,7 +541,7 @@ window_split_kernel(const PassArgs<T> a, uint32_t cpt, uint32_t interleave, uint
     }
     for (uint32_t it = 0; it < cpt; ++it) {
         const uint64_t blk = xcd_order(
-            interleave ? (uint64_t)it * gridDim.x + blockIdx.x : (uint64_t)blockIdx.x * cpt + it, mlog);
+(uint64_t)blockIdx.x * cpt + it, mlog);
         const uint64_t c = blk * PER_BLOCK + sub;
         if (c >= a.n_cosets) break;
         uint64_t base = c;
@@ -619,7 +619,7 @@ __device__ __forceinline__ uint32_t lds_slot(uint32_t u) { return u ^ ((u >> 5) 
 
 template <typename T, int K, int NV>
 __global__ void __launch_bounds__(kBlock)
-window_lds_kernel(const PassArgs<T> a, const LdsMap m, uint32_t cpt, uint32_t interleave, uint32_t mlog,
+window_lds_kernel(const PassArgs<T> a, const LdsMap m, uint32_t cpt, uint32_t mlog,
                   const typename VecOf<T>::type* __restrict__ in0,
                   typename VecOf<T>::type* __restrict__ out0,
                   const typename VecOf<T>::type* __restrict__ in1,
@@ -644,7 +644,7 @@ window_lds_kernel(const PassArgs<T> a, const LdsMap m, uint32_t cpt, uint32_t in
     // Every wave of the block runs the same cpt iterations (uniform barriers).
     for (uint32_t it = 0; it < cpt; ++it) {
         const uint64_t blk = xcd_order(
-            interleave ? (uint64_t)it * gridDim.x + blockIdx.x : (uint64_t)blockIdx.x * cpt + it, mlog);
+(uint64_t)blockIdx.x * cpt + it, mlog);
         const uint64_t ch = blk * WAVES + wv;
         const bool live = ch < m.n_chunks;
         // chunk base: insert zeros at the U positions
@@ -951,7 +951,7 @@ struct WinShape {
     bool lds;
     int split;  // lane-split bits S (0: plain direct or LDS mode)
     LdsMap m;
-    uint32_t cpt, grid, interleave, mlog;
+    uint32_t cpt, grid, mlog;
 };
 
 
@@ -966,11 +966,9 @@ void grid_for_units(uint64_t units, bool persistent, WinShape& w) {
         const uint64_t g = units < kRevBlocks ? units : kRevBlocks;
         w.grid = (uint32_t)(g ? g : 1);
         w.cpt = (uint32_t)((units + w.grid - 1) / w.grid);
-        w.interleave = 1;
     } else {
         w.grid = (uint32_t)(units ? units : 1);
         w.cpt = 1;
-        w.interleave = 0;
     }
 }
 
@@ -1037,17 +1035,17 @@ hipError_t launch_window(const PassArgs<T>& a, int n, const void* in0, void* out
         if (w.split == 1) {                                                                              \
             if constexpr (KK == 5)                                                                       \
                 hipLaunchKernelGGL((window_split_kernel<T, KK, 1, NV>), dim3(w.grid), dim3(kBlock), 0, st, \
-                                   a, w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);               \
+                                   a, w.cpt, w.mlog, i0, o0, i1, o1, gpart);               \
         } else if (w.split == 2) {                                                                       \
             if constexpr (KK == 5)                                                                       \
                 hipLaunchKernelGGL((window_split_kernel<T, KK, 2, NV>), dim3(w.grid), dim3(kBlock), 0, st, \
-                                   a, w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);               \
+                                   a, w.cpt, w.mlog, i0, o0, i1, o1, gpart);               \
         } else if (w.lds)                                                                                \
             hipLaunchKernelGGL((window_lds_kernel<T, KK, NV>), dim3(w.grid), dim3(kBlock), 0, st, a, w.m, \
-                               w.cpt, w.interleave, w.mlog, i0, o0, i1, o1, gpart);                      \
+                               w.cpt, w.mlog, i0, o0, i1, o1, gpart);                      \
         else                                                                                             \
             hipLaunchKernelGGL((window_kernel<T, KK, NV>), dim3(w.grid), dim3(kBlock), 0, st, a, w.cpt, \
-                               w.interleave, w.mlog, i0, o0, i1, o1, gpart);                             \
+                               w.mlog, i0, o0, i1, o1, gpart);                             \
         break;
     switch (a.K) {
         VQE_WIN(1)
@@ -1082,8 +1080,8 @@ hipError_t launch_window_jit(void* fn, const JitArgs& a, int S, const void* mats
     grid_for_units((a.n_cosets + per_unit - 1) / per_unit, reverse, w);
     if (nblocks) *nblocks = w.grid;
     JitArgs ka = a;
-    uint32_t cpt = w.cpt, interleave = w.interleave, mlog = w.mlog;
-    void* params[] = {&ka, (void*)&mats, &cpt, &interleave, &mlog, (void*)&in0, (void*)&out0,
+    uint32_t cpt = w.cpt, mlog = w.mlog;
+    void* params[] = {&ka, (void*)&mats, &cpt, &mlog, (void*)&in0, (void*)&out0,
                       (void*)&in1, (void*)&out1, (void*)&gpart};
     return hipModuleLaunchKernel((hipFunction_t)fn, w.grid, 1, 1, kBlock, 1, 1, 0, st, params, nullptr);
 }

@@ -168,7 +168,7 @@ hipError_t launch_window_rev(const PassArgs<T>& a, int n, const void* psi_in, vo
 
 // Specialised kernel launch (fn = hipFunction_t of the pass, see jit.cpp):
 // S lane-split bits, mats = this pass's matrix table on the device; reverse
-// passes use the persistent grid and report its block count in *nblocks.
+// passes use the persistent grid; *nblocks = blocks used.
 hipError_t launch_window_jit(void* fn, const JitArgs& a, int S, const void* mats, bool reverse, const void* in0,
                              void* out0, const void* in1, void* out1, double* gpart, uint32_t* nblocks,
                              hipStream_t st);
