@@ -284,3 +284,23 @@ def test_abi_argument_errors():
         assert e.value.code == _lib.VQE_ERR_DEVICE
     with pytest.raises(_lib.VqeError):
         _lib.vqe_state_alloc(4, 7)
+
+
+def test_molecule_10_slimming_matches_golden():
+    """Library Jordan-Wigner + slimming of the 20-qubit molecule-shaped
+    Hamiltonian against the oracle's stored counts per cutoff threshold
+    (tests/golden/molecule_10.json, written from oracle/ only)."""
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "molecule_10.json")) as f:
+        ref = json.load(f)
+    wl = synth.WORKLOADS["molecule_10"]
+    h, g = synth.molecule_integrals(wl.n_orb, wl.integral_seed)
+    x, z, w = lham.molecule(h, g)
+    assert len(w) == ref["n_terms_full"]
+    assert abs(w[(x == 0) & (z == 0)].sum() - ref["identity"]) <= 1e-12
+    for key, r in ref["thresholds"].items():
+        keep, n_kept, dropped = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_THRESHOLD, float(key))
+        k = keep == 1
+        assert n_kept == r["n_terms"]
+        assert len(set(x[k].tolist())) == r["n_groups"]
+        assert abs(dropped - r["dropped_abs_sum"]) <= 1e-12 * max(1.0, r["dropped_abs_sum"])
