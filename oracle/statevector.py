@@ -11,8 +11,21 @@ Conventions (the paper, whose ansatz is built from S/D excitation gate sets
   RZ(t) = exp(-i t Z/2) = diag(e^{-it/2}, e^{+it/2});
   RX(t) = exp(-i t X/2) = [[c, -is], [-is, c]];
   CNOT(c -> t) maps |b> to |b xor (b_c << t)>;  CZ(a, b) = (-1)^{b_a b_b}.
-A circuit is a list of gates (kind, q0, q1, param_index, angle); a gate with
-param_index >= 0 takes its angle from the parameter vector, else ``angle``.
+The paper's excitation gate sets (eq. 5; one- and two-electron excitations in
+the style of the gate-fabric ansatz) are read as particle-number-conserving
+real rotations by t/2 inside a two-state subspace, without Jordan-Wigner
+strings:
+  SEXC(t) on qubits (p, q): A = {b_p = 1, b_q = 0}, B = {b_p = 0, b_q = 1};
+  DEXC(t) on qubits (p, q, r, s): A = {b_p = b_q = 1, b_r = b_s = 0},
+                                  B = {b_p = b_q = 0, b_r = b_s = 1};
+  for every pair (a in A, a' = a with the A bits replaced by the B bits):
+      psi'[a] = c psi[a] - s psi[a'],  psi'[a'] = s psi[a] + c psi[a'];
+  all other amplitudes unchanged.  R(t) = exp(-i t G / 2) with
+  G = i(|B><A| - |A><B|) on each pair, whose eigenvalues are 0 and +-1.
+A circuit is a list of gates (kind, q0, q1, param_index, angle); for SEXC and
+DEXC the q0 slot holds the tuple of qubits (p, q) or (p, q, r, s) and q1 is -1.
+A gate with param_index >= 0 takes its angle from the parameter vector, else
+``angle``.
 """
 from __future__ import annotations
 
@@ -21,7 +34,9 @@ import math
 import numpy as np
 
 RY, RZ, RX, H, X, CNOT, CZ = "RY", "RZ", "RX", "H", "X", "CNOT", "CZ"
+SEXC, DEXC = "SEXC", "DEXC"
 ROTATIONS = (RY, RZ, RX)
+EXCITATIONS = (SEXC, DEXC)
 
 
 def basis_state(n, b=0):
@@ -86,6 +101,42 @@ def apply_cz(psi, n, a, b):
     return psi
 
 
+def excitation_patterns(kind, qubits):
+    """(mask, A pattern, B pattern) of an excitation gate on `qubits`."""
+    bit = [1 << q for q in qubits]
+    if kind == SEXC:
+        p, q = bit
+        return p | q, p, q
+    p, q, r, s = bit
+    return p | q | r | s, p | q, r | s
+
+
+def apply_excitation(psi, n, kind, qubits, angle):
+    """Rotation by angle/2 between the A and B patterns (see the module docstring)."""
+    mask, A, B = excitation_patterns(kind, qubits)
+    idx = np.arange(1 << n, dtype=np.int64)
+    ia = idx[(idx & mask) == A]
+    ib = ia ^ A ^ B
+    c, s = math.cos(angle / 2.0), math.sin(angle / 2.0)
+    a = psi[ia].copy()
+    b = psi[ib].copy()
+    psi[ia] = c * a - s * b
+    psi[ib] = s * a + c * b
+    return psi
+
+
+def apply_excitation_generator(psi, n, kind, qubits):
+    """G psi with G = i(|B><A| - |A><B|) on every pair; zero elsewhere."""
+    mask, A, B = excitation_patterns(kind, qubits)
+    idx = np.arange(1 << n, dtype=np.int64)
+    ia = idx[(idx & mask) == A]
+    ib = ia ^ A ^ B
+    out = np.zeros_like(psi)
+    out[ib] = 1j * psi[ia]
+    out[ia] = -1j * psi[ib]
+    return out
+
+
 def gate_angle(g, params):
     kind, q0, q1, pidx, angle = g
     return params[pidx] if pidx >= 0 else angle
@@ -93,6 +144,9 @@ def gate_angle(g, params):
 
 def apply_gate(psi, n, g, params, inverse=False):
     kind, q0, q1, pidx, angle = g
+    if kind in EXCITATIONS:
+        t = gate_angle(g, params)
+        return apply_excitation(psi, n, kind, q0, -t if inverse else t)
     if kind == CNOT:
         return apply_cnot(psi, n, q0, q1)
     if kind == CZ:
@@ -109,6 +163,33 @@ def run(n, gates, params, psi=None):
     for g in gates:
         apply_gate(psi, n, g, params)
     return psi
+
+
+def hartree_fock_index(n_electrons):
+    """Basis index of the Hartree-Fock reference: spin-orbitals 0..N_e-1 occupied."""
+    return (1 << n_electrons) - 1
+
+
+def excitation_ansatz(n, n_electrons, layers=1):
+    """Spin-conserving single and double excitations from the occupied
+    spin-orbitals 0..N_e-1 (spin-orbital 2i + sigma) to the virtual ones,
+    singles first and then doubles (eq. 5 applies the D product after the S
+    product), repeated `layers` times with fresh parameters."""
+    occ = list(range(n_electrons))
+    vir = list(range(n_electrons, n))
+    singles = [(i, a) for i in occ for a in vir if (i - a) % 2 == 0]
+    doubles = [(i, j, a, b) for ii, i in enumerate(occ) for j in occ[ii + 1:]
+               for ai, a in enumerate(vir) for b in vir[ai + 1:]
+               if (i % 2 + j % 2) == (a % 2 + b % 2)]
+    gates, k = [], 0
+    for _ in range(layers):
+        for (i, a) in singles:
+            gates.append((SEXC, (i, a), -1, k, 0.0))
+            k += 1
+        for (i, j, a, b) in doubles:
+            gates.append((DEXC, (i, j, a, b), -1, k, 0.0))
+            k += 1
+    return gates
 
 
 def layered_ansatz(n, layers):

@@ -304,3 +304,109 @@ def test_slim_energy_bound():
         k = keep == 1
         E_slim, _ = expect.energy_masks(psi, n, x[k], z[k], w[k])
         assert slim.dropped_bound_check(E_full, E_slim, dropped)
+
+
+# ------------------------------------------------------------------ excitation gates (eq. 5)
+_P2 = {"I": np.eye(2), "X": np.array([[0, 1], [1, 0]]), "Y": np.array([[0, -1j], [1j, 0]]),
+       "Z": np.diag([1.0, -1.0]),
+       "+": np.array([[0, 0], [1, 0]]),    # |1><0| (raise the occupation)
+       "-": np.array([[0, 1], [0, 0]])}    # |0><1| (lower it)
+
+
+def _kron_ops(n, ops):
+    """Operator with ops[q] on qubit q (identity elsewhere); qubit n-1 leftmost."""
+    from functools import reduce
+    return reduce(np.kron, [_P2[ops.get(q, "I")] for q in reversed(range(n))]).astype(np.complex128)
+
+
+def test_single_excitation_is_exp_of_pauli_generator():
+    """SEXC(t) on (p, q) = expm(-i t G / 2) with G = (X_p Y_q - Y_p X_q)/2,
+    built from Pauli matrices (scipy's expm, not the oracle's pair loop)."""
+    from scipy.linalg import expm
+    n = 3
+    rng = np.random.default_rng(5)
+    for (p, q) in ((0, 1), (2, 0), (0, 2)):
+        G = 0.5 * (_kron_ops(n, {p: "X", q: "Y"}) - _kron_ops(n, {p: "Y", q: "X"}))
+        for t in (0.7, -2.1):
+            psi = rng.normal(size=8) + 1j * rng.normal(size=8)
+            ref = expm(-0.5j * t * G) @ psi
+            got = sv.apply_excitation(psi.copy(), n, sv.SEXC, (p, q), t)
+            assert np.max(np.abs(got - ref)) < 1e-13
+
+
+def test_double_excitation_is_exp_of_ladder_generator():
+    """DEXC(t) on (p, q, r, s) = expm(t K / 2) with K = s-_p s-_q s+_r s+_s - h.c.
+    (|1100> <-> |0011> on those qubits), built from ladder matrices."""
+    from scipy.linalg import expm
+    n = 5
+    rng = np.random.default_rng(6)
+    for (p, q, r, s) in ((0, 1, 2, 3), (4, 1, 0, 3), (2, 4, 1, 0)):
+        K = _kron_ops(n, {p: "-", q: "-", r: "+", s: "+"})
+        K = K - K.conj().T
+        for t in (1.1, -0.4):
+            psi = rng.normal(size=32) + 1j * rng.normal(size=32)
+            ref = expm(0.5 * t * K) @ psi
+            got = sv.apply_excitation(psi.copy(), n, sv.DEXC, (p, q, r, s), t)
+            assert np.max(np.abs(got - ref)) < 1e-13
+
+
+def test_excitation_closed_forms_and_conservation():
+    """On basis states: SEXC(t)|b_p=1,b_q=0> = cos(t/2)|..> + sin(t/2)|b_p=0,b_q=1>;
+    DEXC on |1100> likewise; every excitation circuit keeps particle number and
+    the up/down counts (spin-orbital 2i + sigma)."""
+    n, t = 6, 0.9
+    c, s = math.cos(t / 2), math.sin(t / 2)
+    psi = sv.apply_excitation(sv.basis_state(n, 0b000100), n, sv.SEXC, (2, 5), t)
+    assert abs(psi[0b000100] - c) < 1e-15 and abs(psi[0b100000] - s) < 1e-15
+    assert abs(np.linalg.norm(psi) - 1) < 1e-15
+    psi = sv.apply_excitation(sv.basis_state(n, 0b000011), n, sv.DEXC, (0, 1, 4, 5), t)
+    assert abs(psi[0b000011] - c) < 1e-15 and abs(psi[0b110000] - s) < 1e-15
+    gates = sv.excitation_ansatz(8, 4, layers=2)
+    th = synth.theta(3, len(gates))
+    psi = sv.run(8, gates, th, psi=sv.basis_state(8, sv.hartree_fock_index(4)))
+    idx = np.arange(256)
+    up = np.array([bin(b & 0x55).count("1") for b in idx])
+    dn = np.array([bin(b & 0xAA).count("1") for b in idx])
+    assert np.sum(np.abs(psi[(up != 2) | (dn != 2)]) ** 2) < 1e-28
+    assert abs(np.linalg.norm(psi) - 1) < 1e-14
+
+
+def test_excitation_gradients_three_ways():
+    """Four-term parameter shift (Anselmetti et al. 2021), central differences
+    and the adjoint sweep agree for an S/D circuit from the Hartree-Fock state."""
+    n, ne = 8, 4
+    h, g = synth.molecule_integrals(4, 3)
+    H = ham.molecule(h, g)
+    gates = sv.excitation_ansatz(n, ne)
+    th = synth.theta(8, len(gates)) * 0.5
+    psi0 = sv.basis_state(n, sv.hartree_fock_index(ne))
+    gates_hf = [("X", q, -1, -1, 0.0) for q in range(ne)] + gates
+    E, g_adj = grad.adjoint(n, gates_hf, th, H)
+    ps = grad.param_shift(n, gates_hf, th, H)
+    fd = grad.finite_diff(n, gates_hf, th, H, indices=range(0, len(th), 4))
+    g_ps = np.array([ps[k] for k in range(len(th))])
+    assert np.max(np.abs(g_adj - g_ps)) < 1e-12
+    for k, v in fd.items():
+        assert abs(v - g_adj[k]) < 1e-7
+    assert abs(E - expect.energy(sv.run(n, gates, th, psi=psi0), n, H)[0]) < 1e-13
+
+
+def test_excitation_vqe_reaches_sector_ground_state():
+    """2 electrons in 2 spatial orbitals (4 qubits, one up and one down): the
+    S/D ansatz from Hartree-Fock spans the real states of that sector, so
+    minimising E(theta) reaches the lowest eigenvalue of H restricted to the
+    sector (dense diagonalisation); every theta stays above it."""
+    from scipy.optimize import minimize
+    n, ne = 4, 2
+    h, g = synth.molecule_integrals(2, 11)
+    H = ham.molecule(h, g)
+    M = ed.dense(H, n)
+    sector = [b for b in range(16) if bin(b & 0x5).count("1") == 1 and bin(b & 0xA).count("1") == 1]
+    E0 = np.linalg.eigvalsh(M[np.ix_(sector, sector)]).min()
+    gates = [("X", q, -1, -1, 0.0) for q in range(ne)] + sv.excitation_ansatz(n, ne)
+    P = 1 + max(gt[3] for gt in gates)
+    f = lambda t: expect.energy(sv.run(n, gates, t), n, H)[0]
+    for seed in range(3):
+        assert f(synth.theta(seed, P)) >= E0 - 1e-12
+    best = minimize(f, np.zeros(P) + 0.1, method="BFGS", options={"gtol": 1e-10})
+    assert abs(best.fun - E0) < 1e-9
