@@ -63,6 +63,21 @@ extern "C" {
 #define VQE_GATE_X     4
 #define VQE_GATE_CNOT  5   /* q0 = control, q1 = target */
 #define VQE_GATE_CZ    6
+/* Excitation gate sets of the paper's ansatz (eq. 5): particle-conserving
+ * rotations by theta/2 inside a two-state subspace, applied as
+ *   psi'[a] = c psi[a] - s psi[a'],  psi'[a'] = s psi[a] + c psi[a'],
+ *   c = cos(theta/2), s = sin(theta/2),
+ * for every basis index a in pattern A and a' = a with the A bits replaced by
+ * the B bits; other amplitudes are unchanged (no Jordan-Wigner strings).
+ *   SEXC on (q0, q1):          A = {q0 = 1, q1 = 0}, B = {q0 = 0, q1 = 1}
+ *   DEXC on (q0, q1, q2, q3):  A = {q0 = q1 = 1, q2 = q3 = 0},
+ *                              B = {q0 = q1 = 0, q2 = q3 = 1}
+ * Only specialised kernels (vqe_set_specialize) and the batched small-state
+ * kernel apply them; interpreted evaluations of a circuit holding one return
+ * VQE_ERR_UNSUPPORTED, and the default kernel form runs such circuits
+ * specialised at every size. */
+#define VQE_GATE_SEXC  7
+#define VQE_GATE_DEXC  8
 
 /* ---- expectation modes ---- */
 #define VQE_EXPECT_GROUPED   0  /* one sweep per X-mask group serves every Z pattern */
@@ -70,7 +85,8 @@ extern "C" {
 
 /* ---- gradient methods ---- */
 #define VQE_GRAD_ADJOINT      0  /* reverse sweep un-applying one gate at a time */
-#define VQE_GRAD_PARAM_SHIFT  1  /* [E(t + pi/2 e_k) - E(t - pi/2 e_k)] / 2 per parameter */
+#define VQE_GRAD_PARAM_SHIFT  1  /* [E(t + pi/2 e_k) - E(t - pi/2 e_k)] / 2 per parameter;
+                                     excitation gates: the four-term rule (see vqe_energy_grad) */
 
 /* ---- slimming modes (Sec. II-D, III-D) ---- */
 #define VQE_SLIM_THRESHOLD       0  /* keep iff |w| >= value */
@@ -81,15 +97,20 @@ typedef struct vqe_state vqe_state;
 typedef struct vqe_circuit vqe_circuit;
 typedef struct vqe_hamiltonian vqe_hamiltonian;
 
-/* One gate.  A gate with param_index >= 0 takes its angle from the parameter
- * vector passed at evaluation time, else from `angle`.  Only RY, RZ and RX
- * may be parameterised.  q1 is used by CNOT and CZ only. */
+/* One gate (24 bytes).  A gate with param_index >= 0 takes its angle from
+ * the parameter vector passed at evaluation time, else from `angle`.  RY, RZ,
+ * RX, SEXC and DEXC may be parameterised.  q1 is used by CNOT, CZ, SEXC and
+ * DEXC, q2 and q3 by DEXC; the qubits of one gate must differ.  Reserved
+ * fields are ignored. */
 typedef struct vqe_gate {
     uint8_t kind;
     uint8_t q0;
     uint8_t q1;
-    uint8_t reserved;
+    uint8_t q2;
+    uint8_t q3;
+    uint8_t reserved[3];
     int32_t param_index;
+    int32_t reserved2;
     double angle;
 } vqe_gate;
 
@@ -139,8 +160,9 @@ int vqe_state_write(vqe_state* s, uint64_t offset, uint64_t count, const void* h
 /* ------------------------------------------------------------------ circuits
  * U(theta) as an ordered gate list (applied first to last).  Creating a
  * circuit plans its fused passes: gates are grouped into windows of at most
- * 5 qubits, one HBM read and write of the state per window, respecting the
- * order of every gate pair that shares a qubit. */
+ * 5 (interpreted kernels) or VQE_MAX_WINDOW (specialised kernels) qubits, one
+ * HBM read and write of the state per window, respecting the order of every
+ * gate pair that shares a qubit. */
 int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_circuit** out);
 int vqe_circuit_free(vqe_circuit* c);
 
@@ -195,8 +217,13 @@ int vqe_apply_hamiltonian(vqe_state* psi, vqe_state* lam, const vqe_hamiltonian*
  *     be a distinct state of the same n and dtype.  With n_ckpt > 0 forward
  *     states are kept at evenly spaced pass boundaries and restored during the
  *     reverse sweep, which bounds the drift of the un-applied psi.
- *   PARAM_SHIFT: 2 n_params + 1 circuit runs (the independent circuit runs of
- *     Sec. II-C), energies by opts->expect_mode; lam is unused (may be NULL).
+ *   PARAM_SHIFT: one circuit run at theta and two per parameter (the
+ *     independent circuit runs of Sec. II-C), energies by opts->expect_mode;
+ *     for a parameter of an excitation gate four runs and
+ *     dE/dt = d1 [E(t + pi/2) - E(t - pi/2)] - d2 [E(t + 3pi/2) - E(t - 3pi/2)],
+ *     d1,2 = (sqrt2 +- 1) / (4 sqrt2) (generator eigenvalues 0, +-1; Anselmetti
+ *     et al. 2021).  Exact when each parameter drives one gate.  lam is unused
+ *     (may be NULL).
  * psi is overwritten; on return it holds U(theta)|0> for PARAM_SHIFT and the
  * reference |0...0> (up to rounding) for ADJOINT. */
 int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,

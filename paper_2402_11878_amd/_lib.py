@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvqe.so")
 
 VQE_OK, VQE_ERR_ARG, VQE_ERR_OOM, VQE_ERR_DEVICE, VQE_ERR_UNSUPPORTED, VQE_ERR_STATE = 0, -1, -2, -3, -4, -5
 VQE_C64, VQE_C128 = 1, 2
-GATE_RY, GATE_RZ, GATE_RX, GATE_H, GATE_X, GATE_CNOT, GATE_CZ = range(7)
+GATE_RY, GATE_RZ, GATE_RX, GATE_H, GATE_X, GATE_CNOT, GATE_CZ, GATE_SEXC, GATE_DEXC = range(9)
 EXPECT_GROUPED, EXPECT_PER_TERM = 0, 1
 GRAD_ADJOINT, GRAD_PARAM_SHIFT = 0, 1
 SLIM_THRESHOLD, SLIM_REMOVE_PERCENT, SLIM_BUDGET = 0, 1, 2
@@ -32,8 +32,9 @@ class VqeError(RuntimeError):
 
 
 class vqe_gate(C.Structure):
-    _fields_ = [("kind", C.c_uint8), ("q0", C.c_uint8), ("q1", C.c_uint8), ("reserved", C.c_uint8),
-                ("param_index", C.c_int32), ("angle", C.c_double)]
+    _fields_ = [("kind", C.c_uint8), ("q0", C.c_uint8), ("q1", C.c_uint8), ("q2", C.c_uint8), ("q3", C.c_uint8),
+                ("reserved", C.c_uint8 * 3), ("param_index", C.c_int32), ("reserved2", C.c_int32),
+                ("angle", C.c_double)]
 
 
 class vqe_grad_opts(C.Structure):
@@ -48,9 +49,10 @@ class vqe_batch_item(C.Structure):
 
 BATCH_MAX_QUBITS = {1: 13, 2: 12}
 
-GATE_DTYPE = np.dtype([("kind", "u1"), ("q0", "u1"), ("q1", "u1"), ("reserved", "u1"),
-                       ("param_index", "<i4"), ("angle", "<f8")], align=True)
-assert GATE_DTYPE.itemsize == C.sizeof(vqe_gate) == 16
+GATE_DTYPE = np.dtype([("kind", "u1"), ("q0", "u1"), ("q1", "u1"), ("q2", "u1"), ("q3", "u1"),
+                       ("reserved", "u1", (3,)), ("param_index", "<i4"), ("reserved2", "<i4"),
+                       ("angle", "<f8")], align=True)
+assert GATE_DTYPE.itemsize == C.sizeof(vqe_gate) == 24
 
 _P = C.c_void_p
 _SZ = C.c_size_t

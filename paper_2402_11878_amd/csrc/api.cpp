@@ -98,7 +98,8 @@ struct vqe_circuit {
     size_t n_params = 0;
     std::vector<BatchGate> bgates;  // gate table of the batched small-state kernel
     uint32_t n_mats = 0;            // matrices per evaluation (gates with a 2x2 matrix)
-    Plan plan[2];  // [0]: interpreted, [1]: specialised
+    Plan plan[2];  // [0]: interpreted (not built for circuits with excitation gates), [1]: specialised
+    bool has_excitation = false;
 };
 
 struct vqe_hamiltonian {
@@ -259,6 +260,8 @@ void fill_matrix(Mat2<T>& m, const Gate& g, double th, bool inverse) {
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     switch (g.kind) {
         case VQE_GATE_RY:  // [[c, -s], [s, c]]
+        case VQE_GATE_SEXC:  // the same rotation between the A and B patterns
+        case VQE_GATE_DEXC:
             v[0] = c; v[2] = -s; v[4] = s; v[6] = c;
             break;
         case VQE_GATE_RZ:  // diag(e^{-i t/2}, e^{i t/2})
@@ -291,9 +294,13 @@ uint8_t grad_op(int kind) {
     switch (kind) {
         case VQE_GATE_RY: return OP_GY;
         case VQE_GATE_RZ: return OP_GZ;
+        case VQE_GATE_SEXC: return OP_GPAIR2;
+        case VQE_GATE_DEXC: return OP_GPAIR4;
         default: return OP_GX;
     }
 }
+
+bool is_excitation(int kind) { return kind == VQE_GATE_SEXC || kind == VQE_GATE_DEXC; }
 
 int local_bit(const PlannedPass& p, int q) {
     for (int j = 0; j < p.K; ++j)
@@ -317,6 +324,17 @@ void emit_gate(const Gate& g, int gi, const PlannedPass& p, std::vector<KOp>& op
             break;
         case VQE_GATE_X:
             op.type = OP_XFLIP;
+            break;
+        case VQE_GATE_SEXC:
+        case VQE_GATE_DEXC:
+            op.type = g.kind == VQE_GATE_SEXC ? OP_PAIR2 : OP_PAIR4;
+            op.b = (uint8_t)local_bit(p, g.q1);
+            if (g.kind == VQE_GATE_DEXC) {
+                op.c = (uint8_t)local_bit(p, g.q2);
+                op.d = (uint8_t)local_bit(p, g.q3);
+            }
+            op.slot = (uint8_t)mat_gate.size();
+            mat_gate.push_back(gi);
             break;
         default:
             op.type = mat_op(g.kind);
@@ -393,7 +411,17 @@ std::mutex g_jit_plan_mu;
 bool use_specialised(const vqe_circuit* c) {
     const int mode = jit_mode();
     return mode == VQE_SPECIALIZE_ALWAYS ||
-           (mode == VQE_SPECIALIZE_AUTO && c->n >= VQE_SPECIALIZE_AUTO_MIN_QUBITS);
+           (mode == VQE_SPECIALIZE_AUTO && (c->n >= VQE_SPECIALIZE_AUTO_MIN_QUBITS || c->has_excitation));
+}
+
+// VQE_OK if the current kernel form can evaluate c (interpreted kernels have
+// no excitation gates).
+int check_form(const vqe_circuit* c, const char* fn) {
+    if (c->has_excitation && !use_specialised(c)) {
+        set_error(std::string(fn) + ": excitation gates need specialised kernels (vqe_set_specialize)");
+        return VQE_ERR_UNSUPPORTED;
+    }
+    return VQE_OK;
 }
 
 const Plan& plan_now(const vqe_circuit* c) { return c->plan[use_specialised(c) ? 1 : 0]; }
@@ -678,9 +706,25 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
 template <typename T>
 int param_shift_impl(vqe_state* psi, const vqe_circuit* c, const double* params, const vqe_hamiltonian* h,
                      int mode, double* energy, double* grad) {
+    // Shift rule per parameter: two runs at +-pi/2 for the rotations (their
+    // generators square to one); four runs at +-pi/2 and +-3pi/2 for the
+    // excitation gates, whose generators have eigenvalues 0 and +-1 (the
+    // four-term rule of Anselmetti et al. 2021).
     const size_t P = c->n_params;
+    std::vector<char> exc(P, 0);
+    for (const Gate& g : c->gates)
+        if (g.pidx >= 0 && is_excitation(g.kind)) exc[g.pidx] = 1;
+    std::vector<std::pair<size_t, double>> shifts;  // evaluation e >= 1: (parameter, shift)
+    for (size_t k = 0; k < P; ++k) {
+        shifts.push_back({k, M_PI / 2});
+        shifts.push_back({k, -M_PI / 2});
+        if (exc[k]) {
+            shifts.push_back({k, 3 * M_PI / 2});
+            shifts.push_back({k, -3 * M_PI / 2});
+        }
+    }
     const size_t per = mode == VQE_EXPECT_PER_TERM ? 2 * h->w.size() : 2;
-    const size_t n_eval = 2 * P + 1;
+    const size_t n_eval = 1 + shifts.size();
     int rc = ensure_res(psi, per * n_eval);
     if (rc) return rc;
     std::vector<double> th(params, params + P);
@@ -689,10 +733,7 @@ int param_shift_impl(vqe_state* psi, const vqe_circuit* c, const double* params,
     // Evaluation 0 last so that psi ends in U(theta)|0>.
     for (size_t e = n_eval; e-- > 0;) {
         std::copy(params, params + P, th.begin());
-        if (e > 0) {
-            const size_t k = (e - 1) / 2;
-            th[k] += (e % 2 == 1) ? M_PI / 2 : -M_PI / 2;
-        }
+        if (e > 0) th[shifts[e - 1].first] += shifts[e - 1].second;
         VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, psi->stream));
         rc = forward<T>(psi, c, plan_now(c), th.data(), nob, nock);
         if (rc) return rc;
@@ -713,7 +754,17 @@ int param_shift_impl(vqe_state* psi, const vqe_circuit* c, const double* params,
         }
     }
     *energy = E[0];
-    for (size_t k = 0; k < P; ++k) grad[k] = 0.5 * (E[1 + 2 * k] - E[2 + 2 * k]);
+    const double d1 = (std::sqrt(2.0) + 1) / (4 * std::sqrt(2.0)), d2 = (std::sqrt(2.0) - 1) / (4 * std::sqrt(2.0));
+    size_t e = 1;
+    for (size_t k = 0; k < P; ++k) {
+        if (exc[k]) {
+            grad[k] = d1 * (E[e] - E[e + 1]) - d2 * (E[e + 2] - E[e + 3]);
+            e += 4;
+        } else {
+            grad[k] = 0.5 * (E[e] - E[e + 1]);
+            e += 2;
+        }
+    }
     return VQE_OK;
 }
 
@@ -757,6 +808,11 @@ int build_plan(vqe_circuit* c, const PlanLimits& lim, bool jit, Plan& pl) {
                 KOp gop{};
                 gop.type = grad_op(g.kind);
                 gop.a = (uint8_t)local_bit(p, g.q0);
+                if (is_excitation(g.kind)) gop.b = (uint8_t)local_bit(p, g.q1);
+                if (g.kind == VQE_GATE_DEXC) {
+                    gop.c = (uint8_t)local_bit(p, g.q2);
+                    gop.d = (uint8_t)local_bit(p, g.q3);
+                }
                 gop.slot = (uint8_t)slot;
                 po.rev.push_back(gop);
             }
@@ -794,7 +850,12 @@ uint32_t reg_needs(const KOp& op) {
         case OP_GY:
             return 1u << op.a;
         case OP_CNOT:
+        case OP_PAIR2:
+        case OP_GPAIR2:
             return (1u << op.a) | (1u << op.b);
+        case OP_PAIR4:
+        case OP_GPAIR4:
+            return (1u << op.a) | (1u << op.b) | (1u << op.c) | (1u << op.d);
         default:  // OP_DIAG, OP_CZ, OP_GZ act per lane on a lane-resident bit
             return 0;
     }
@@ -859,7 +920,13 @@ bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps
         }
         KOp ph = op;
         ph.a = (uint8_t)slot_of[op.a];
-        if (op.type == OP_CNOT || op.type == OP_CZ) ph.b = (uint8_t)slot_of[op.b];
+        if (op.type == OP_CNOT || op.type == OP_CZ || op.type == OP_PAIR2 || op.type == OP_GPAIR2 ||
+            op.type == OP_PAIR4 || op.type == OP_GPAIR4)
+            ph.b = (uint8_t)slot_of[op.b];
+        if (op.type == OP_PAIR4 || op.type == OP_GPAIR4) {
+            ph.c = (uint8_t)slot_of[op.c];
+            ph.d = (uint8_t)slot_of[op.d];
+        }
         out.ops.push_back(ph);
     }
     for (int sl = 0; sl < K; ++sl) out.map_out[sl] = (uint8_t)bit_at[sl];
@@ -946,7 +1013,8 @@ int batch_impl(vqe_batch* b, size_t n_items, const vqe_batch_item* items) {
         for (size_t k = 0; k < c->bgates.size(); ++k) {
             hg[g_off + k] = c->bgates[k];
             const Gate& gt = c->gates[k];
-            if (c->bgates[k].type == OP_U2) fill_matrix(hm[m_off + c->bgates[k].mat], gt, angle_of(gt, items[i].params), false);
+            if (c->bgates[k].type == OP_U2 || c->bgates[k].type == OP_PAIR2)
+                fill_matrix(hm[m_off + c->bgates[k].mat], gt, angle_of(gt, items[i].params), false);
         }
         g_off += c->bgates.size();
         m_off += c->n_mats;
@@ -1129,16 +1197,26 @@ int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_
     size_t n_params = 0;
     for (size_t i = 0; i < n_gates; ++i) {
         const vqe_gate& g = gates[i];
-        const bool two = g.kind == VQE_GATE_CNOT || g.kind == VQE_GATE_CZ;
-        if (g.kind > VQE_GATE_CZ) {
+        if (g.kind > VQE_GATE_DEXC) {
             set_error("vqe_circuit_create: gate " + std::to_string(i) + " has an unknown kind");
             return VQE_ERR_ARG;
         }
-        if (g.q0 >= n_qubits || (two && (g.q1 >= n_qubits || g.q1 == g.q0))) {
-            set_error("vqe_circuit_create: gate " + std::to_string(i) + " has an invalid qubit");
+        Gate ig{g.kind, g.q0, g.q1, g.param_index, g.angle};
+        ig.q2 = g.q2;
+        ig.q3 = g.q3;
+        int gq[4];
+        const int nqg = gate_qubits(ig, gq);
+        bool ok = true;
+        for (int a = 0; a < nqg; ++a) {
+            ok = ok && gq[a] < n_qubits;
+            for (int b = 0; b < a; ++b) ok = ok && gq[a] != gq[b];
+        }
+        if (!ok) {
+            set_error("vqe_circuit_create: gate " + std::to_string(i) + " has an invalid or repeated qubit");
             return VQE_ERR_ARG;
         }
-        if (g.param_index >= 0 && !(g.kind == VQE_GATE_RY || g.kind == VQE_GATE_RZ || g.kind == VQE_GATE_RX)) {
+        if (g.param_index >= 0 && !(g.kind == VQE_GATE_RY || g.kind == VQE_GATE_RZ || g.kind == VQE_GATE_RX ||
+                                    is_excitation(g.kind))) {
             set_error("vqe_circuit_create: gate " + std::to_string(i) + " cannot take a parameter");
             return VQE_ERR_ARG;
         }
@@ -1150,7 +1228,9 @@ int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_
             set_error("vqe_circuit_create: gate " + std::to_string(i) + " has a non-finite angle");
             return VQE_ERR_ARG;
         }
-        gs[i] = Gate{g.kind, g.q0, two ? g.q1 : g.q0, g.param_index, g.angle};
+        if (nqg == 1) ig.q1 = ig.q0;
+        if (nqg < 4) ig.q2 = ig.q3 = 0;
+        gs[i] = ig;
         if (g.param_index >= 0) n_params = std::max(n_params, (size_t)g.param_index + 1);
     }
     auto* c = new vqe_circuit();
@@ -1167,13 +1247,25 @@ int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_
         if (g.kind == VQE_GATE_CNOT) bg.type = OP_CNOT;
         else if (g.kind == VQE_GATE_CZ) bg.type = OP_CZ;
         else if (g.kind == VQE_GATE_X) bg.type = OP_XFLIP;
-        else {
+        else if (is_excitation(g.kind)) {
+            // pair rotation on the basis patterns A, B (batched states have n <= 13)
+            bg.type = OP_PAIR2;
+            bg.gen = OP_GPAIR2;
+            const bool dbl = g.kind == VQE_GATE_DEXC;
+            if (n_qubits <= 16) {
+                bg.pa = (uint16_t)(dbl ? (1u << g.q0) | (1u << g.q1) : (1u << g.q0));
+                bg.pb = (uint16_t)(dbl ? (1u << g.q2) | (1u << g.q3) : (1u << g.q1));
+            }
+            bg.mat = c->n_mats++;
+            c->has_excitation = true;
+        } else {
             bg.type = OP_U2;
             bg.mat = c->n_mats++;
         }
         c->bgates.push_back(bg);
     }
     for (int v = 0; v < 2; ++v) {
+        if (v == 0 && c->has_excitation) continue;  // interpreted kernels have no pair ops
         int rc = build_plan(c, v ? kJitLimits : kInterpLimits, v == 1, c->plan[v]);
         if (rc) {
             free_circuit(c);
@@ -1206,6 +1298,7 @@ int vqe_circuit_pass(const vqe_circuit* c, int dtype, size_t pass, int* window, 
         set_error("vqe_circuit_pass: null circuit or bad dtype");
         return VQE_ERR_ARG;
     }
+    if (int rc = check_form(c, "vqe_circuit_pass")) return rc;
     const Plan& pl = plan_now(c);
     if (pass >= pl.passes.size()) {
         set_error("vqe_circuit_pass: pass index out of range");
@@ -1234,6 +1327,7 @@ int vqe_apply_circuit(vqe_state* s, const vqe_circuit* c, const double* params, 
         return VQE_ERR_ARG;
     }
     if (int rc = check_params(c, params, n_params, "vqe_apply_circuit")) return rc;
+    if (int rc = check_form(c, "vqe_apply_circuit")) return rc;
     VQE_HIP(hipSetDevice(s->device));
     const std::vector<size_t> nob;
     const std::vector<void*> nock;
@@ -1394,6 +1488,7 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const 
         return VQE_ERR_ARG;
     }
     if (int rc = check_params(c, params, n_params, "vqe_energy_grad")) return rc;
+    if (int rc = check_form(c, "vqe_energy_grad")) return rc;
     const int method = opts ? opts->method : VQE_GRAD_ADJOINT;
     VQE_HIP(hipSetDevice(psi->device));
     if (int rc = upload_hamiltonian(h)) return rc;
@@ -1506,6 +1601,7 @@ int vqe_circuit_prepare(const vqe_circuit* c, int dtype) {
         set_error("vqe_circuit_prepare: null circuit or bad dtype");
         return VQE_ERR_ARG;
     }
+    if (int rc = check_form(c, "vqe_circuit_prepare")) return rc;
     const Plan& pl = plan_now(c);
     if (!pl.jit) return VQE_OK;
     return ensure_jit(c, pl, dtype == VQE_C128 ? 1 : 0);

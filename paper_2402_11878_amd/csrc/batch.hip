@@ -6,7 +6,8 @@
 // of different circuits and Hamiltonians share one launch (grid = requests).
 //
 // Per request, in order: psi = |0>; every gate applied in turn (one LDS sweep
-// and barrier per gate); lam[b] = sum_x psi[b^x] sum_z c_z (-1)^popcount(z&b)
+// and barrier per gate; excitation gates as rotations between two basis
+// patterns); lam[b] = sum_x psi[b^x] sum_z c_z (-1)^popcount(z&b)
 // with the energy and norm reduced over the block in a fixed tree; then the
 // gates in reverse: for a parameterised gate, g += Im<lam|G|psi> reduced in
 // the same fixed tree, followed by un-applying the gate (U^dagger = conj
@@ -65,6 +66,27 @@ __device__ void apply_gate(typename VecB<T>::type* s, int n, const BatchGate& g,
                 x.y = -x.y;
                 s[j] = x;
             }
+        }
+    } else if (g.type == OP_PAIR2) {
+        // rotation between the basis patterns A = pa and B = pb on the bits pa | pb
+        T u0r = m[0], u1r = m[2], u2r = m[4], u3r = m[6];
+        if (dag) {
+            const T t = u1r;
+            u1r = u2r;
+            u2r = t;
+        }
+        const uint32_t M = (uint32_t)g.pa | g.pb, X = (uint32_t)g.pa ^ g.pb;
+        for (uint32_t i = t; i < (1u << n); i += kBT) {
+            if ((i & M) != g.pa) continue;
+            const uint32_t j = i ^ X;
+            const V x = s[i], y = s[j];
+            V o0, o1;
+            o0.x = u0r * x.x + u1r * y.x;
+            o0.y = u0r * x.y + u1r * y.y;
+            o1.x = u2r * x.x + u3r * y.x;
+            o1.y = u2r * x.y + u3r * y.y;
+            s[i] = o0;
+            s[j] = o1;
         }
     } else if (g.type == OP_XFLIP) {
         const uint32_t cnt = 1u << (n - 1);
@@ -157,7 +179,19 @@ batch_kernel(const BatchDesc<T>* __restrict__ items, const BatchGate* __restrict
     // reverse sweep
     for (uint32_t gi = d.n_gates; gi-- > 0;) {
         const BatchGate g = gates[d.gate_off + gi];
-        if (g.pidx >= 0) {
+        if (g.pidx >= 0 && g.gen == OP_GPAIR2) {
+            // Re(conj(lam_B) psi_A) - Re(conj(lam_A) psi_B) over the pattern pairs
+            const uint32_t M = (uint32_t)g.pa | g.pb, X = (uint32_t)g.pa ^ g.pb;
+            T acc = 0;
+            for (uint32_t i = t; i < dim; i += kBT) {
+                if ((i & M) != g.pa) continue;
+                const uint32_t j = i ^ X;
+                const V pa = psi[i], pb = psi[j], la = lam[i], lb = lam[j];
+                acc += (lb.x * pa.x + lb.y * pa.y) - (la.x * pb.x + la.y * pb.y);
+            }
+            const double gsum = block_sum((double)acc, red);
+            if (t == 0) o[1 + g.pidx] += gsum / nrm;
+        } else if (g.pidx >= 0) {
             const uint32_t q = g.q0;
             const uint32_t cnt = 1u << (n - 1);
             T acc = 0;

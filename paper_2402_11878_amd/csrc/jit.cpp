@@ -203,6 +203,40 @@ struct Gen {
                 }
                 break;
             }
+            case OP_PAIR2:
+            case OP_PAIR4: {
+                uint32_t mask, PA, PB;
+                pair_patterns(k, mask, PA, PB);
+                mats(k.slot, false);
+                o << "    const T ca = m[0], cb = m[2], cc = m[4], cd = m[6];\n";
+                for (int p = 0; p < N; ++p) {
+                    if ((p & (int)mask) != (int)PA) continue;
+                    const int q = p ^ (int)PA ^ (int)PB;
+                    for (int v = 0; v < NV; ++v)
+                        o << "    { const T ar = " << R(v, p) << ", ai = " << I(v, p) << ", br = " << R(v, q)
+                          << ", bi = " << I(v, q) << ";\n"
+                          << "      " << R(v, p) << " = ca * ar + cb * br; " << I(v, p) << " = ca * ai + cb * bi;\n"
+                          << "      " << R(v, q) << " = cc * ar + cd * br; " << I(v, q) << " = cc * ai + cd * bi; }\n";
+                }
+                o << "  }\n";
+                break;
+            }
+            case OP_GPAIR2:
+            case OP_GPAIR4: {
+                if (NV != 2) break;
+                uint32_t mask, PA, PB;
+                pair_patterns(k, mask, PA, PB);
+                // Re<lam|K|psi>, K = |B><A| - |A><B|: Re(conj(lam_B) psi_A) - Re(conj(lam_A) psi_B)
+                o << "  { T acc = 0;\n";
+                for (int p = 0; p < N; ++p) {
+                    if ((p & (int)mask) != (int)PA) continue;
+                    const int q = p ^ (int)PA ^ (int)PB;
+                    o << "    acc += (" << R(1, q) << " * " << R(0, p) << " + " << I(1, q) << " * " << I(0, p) << ") - ("
+                      << R(1, p) << " * " << R(0, q) << " + " << I(1, p) << " * " << I(0, q) << ");\n";
+                }
+                o << "    g" << (int)k.slot << " += (double)acc; }\n";
+                break;
+            }
             case OP_GX:
             case OP_GY:
             case OP_GZ: {

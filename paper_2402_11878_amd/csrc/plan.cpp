@@ -28,13 +28,19 @@ struct PlanState {
     std::vector<size_t> head;             // per qubit, position of next unscheduled gate
 };
 
-int nq(const Gate& g) { return (g.kind == VQE_GATE_CNOT || g.kind == VQE_GATE_CZ) ? 2 : 1; }
-
 bool is_param(const Gate& g) { return g.pidx >= 0; }
 
 bool uses_matrix(const Gate& g) {
     return g.kind == VQE_GATE_RY || g.kind == VQE_GATE_RZ || g.kind == VQE_GATE_RX ||
-           g.kind == VQE_GATE_H;
+           g.kind == VQE_GATE_H || g.kind == VQE_GATE_SEXC || g.kind == VQE_GATE_DEXC;
+}
+
+uint64_t gate_mask(const Gate& g) {
+    int q[4];
+    const int k = gate_qubits(g, q);
+    uint64_t m = 0;
+    for (int i = 0; i < k; ++i) m |= 1ull << q[i];
+    return m;
 }
 
 // Closure of window W (bit mask over qubits) starting from `head`; appends the
@@ -53,9 +59,12 @@ int closure(const PlanState& ps, uint64_t W, std::vector<size_t>& head, std::vec
             while (head[q] < ps.chain[q].size()) {
                 int gi = ps.chain[q][head[q]];
                 const Gate& g = G[gi];
-                int qa = g.q0, qb = nq(g) == 2 ? g.q1 : g.q0;
-                if (!((W >> qa) & 1) || !((W >> qb) & 1)) break;
-                if (ps.chain[qa][head[qa]] != gi || ps.chain[qb][head[qb]] != gi) break;
+                int gq[4];
+                const int nqg = gate_qubits(g, gq);
+                bool ready = true;
+                for (int i = 0; i < nqg && ready; ++i)
+                    ready = ((W >> gq[i]) & 1) && ps.chain[gq[i]][head[gq[i]]] == gi;
+                if (!ready) break;
                 int add_ops = 1 + (is_param(g) ? 1 : 0);
                 int add_mats = uses_matrix(g) ? 1 : 0;
                 int add_slots = is_param(g) ? 1 : 0;
@@ -64,8 +73,7 @@ int closure(const PlanState& ps, uint64_t W, std::vector<size_t>& head, std::vec
                 ops_rev += add_ops;
                 mats += add_mats;
                 slots += add_slots;
-                head[qa]++;
-                if (qb != qa) head[qb]++;
+                for (int i = 0; i < nqg; ++i) head[gq[i]]++;
                 if (out) out->push_back(gi);
                 ++count;
                 changed = true;
@@ -90,9 +98,9 @@ bool plan_passes(int n, const std::vector<Gate>& gates, const PlanLimits& lim, s
     ps.chain.assign(n, {});
     ps.head.assign(n, 0);
     for (size_t i = 0; i < gates.size(); ++i) {
-        const Gate& g = gates[i];
-        ps.chain[g.q0].push_back((int)i);
-        if (nq(g) == 2) ps.chain[g.q1].push_back((int)i);
+        int gq[4];
+        const int nqg = gate_qubits(gates[i], gq);
+        for (int k = 0; k < nqg; ++k) ps.chain[gq[k]].push_back((int)i);
     }
     size_t scheduled = 0;
     std::vector<char> done(gates.size(), 0);
@@ -103,8 +111,7 @@ bool plan_passes(int n, const std::vector<Gate>& gates, const PlanLimits& lim, s
         std::vector<uint64_t> cands;
         for (int a = 0; a + K <= n; ++a) cands.push_back(((K == 64 ? ~0ull : ((1ull << K) - 1))) << a);
         {
-            const Gate& g0 = gates[earliest];
-            uint64_t W = (1ull << g0.q0) | (nq(g0) == 2 ? (1ull << g0.q1) : 0);
+            uint64_t W = gate_mask(gates[earliest]);
             while (popcount64(W) < K) {
                 int best_q = -1, best_c = -1;
                 for (int q = 0; q < n; ++q) {
@@ -139,10 +146,7 @@ bool plan_passes(int n, const std::vector<Gate>& gates, const PlanLimits& lim, s
         closure(ps, bestW, ps.head, &p.gates);
         // Shrink the window to the qubits actually touched.
         uint64_t used = 0;
-        for (int gi : p.gates) {
-            used |= 1ull << gates[gi].q0;
-            if (nq(gates[gi]) == 2) used |= 1ull << gates[gi].q1;
-        }
+        for (int gi : p.gates) used |= gate_mask(gates[gi]);
         p.K = 0;
         for (int q = 0; q < n; ++q)
             if ((used >> q) & 1) p.pos[p.K++] = q;

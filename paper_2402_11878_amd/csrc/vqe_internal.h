@@ -52,11 +52,31 @@ enum OpType : uint8_t {
     OP_GY = 7,    // gradient slot += Im<lam| Y_a |psi>
     OP_GZ = 8,    // gradient slot += Im<lam| Z_a |psi>
     OP_TPOSE = 9, // lane-split layout: swap the roles of register bit a and lane slot b
+    // Excitation gates: rotation by mats[slot] = [[c, -s], [s, c]] between the
+    // patterns A and B of a 2- or 4-bit subset (specialised kernels only).
+    OP_PAIR2 = 10,  // A = {a = 1, b = 0}, B = {a = 0, b = 1}
+    OP_PAIR4 = 11,  // A = {a = b = 1, c = d = 0}, B = {a = b = 0, c = d = 1}
+    OP_GPAIR2 = 12, // gradient slot += Re<lam| K |psi>, K = |B><A| - |A><B| of OP_PAIR2
+    OP_GPAIR4 = 13, // ... of OP_PAIR4
 };
 
 struct KOp {
     uint8_t type, a, b, slot;
+    uint8_t c, d;  // third and fourth bit of OP_PAIR4 / OP_GPAIR4
+    uint8_t pad[2];
 };
+
+// Bit subset and the A / B patterns of a pair op (over the op's local bits).
+inline void pair_patterns(const KOp& k, uint32_t& mask, uint32_t& A, uint32_t& B) {
+    if (k.type == OP_PAIR2 || k.type == OP_GPAIR2) {
+        A = 1u << k.a;
+        B = 1u << k.b;
+    } else {
+        A = (1u << k.a) | (1u << k.b);
+        B = (1u << k.c) | (1u << k.d);
+    }
+    mask = A | B;
+}
 
 // Matrix of a 2x2 op: row-major entries u00 u01 u10 u11, each (re, im).
 template <typename T>
@@ -127,12 +147,12 @@ constexpr int kBatchMaxQubitsC64 = 13;
 constexpr int kBatchMaxQubitsC128 = 12;
 
 struct BatchGate {
-    uint8_t type;  // OP_U2, OP_CNOT, OP_CZ, OP_XFLIP
+    uint8_t type;  // OP_U2, OP_CNOT, OP_CZ, OP_XFLIP, OP_PAIR2 (any pair rotation)
     uint8_t q0, q1;
-    uint8_t gen;   // OP_GX / OP_GY / OP_GZ for parameterised gates
+    uint8_t gen;   // OP_GX / OP_GY / OP_GZ / OP_GPAIR2 for parameterised gates
     int32_t pidx;  // parameter index or -1
     uint32_t mat;  // matrix index within the request
-    uint32_t pad;
+    uint16_t pa, pb;  // pair rotations: basis patterns A and B (n <= 16)
 };
 
 template <typename T>
@@ -207,7 +227,27 @@ hipError_t launch_reduce(const double* part, uint32_t nblocks, uint32_t nslots,
 struct Gate {
     int kind, q0, q1, pidx;
     double angle;
+    int q2 = 0, q3 = 0;  // DEXC only
 };
+
+// Qubits of a gate (1, 2 or 4); returns the count.
+inline int gate_qubits(const Gate& g, int q[4]) {
+    q[0] = g.q0;
+    switch (g.kind) {
+        case VQE_GATE_CNOT:
+        case VQE_GATE_CZ:
+        case VQE_GATE_SEXC:
+            q[1] = g.q1;
+            return 2;
+        case VQE_GATE_DEXC:
+            q[1] = g.q1;
+            q[2] = g.q2;
+            q[3] = g.q3;
+            return 4;
+        default:
+            return 1;
+    }
+}
 
 struct PlannedPass {
     int K = 0;

@@ -7,7 +7,7 @@ import numpy as np
 from oracle import statevector as osv
 from paper_2402_11878_amd import _lib
 
-NAMES = {0: "RY", 1: "RZ", 2: "RX", 3: "H", 4: "X", 5: "CNOT", 6: "CZ"}
+NAMES = {0: "RY", 1: "RZ", 2: "RX", 3: "H", 4: "X", 5: "CNOT", 6: "CZ", 7: "SEXC", 8: "DEXC"}
 
 
 def say(*a):
@@ -16,8 +16,17 @@ def say(*a):
 
 
 def oracle_gates(arr):
-    return [(NAMES[int(g["kind"])], int(g["q0"]), int(g["q1"]), int(g["param_index"]), float(g["angle"]))
-            for g in arr]
+    out = []
+    for g in arr:
+        k = int(g["kind"])
+        if k == 7:
+            out.append(("SEXC", (int(g["q0"]), int(g["q1"])), -1, int(g["param_index"]), float(g["angle"])))
+        elif k == 8:
+            out.append(("DEXC", (int(g["q0"]), int(g["q1"]), int(g["q2"]), int(g["q3"])), -1,
+                        int(g["param_index"]), float(g["angle"])))
+        else:
+            out.append((NAMES[k], int(g["q0"]), int(g["q1"]), int(g["param_index"]), float(g["angle"])))
+    return out
 
 
 class Dev:

@@ -144,8 +144,15 @@ def test_slim_argument_errors():
 
 def _oracle_gates(arr):
     names = {0: "RY", 1: "RZ", 2: "RX", 3: "H", 4: "X", 5: "CNOT", 6: "CZ"}
-    return [(names[int(g["kind"])], int(g["q0"]), int(g["q1"]), int(g["param_index"]), float(g["angle"]))
-            for g in arr]
+    out = []
+    for g in arr:
+        k = int(g["kind"])
+        if k in (7, 8):
+            qs = (int(g["q0"]), int(g["q1"])) + ((int(g["q2"]), int(g["q3"])) if k == 8 else ())
+            out.append(("SEXC" if k == 7 else "DEXC", qs, -1, int(g["param_index"]), float(g["angle"])))
+        else:
+            out.append((names[k], int(g["q0"]), int(g["q1"]), int(g["param_index"]), float(g["angle"])))
+    return out
 
 
 def random_circuit(n, n_gates, seed):
@@ -304,3 +311,70 @@ def test_molecule_10_slimming_matches_golden():
         assert n_kept == r["n_terms"]
         assert len(set(x[k].tolist())) == r["n_groups"]
         assert abs(dropped - r["dropped_abs_sum"]) <= 1e-12 * max(1.0, r["dropped_abs_sum"])
+
+
+# ------------------------------------------------------------------ excitation gates (eq. 5)
+@pytest.mark.parametrize("n,ne,layers", [(4, 2, 1), (8, 4, 1), (10, 4, 2)])
+def test_excitation_builder_matches_oracle(n, ne, layers):
+    """The library's S/D ansatz (after the X gates of the Hartree-Fock
+    reference) is the oracle's gate list."""
+    arr, P = ansatz.excitations(n, ne, layers)
+    og = _oracle_gates(arr)
+    assert og[:ne] == [("X", q, 0, -1, 0.0) for q in range(ne)]
+    ref = osv.excitation_ansatz(n, ne, layers)
+    assert [(k, tuple(q), p) for (k, q, _, p, _) in og[ne:]] == [(k, tuple(q), p) for (k, q, _, p, _) in ref]
+    assert P == len(ref)
+
+
+@pytest.mark.parametrize("n,ne,seed", [(6, 2, 0), (8, 4, 1), (9, 3, 2)])
+def test_excitation_plan_is_valid_reordering(n, ne, seed, specialize_mode):
+    """Specialised plans of circuits mixing excitation gates with the other
+    kinds are valid reorderings (windows hold all qubits of every gate); the
+    default form plans them specialised at any size, the interpreted form
+    reports them unsupported."""
+    exc, P = ansatz.excitations(n, ne)
+    rnd, P2 = random_circuit(n, 40, seed)
+    rnd["param_index"][rnd["param_index"] >= 0] += P
+    arr = np.concatenate([exc, rnd])
+    og = _oracle_gates(arr)
+    th = synth.theta(seed, P + P2)
+    ref = osv.run(n, og, th)
+    c = _lib.vqe_circuit_create(n, arr)
+    try:
+        specialize_mode(_lib.SPECIALIZE_AUTO)
+        order, p = [], 0
+        while True:
+            try:
+                qubits, idx = _lib.vqe_circuit_pass(c, _lib.VQE_C128, p)
+            except _lib.VqeError:
+                break
+            assert 1 <= len(qubits) <= min(_lib.MAX_WINDOW, n)
+            for gi in idx:
+                kind, q0, q1, _, _ = og[gi]
+                need = q0 if isinstance(q0, tuple) else ((q0, q1) if kind in ("CNOT", "CZ") else (q0,))
+                assert set(need) <= set(qubits)
+            order += idx
+            p += 1
+        assert sorted(order) == list(range(len(og)))
+        got = osv.run(n, [og[i] for i in order], th)
+        assert np.max(np.abs(got - ref)) < 1e-12
+        specialize_mode(_lib.SPECIALIZE_NEVER)
+        with pytest.raises(_lib.VqeError) as e:
+            _lib.vqe_circuit_pass(c, _lib.VQE_C128, 0)
+        assert e.value.code == _lib.VQE_ERR_UNSUPPORTED
+    finally:
+        _lib.vqe_circuit_free(c)
+
+
+def test_excitation_gate_argument_errors():
+    bad = ansatz.gates_array([(_lib.GATE_DEXC, (0, 1, 2, 1), 0, 0.0)])
+    with pytest.raises(_lib.VqeError) as e:
+        _lib.vqe_circuit_create(4, bad)
+    assert e.value.code == _lib.VQE_ERR_ARG
+    bad = ansatz.gates_array([(_lib.GATE_SEXC, (0, 4), 0, 0.0)])
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_circuit_create(4, bad)
+    ok = ansatz.gates_array([(_lib.GATE_SEXC, (3, 0), -1, 0.4), (_lib.GATE_DEXC, (0, 1, 2, 3), 0, 0.0)])
+    c = _lib.vqe_circuit_create(4, ok)
+    assert _lib.vqe_circuit_info(c)[0] == 1
+    _lib.vqe_circuit_free(c)
