@@ -378,3 +378,20 @@ def test_excitation_gate_argument_errors():
     c = _lib.vqe_circuit_create(4, ok)
     assert _lib.vqe_circuit_info(c)[0] == 1
     _lib.vqe_circuit_free(c)
+
+
+def test_cutoff_ratio_rule():
+    """Algorithm 1 read as: first k in 10, 9, ..., 1 with |E_k - E_10| >=
+    delta_E returns (k + 1)/10; none returns 0.1 (energies given per tenth)."""
+    from paper_2402_11878_amd.vqe import cutoff_ratio
+    E = {10: -1.0, 9: -1.0, 8: -0.9999, 7: -0.999, 6: -0.99, 5: -0.9, 4: -0.5, 3: -0.4, 2: -0.3, 1: -0.2}
+    calls = []
+
+    def f(k):
+        calls.append(k)
+        return E[k]
+    assert cutoff_ratio(f, 5e-4) == 0.8          # k = 7 is the first miss
+    assert calls == [10, 9, 8, 7]
+    assert cutoff_ratio(lambda k: E[k], 1e-5) == 0.9   # k = 8 misses
+    assert cutoff_ratio(lambda k: E[k], 10.0) == 0.1   # never
+    assert cutoff_ratio(lambda k: E[k], 0.0) == 1.1    # |E_10 - E_10| >= 0 at once
