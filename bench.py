@@ -70,11 +70,35 @@ def measured_traffic(kernel="window_rev", record="profiles/window_rev_hubbard4x4
     return float(kv["traffic_bytes_per_launch"])
 
 
-def run_dtype(torch, L, core, wl, dtype, n_ckpt, steps, warmup, theta):
-    """Times `steps` energy+gradient evaluations; returns a result dict."""
-    from paper_2402_11878_amd import hamiltonians as hm
+WORKLOAD_TEXT = {
+    "hubbard1d_6": "1-D Fermi-Hubbard, 6 sites open, t=1, U=4",
+    "hubbard2x7": "2-D Fermi-Hubbard 2x7, periodic along the long axis, t=1, U=8, JW snake order",
+    "hubbard4x4": "2-D Fermi-Hubbard 4x4 open, t=1, U=4, JW snake order",
+    "molecule_10": "molecule-shaped Hamiltonian, 10 spatial orbitals, integral seed 0",
+    "molecule_16": "molecule-shaped Hamiltonian, 16 spatial orbitals, integral seed 0",
+}
+
+
+def workload_hamiltonian(wl, threshold):
+    """(x, z, w) of a workload: lattice models as built, molecule-shaped ones
+    slimmed at `threshold` (default: the workload's largest threshold)."""
+    import synth
+    from paper_2402_11878_amd import _lib as L, hamiltonians as hm
+    if wl.kind != "molecule":
+        return hm.from_lattice(wl.lattice), None
+    h, g = synth.molecule_integrals(wl.n_orb, wl.integral_seed)
+    x, z, w = hm.molecule(h, g)
+    th = max(wl.thresholds) if threshold is None else threshold
+    keep, _, _ = L.vqe_slim_hamiltonian(x, z, w, L.SLIM_THRESHOLD, th)
+    m = keep == 1
+    return (x[m], z[m], w[m]), th
+
+
+def run_dtype(torch, L, core, wl, dtype, n_ckpt, steps, warmup, thetas, threshold=None):
+    """Times `steps` energy+gradient evaluations, cycling through the rows of
+    `thetas` (a workload's parameter batch); returns a result dict."""
     n = wl.n_qubits
-    x, z, w = hm.from_lattice(wl.lattice)
+    (x, z, w), th_used = workload_hamiltonian(wl, threshold)
     H = core.Hamiltonian(n, x, z, w)
     circ = core.Circuit.layered(n, wl.layers)
     tdt = torch.complex64 if dtype == L.VQE_C64 else torch.complex128
@@ -86,16 +110,18 @@ def run_dtype(torch, L, core, wl, dtype, n_ckpt, steps, warmup, theta):
     try:
         for i in range(warmup):
             log(f"[bench] {name} warmup step {i + 1}/{warmup}")
-            E, g = L.vqe_energy_grad(psi, lam, circ.handle, theta, H.handle, ckpt=ck)
+            E, g = L.vqe_energy_grad(psi, lam, circ.handle, thetas[i % len(thetas)], H.handle, ckpt=ck)
         torch.cuda.synchronize()
         L.vqe_profile_reset()
         L.vqe_profile_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         energies = []
+        grads = []
         for i in range(steps):
-            E, g = L.vqe_energy_grad(psi, lam, circ.handle, theta, H.handle, ckpt=ck)
+            E, g = L.vqe_energy_grad(psi, lam, circ.handle, thetas[i % len(thetas)], H.handle, ckpt=ck)
             energies.append(E)
+            grads.append(g)
             log(f"[bench] {name} step {i + 1}/{steps} E={E:.12f}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -108,7 +134,8 @@ def run_dtype(torch, L, core, wl, dtype, n_ckpt, steps, warmup, theta):
         del bufs
         torch.cuda.empty_cache()
     sec = (t1 - t0) / steps
-    return dict(name=name, sec=sec, E=energies[-1], grad=g, energies=energies, prof=prof,
+    return dict(name=name, sec=sec, E=energies[-1], grad=g, grads=grads, energies=energies, prof=prof,
+                threshold=th_used,
                 n_gates=len(circ.gates), n_passes_adj=circ.passes_count(dtype), n_terms=H.n_terms,
                 n_groups=H.n_groups,
                 state_bytes=(1 << n) * (8 if dtype == L.VQE_C64 else 16), n_ckpt=n_ckpt)
@@ -117,14 +144,14 @@ def run_dtype(torch, L, core, wl, dtype, n_ckpt, steps, warmup, theta):
 def cpu_baseline(wl_name):
     """The CPU oracle, as it stands, on a bounded sample of the workload.
 
-    The 32-qubit state does not fit the oracle's NumPy temporaries on the
-    host, so the sample is the same workload shape at 20 qubits: a 2 x 5
+    The 28- and 32-qubit states do not fit the oracle's NumPy temporaries on
+    the host, so the sample is the same workload shape at 20 qubits: a 2 x 5
     open Hubbard lattice (t = 1, U = 4, snake order), the same ansatz at 4
     layers, energy + adjoint gradient by the oracle's gate-by-gate reverse
-    sweep.  Its
-    time is scaled to the 32-qubit step by 2^(32-20) (state size) times the
-    ratio of (3 gates + terms) (gate sweeps of psi forward and of psi, lam in
-    reverse, plus one sweep per Hamiltonian term).
+    sweep.  Its time is scaled to the workload's step by 2^(n-20) (state
+    size) times the ratio of (3 gates + terms) (gate sweeps of psi forward
+    and of psi, lam in reverse, plus one sweep per Hamiltonian term).
+    Lattice workloads only.
     """
     import synth
     from oracle import grad as ogr, hamiltonian as oham, statevector as osv
@@ -145,7 +172,8 @@ def cpu_baseline(wl_name):
     return dict(value=1.0 / (t * scale), unit="evals/s", cores=1, kind="oracle",
                 sample=(f"oracle energy+adjoint gradient of a 20-qubit 2x5 Hubbard lattice with the same "
                         f"ansatz at {ls} layers ({len(gates)} gates) took {t:.2f} s on 1 host core; scaled by "
-                        f"2^12 x (3*gates+terms) ratio, {scale:.0f} in all, to the 32-qubit step"),
+                        f"2^{wl.n_qubits - ns} x (3*gates+terms) ratio, {scale:.0f} in all, to the "
+                        f"{wl.n_qubits}-qubit step"),
                 sample_seconds=t, host_cpus=os.cpu_count())
 
 
@@ -294,7 +322,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hubbard4x4")
+    ap.add_argument("--workload", default="hubbard4x4",
+                    help="hubbard4x4 (the 32-qubit step), hubbard2x7 (28 qubits, batch of 8 vectors), "
+                         "molecule_16 (32 qubits), molecule_10, hubbard1d_6")
+    ap.add_argument("--threshold", type=float, default=None,
+                    help="slimming threshold of molecule-shaped workloads (default: the workload's largest)")
     ap.add_argument("--skip-c64", action="store_true")
     ap.add_argument("--skip-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -327,12 +359,12 @@ def main():
         copy_calibration(args)
         return
     wl = synth.WORKLOADS[args.workload]
-    theta = wl.thetas()[0]
+    thetas = wl.thetas()
     res = {}
     if not args.skip_c128:
-        res["c128"] = run_dtype(torch, L, core, wl, L.VQE_C128, 1, args.steps, args.warmup, theta)
+        res["c128"] = run_dtype(torch, L, core, wl, L.VQE_C128, 1, args.steps, args.warmup, thetas, args.threshold)
     if not args.skip_c64:
-        res["c64"] = run_dtype(torch, L, core, wl, L.VQE_C64, 4, args.steps, args.warmup, theta)
+        res["c64"] = run_dtype(torch, L, core, wl, L.VQE_C64, 4, args.steps, args.warmup, thetas, args.threshold)
     head = res["c128"] if "c128" in res else res["c64"]
 
     n_rev, ms_rev, b_rev = head["prof"][L.KERNEL_WINDOW_REV]
@@ -347,7 +379,7 @@ def main():
                                      frac=(b / cnt) / (ms / cnt * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                      share=ms / (head["sec"] * 1e3 * args.steps))
     out = {
-        "metric": "VQE energy+adjoint-grad evals/s at 32q",
+        "metric": f"VQE energy+adjoint-grad evals/s at {wl.n_qubits}q",
         "value": 1.0 / head["sec"],
         "unit": "evals/s",
         "n_gpus": 1,
@@ -360,9 +392,11 @@ def main():
         "dtype": "f64" if head["name"] == "c128" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{wl.name}: 2-D Fermi-Hubbard 4x4 open, t=1, U=4, JW snake order, {wl.n_qubits} qubits, "
-                        f"{head['n_terms']} Pauli terms / {head['n_groups']} X-groups; {wl.layers}-layer RY/RZ/CNOT "
-                        f"ansatz ({head['n_gates']} gates, {wl.n_params} params, seed {wl.theta_seed}); "
+            "workload": f"{wl.name}: {WORKLOAD_TEXT.get(wl.name, wl.kind)}, {wl.n_qubits} qubits, "
+                        + (f"slimmed at |w| >= {head['threshold']:g}, " if head["threshold"] is not None else "")
+                        + f"{head['n_terms']} Pauli terms / {head['n_groups']} X-groups; {wl.layers}-layer RY/RZ/CNOT "
+                        f"ansatz ({head['n_gates']} gates, {wl.n_params} params, seed {wl.theta_seed}"
+                        + (f", {len(thetas)} parameter vectors cycled" if len(thetas) > 1 else "") + "); "
                         f"{head['name']} state, {head['n_ckpt']} checkpoint(s); energy + adjoint gradient",
             "n_qubits": wl.n_qubits,
             "state": head["name"],
@@ -393,7 +427,7 @@ def main():
                           n_ckpt=a["n_ckpt"],
                           window_rev_frac=(a["prof"][1][2] / a["prof"][1][0]) / (a["prof"][1][1] / a["prof"][1][0] * 1e-3)
                           / 1e9 / HBM_PEAK_GBS if a["prof"][1][0] else None)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and wl.kind != "molecule":
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
