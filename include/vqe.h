@@ -265,7 +265,8 @@ int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* it
  * time in milliseconds and their summed algorithmic bytes (the bytes the
  * method must move: 2 S per forward window pass, 4 S per reverse window
  * pass, (1 + D) S read + S written for H psi where D is the number of
- * distinct partner tiles, S per per-term sweep; S = state bytes). */
+ * distinct partner tiles, or 2 S (first) / 3 S (others) per window pass of H
+ * psi, S per per-term sweep; S = state bytes). */
 #define VQE_KERNEL_WINDOW_FWD  0
 #define VQE_KERNEL_WINDOW_REV  1
 #define VQE_KERNEL_HPSI        2
@@ -275,6 +276,19 @@ int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* it
 int vqe_profile_enable(int on);
 int vqe_profile_reset(void);
 int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* bytes);
+
+/* Inspection of how lam = H psi (vqe_apply_hamiltonian, the adjoint of
+ * vqe_energy_grad) runs for this Hamiltonian.  Host only.
+ *   Tile form (*n_windows = 0): one sweep over tiles of 1024 amplitudes that
+ *     reads the partner tile of every distinct out-of-tile x: (1 + D) S read,
+ *     S written (D = distinct non-zero x >> 10, S = state bytes).
+ *   Window form (*n_windows = m > 0): m passes over 12-qubit windows that
+ *     all contain qubits 0..2, every X group inside one window; a pass reads
+ *     psi and writes lam (the first) or reads and writes it (the others):
+ *     (3 m - 1) S.  Chosen when it moves fewer bytes; n >= 12 only.
+ * window_masks (capacity entries, may be NULL) receives each window's qubit
+ * mask in pass order. */
+int vqe_hamiltonian_plan(const vqe_hamiltonian* h, size_t* n_windows, uint64_t* window_masks, size_t capacity);
 
 /* ------------------------------------------------------------------ kernel form
  * Window passes of the ansatz (eq. 6) and of the adjoint sweep run either as

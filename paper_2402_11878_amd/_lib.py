@@ -84,6 +84,7 @@ _SIGS = {
     "vqe_batch_free": (C.c_int, [_P]),
     "vqe_batch_energy_grad": (C.c_int, [_P, _SZ, C.POINTER(vqe_batch_item)]),
     "vqe_set_specialize": (C.c_int, [C.c_int]),
+    "vqe_hamiltonian_plan": (C.c_int, [_P, C.POINTER(_SZ), C.POINTER(C.c_uint64), _SZ]),
     "vqe_circuit_prepare": (C.c_int, [_P, C.c_int]),
     "vqe_profile_enable": (C.c_int, [C.c_int]),
     "vqe_profile_reset": (C.c_int, []),
@@ -219,6 +220,15 @@ def vqe_hamiltonian_info(h):
     nt, ng, idw = _SZ(), _SZ(), C.c_double()
     check("vqe_hamiltonian_info", lib().vqe_hamiltonian_info(h, C.byref(nt), C.byref(ng), C.byref(idw)))
     return nt.value, ng.value, idw.value
+
+
+def vqe_hamiltonian_plan(h):
+    """Qubit masks of the window passes of H psi (empty list: the tile form)."""
+    m = _SZ()
+    check("vqe_hamiltonian_plan", lib().vqe_hamiltonian_plan(h, C.byref(m), None, 0))
+    arr = (C.c_uint64 * max(m.value, 1))()
+    check("vqe_hamiltonian_plan", lib().vqe_hamiltonian_plan(h, C.byref(m), arr, m.value))
+    return [int(v) for v in arr[: m.value]]
 
 
 def vqe_expect_pauli(s, h, mode=EXPECT_GROUPED):

@@ -114,6 +114,14 @@ struct vqe_hamiltonian {
     GroupDesc* d_groups = nullptr;
     TermDesc<float>* d_t32 = nullptr;
     TermDesc<double>* d_t64 = nullptr;
+    // window-pass form of lam = H psi (empty when the tile kernel moves fewer bytes)
+    std::vector<HwDesc> hw_wins;
+    std::vector<HwGroup> hw_groups;
+    std::vector<HwTerm<float>> hw_t32;
+    std::vector<HwTerm<double>> hw_t64;
+    HwGroup* d_hw_groups = nullptr;
+    HwTerm<float>* d_hw_t32 = nullptr;
+    HwTerm<double>* d_hw_t64 = nullptr;
 };
 
 struct vqe_batch {
@@ -234,7 +242,126 @@ int upload_hamiltonian(const vqe_hamiltonian* ch) {
     VQE_HIP(hipMemcpy(h->d_groups, h->groups.data(), h->groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
     VQE_HIP(hipMemcpy(h->d_t32, h->t32.data(), h->t32.size() * sizeof(TermDesc<float>), hipMemcpyHostToDevice));
     VQE_HIP(hipMemcpy(h->d_t64, h->t64.data(), h->t64.size() * sizeof(TermDesc<double>), hipMemcpyHostToDevice));
+    if (!h->hw_wins.empty()) {
+        if (hipMalloc((void**)&h->d_hw_groups, h->hw_groups.size() * sizeof(HwGroup)) != hipSuccess ||
+            hipMalloc((void**)&h->d_hw_t32, h->hw_t32.size() * sizeof(HwTerm<float>)) != hipSuccess ||
+            hipMalloc((void**)&h->d_hw_t64, h->hw_t64.size() * sizeof(HwTerm<double>)) != hipSuccess) {
+            set_error("hipMalloc of the window-pass Hamiltonian tables failed");
+            return VQE_ERR_OOM;
+        }
+        VQE_HIP(hipMemcpy(h->d_hw_groups, h->hw_groups.data(), h->hw_groups.size() * sizeof(HwGroup),
+                          hipMemcpyHostToDevice));
+        VQE_HIP(hipMemcpy(h->d_hw_t32, h->hw_t32.data(), h->hw_t32.size() * sizeof(HwTerm<float>),
+                          hipMemcpyHostToDevice));
+        VQE_HIP(hipMemcpy(h->d_hw_t64, h->hw_t64.data(), h->hw_t64.size() * sizeof(HwTerm<double>),
+                          hipMemcpyHostToDevice));
+    }
     return VQE_OK;
+}
+
+// Window-pass plan of lam = H psi (see HwDesc): a greedy cover of the X
+// masks by windows of kHwBits qubits that contain qubits 0..kHwLow-1.  A
+// window grows one qubit at a time, taking the qubit with the largest
+// sum over the uncovered masks containing it of 1 / (their bits still
+// outside the window), so that nearly complete masks weigh most; it takes
+// every mask inside it.  Kept only if its (3 m - 1) S of traffic (m
+// windows; psi read per pass, lam written once and read-modify-written
+// m - 1 times) is below the tile kernel's (D + 2) S.
+void plan_hwin(vqe_hamiltonian* h) {
+    const int n = h->n;
+    if (n < kHwBits) return;
+    const uint64_t low = (1ull << kHwLow) - 1;
+    const size_t G = h->groups.size();
+    std::vector<int> win_of(G, -1);
+    std::vector<size_t> rem;
+    for (size_t g = 0; g < G; ++g) {
+        if (__builtin_popcountll(h->groups[g].x | low) > kHwBits) return;  // a mask no window can hold
+        if ((h->groups[g].x & ~low) == 0) win_of[g] = 0;
+        else rem.push_back(g);
+    }
+    if (rem.size() > 4096) return;  // planning cost; such Hamiltonians stay on the tile kernel
+    std::vector<uint64_t> wins;
+    while (!rem.empty() || wins.empty()) {
+        uint64_t W = low;
+        while (__builtin_popcountll(W) < kHwBits) {
+            int best = -1;
+            double best_score = 0.0;
+            for (int q = 0; q < n; ++q) {
+                if ((W >> q) & 1) continue;
+                double sc = 0.0;
+                for (size_t g : rem) {
+                    const uint64_t x = h->groups[g].x;
+                    if (!((x >> q) & 1)) continue;
+                    const int outside = __builtin_popcountll(x & ~W);
+                    if (__builtin_popcountll(W) + outside <= kHwBits) sc += 1.0 / outside;
+                }
+                if (sc > best_score) {
+                    best_score = sc;
+                    best = q;
+                }
+            }
+            if (best < 0) break;
+            W |= 1ull << best;
+        }
+        for (int q = 0; q < n && __builtin_popcountll(W) < kHwBits; ++q) W |= 1ull << q;  // fill up
+        const int wi = (int)wins.size();
+        std::vector<size_t> left;
+        for (size_t g : rem) {
+            if ((h->groups[g].x & ~W) == 0) win_of[g] = wi;
+            else left.push_back(g);
+        }
+        if (left.size() == rem.size() && !rem.empty()) return;  // no progress
+        rem.swap(left);
+        wins.push_back(W);
+    }
+    std::vector<uint64_t> hi;
+    for (const auto& g : h->groups)
+        if (g.x >> kTileBits) hi.push_back(g.x >> kTileBits);
+    std::sort(hi.begin(), hi.end());
+    const size_t D = std::unique(hi.begin(), hi.end()) - hi.begin();
+    if (3 * wins.size() - 1 >= D + 2) return;
+    for (size_t wi = 0; wi < wins.size(); ++wi) {
+        HwDesc d{};
+        int k = 0, local[64];
+        for (int q = 0; q < n; ++q)
+            if ((wins[wi] >> q) & 1) {
+                local[q] = k;
+                d.pos[k++] = (uint32_t)q;
+            }
+        auto compress = [&](uint64_t m) {
+            uint32_t r = 0;
+            for (int q = 0; q < n; ++q)
+                if ((m >> q) & 1) r |= 1u << local[q];
+            return r;
+        };
+        d.g_begin = (uint32_t)h->hw_groups.size();
+        for (size_t g = 0; g < G; ++g) {
+            if (win_of[g] != (int)wi) continue;
+            const GroupDesc& gd = h->groups[g];
+            HwGroup hg{};
+            hg.xl = compress(gd.x);
+            hg.t_begin = (uint32_t)h->hw_t64.size();
+            for (uint32_t t = gd.begin; t < gd.end; ++t) {
+                const uint64_t z = h->t64[t].z;
+                HwTerm<double> t64{};
+                t64.zo = z & ~wins[wi];
+                t64.zl = compress(z & wins[wi]);
+                t64.cre = h->t64[t].cre;
+                t64.cim = h->t64[t].cim;
+                HwTerm<float> t32{};
+                t32.zo = t64.zo;
+                t32.zl = t64.zl;
+                t32.cre = h->t32[t].cre;
+                t32.cim = h->t32[t].cim;
+                h->hw_t64.push_back(t64);
+                h->hw_t32.push_back(t32);
+            }
+            hg.t_end = (uint32_t)h->hw_t64.size();
+            h->hw_groups.push_back(hg);
+        }
+        d.g_end = (uint32_t)h->hw_groups.size();
+        h->hw_wins.push_back(d);
+    }
 }
 
 // Per-block partial-sum buffer of a state: room for the largest launch
@@ -561,6 +688,37 @@ const TermDesc<float>* terms_of<float>(const vqe_hamiltonian* h) { return h->d_t
 template <>
 const TermDesc<double>* terms_of<double>(const vqe_hamiltonian* h) { return h->d_t64; }
 
+template <typename T>
+const HwTerm<T>* hw_terms_of(const vqe_hamiltonian* h);
+template <>
+const HwTerm<float>* hw_terms_of<float>(const vqe_hamiltonian* h) { return h->d_hw_t32; }
+template <>
+const HwTerm<double>* hw_terms_of<double>(const vqe_hamiltonian* h) { return h->d_hw_t64; }
+
+double hpsi_bytes(const vqe_hamiltonian* h, const vqe_state* s, bool write);
+
+// lam = H psi with the energy partials reduced into d_out[0..1]
+// (Re<psi|lam>, <psi|psi>): window passes when planned, else the tile kernel.
+template <typename T>
+int apply_h(vqe_state* psi, void* lam, const vqe_hamiltonian* h, double* d_out) {
+    hipStream_t st = psi->stream;
+    uint32_t nb = 0;
+    if (!h->hw_wins.empty()) {
+        const size_t m = h->hw_wins.size();
+        for (size_t wi = 0; wi < m; ++wi) {
+            ProfScope ps(VQE_KERNEL_HPSI, (wi ? 3.0 : 2.0) * (double)psi->bytes, st);
+            VQE_HIP(launch_hwin<T>(psi->n, h->hw_wins[wi], psi->data, lam, h->d_hw_groups, hw_terms_of<T>(h),
+                                   wi == 0, wi + 1 == m, psi->d_part, &nb, st));
+        }
+    } else {
+        ProfScope ps(VQE_KERNEL_HPSI, hpsi_bytes(h, psi, true), st);
+        VQE_HIP(launch_hpsi<T>(psi->n, psi->data, lam, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 0,
+                               psi->d_part, &nb, st));
+    }
+    VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, d_out, 0, st));
+    return VQE_OK;
+}
+
 // Algorithmic bytes of one H psi sweep: own tile + one partner tile per
 // distinct out-of-tile partner offset (x >> tile bits), plus the write of lam.
 // The energy-only sweep visits each out-of-tile pair once (half the partners).
@@ -663,13 +821,8 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
     VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, st));
     rc = forward<T>(psi, c, pl, params, bounds, ck);
     if (rc) return rc;
-    uint32_t nb = 0;
-    {
-        ProfScope ps(VQE_KERNEL_HPSI, hpsi_bytes(h, psi, true), st);
-        VQE_HIP(launch_hpsi<T>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(),
-                               terms_of<T>(h), 0, psi->d_part, &nb, st));
-    }
-    VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, d_e, 0, st));
+    rc = apply_h<T>(psi, lam->data, h, d_e);
+    if (rc) return rc;
     VQE_HIP(launch_zero(d_g, c->n_params, st));
     const int d = sizeof(T) == 8 ? 1 : 0;
     const Mat2<T>* mats = (const Mat2<T>*)psi->d_mats;  // uploaded by forward()
@@ -1401,6 +1554,7 @@ int vqe_hamiltonian_create(int n_qubits, const uint64_t* x, const uint64_t* z, c
         t64[t] = TermDesc<double>{h->z[t], cre, cim};
         t32[t] = TermDesc<float>{h->z[t], (float)cre, (float)cim};
     }
+    plan_hwin(h);
     *out = h;
     return VQE_OK;
     VQE_GUARD_END
@@ -1411,7 +1565,30 @@ int vqe_hamiltonian_free(vqe_hamiltonian* h) {
     if (h->d_groups) (void)hipFree(h->d_groups);
     if (h->d_t32) (void)hipFree(h->d_t32);
     if (h->d_t64) (void)hipFree(h->d_t64);
+    if (h->d_hw_groups) (void)hipFree(h->d_hw_groups);
+    if (h->d_hw_t32) (void)hipFree(h->d_hw_t32);
+    if (h->d_hw_t64) (void)hipFree(h->d_hw_t64);
     delete h;
+    return VQE_OK;
+}
+
+int vqe_hamiltonian_plan(const vqe_hamiltonian* h, size_t* n_windows, uint64_t* window_masks, size_t capacity) {
+    if (!h || !n_windows) {
+        set_error("vqe_hamiltonian_plan: null argument");
+        return VQE_ERR_ARG;
+    }
+    *n_windows = h->hw_wins.size();
+    if (window_masks) {
+        if (capacity < h->hw_wins.size()) {
+            set_error("vqe_hamiltonian_plan: window_masks capacity too small");
+            return VQE_ERR_ARG;
+        }
+        for (size_t i = 0; i < h->hw_wins.size(); ++i) {
+            uint64_t m = 0;
+            for (int k = 0; k < kHwBits; ++k) m |= 1ull << h->hw_wins[i].pos[k];
+            window_masks[i] = m;
+        }
+    }
     return VQE_OK;
 }
 
@@ -1460,17 +1637,9 @@ int vqe_apply_hamiltonian(vqe_state* psi, vqe_state* lam, const vqe_hamiltonian*
     if ((rc = ensure_part(psi))) return rc;
     rc = ensure_res(psi, 2);
     if (rc) return rc;
-    uint32_t nb = 0;
-    {
-        ProfScope ps(VQE_KERNEL_HPSI, hpsi_bytes(h, psi, true), psi->stream);
-        if (psi->dtype == VQE_C64)
-            VQE_HIP(launch_hpsi<float>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(),
-                                       h->d_t32, 0, psi->d_part, &nb, psi->stream));
-        else
-            VQE_HIP(launch_hpsi<double>(psi->n, psi->data, lam->data, h->d_groups, (uint32_t)h->groups.size(),
-                                        h->d_t64, 0, psi->d_part, &nb, psi->stream));
-    }
-    VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, psi->d_res, 0, psi->stream));
+    rc = psi->dtype == VQE_C64 ? apply_h<float>(psi, lam->data, h, psi->d_res)
+                               : apply_h<double>(psi, lam->data, h, psi->d_res);
+    if (rc) return rc;
     VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, psi->stream));
     VQE_HIP(hipStreamSynchronize(psi->stream));
     if (energy) *energy = psi->h_res[0] / psi->h_res[1];

@@ -815,6 +815,137 @@ hpsi_kernel(int n, int tb, uint32_t tpb, const typename VecOf<T>::type* __restri
     }
 }
 
+// ---------------------------------------------------------------- H psi window pass
+// One block per coset at a time (persistent grid, block-contiguous runs of
+// cosets in XCD-aware order).  Thread t of kHwThreads holds the window
+// patterns j = t + kHwThreads r (r < R): the coset of psi is staged in LDS,
+// the lam accumulators stay in registers.  For a group with x inside the window the
+// partner psi[b ^ x] is psi_coset[j ^ xl] from LDS; the Z parity of a term
+// splits into the coset base's outside bits (uniform) and the window bits
+// (per pattern).
+constexpr int kHwThreads = 512;  // 16 waves per CU at two 64 KiB blocks
+
+template <typename T>
+__global__ void __launch_bounds__(kHwThreads)
+hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
+            const typename VecOf<T>::type* __restrict__ psi, typename VecOf<T>::type* __restrict__ lam,
+            const HwGroup* __restrict__ groups, const HwTerm<T>* __restrict__ terms, int first, int last,
+            double* __restrict__ part) {
+    using V = typename VecOf<T>::type;
+    constexpr int R = (1 << kHwBits) / kHwThreads;
+    constexpr int TB = 9;  // log2(kHwThreads): window bits 0..8 come from the thread index
+    static_assert((1 << TB) == kHwThreads && R * kHwThreads == (1 << kHwBits), "window pass layout");
+    __shared__ V sp[1 << kHwBits];
+    __shared__ double red[2][kHwThreads];
+    const int t = threadIdx.x;
+    uint64_t bitval[kHwBits];
+#pragma unroll
+    for (int k = 0; k < kHwBits; ++k) bitval[k] = 1ull << w.pos[k];
+    uint64_t off_t = 0;
+#pragma unroll
+    for (int k = 0; k < TB; ++k)
+        if ((t >> k) & 1) off_t += bitval[k];
+    double e_acc = 0.0, n_acc = 0.0;
+    for (uint32_t it = 0; it < cpt; ++it) {
+        const uint64_t c = xcd_order((uint64_t)blockIdx.x * cpt + it, mlog);
+        if (c >= n_cosets) break;
+        uint64_t base = c;
+#pragma unroll
+        for (int k = 0; k < kHwBits; ++k) {
+            const uint64_t low = base & (bitval[k] - 1);
+            base = ((base ^ low) << 1) | low;
+        }
+        // Stage psi in LDS (all loads of the coset issued before the first
+        // write waits), then hold only the lam accumulators in registers.
+        auto addr = [&](int r) {
+            uint64_t idx = base + off_t;
+#pragma unroll
+            for (int k = 0; k < kHwBits - TB; ++k)
+                if ((r >> k) & 1) idx += bitval[TB + k];
+            return idx;
+        };
+        {
+            V ps[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) ps[r] = psi[addr(r)];
+#pragma unroll
+            for (int r = 0; r < R; ++r) sp[t + kHwThreads * r] = ps[r];
+        }
+        T lr[R], li[R];
+        if (first) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                lr[r] = 0;
+                li[r] = 0;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const V l = lam[addr(r)];
+                lr[r] = l.x;
+                li[r] = l.y;
+            }
+        }
+        __syncthreads();
+        for (uint32_t g = w.g_begin; g < w.g_end; ++g) {
+            const HwGroup G = groups[g];
+            // D_x(b) for 4 patterns at a time (bounded registers), then lam += D psi[b ^ x]
+#pragma unroll
+            for (int r0 = 0; r0 < R; r0 += 4) {
+                T dr[4] = {0, 0, 0, 0}, di[4] = {0, 0, 0, 0};
+                for (uint32_t k = G.t_begin; k < G.t_end; ++k) {
+                    const HwTerm<T> tm = terms[k];
+                    const uint32_t s0 = (__popcll(tm.zo & base) ^ __popc(tm.zl & (uint32_t)t)) & 1u;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t par = s0 ^ (__popc(tm.zl & ((uint32_t)(r0 + q) << TB)) & 1u);
+                        dr[q] += par ? -tm.cre : tm.cre;
+                        di[q] += par ? -tm.cim : tm.cim;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = r0 + q;
+                    const V pv = sp[(t + kHwThreads * r) ^ G.xl];
+                    lr[r] += dr[q] * pv.x - di[q] * pv.y;
+                    li[r] += dr[q] * pv.y + di[q] * pv.x;
+                }
+            }
+        }
+        T e_t = 0, n_t = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            V o;
+            o.x = lr[r];
+            o.y = li[r];
+            lam[addr(r)] = o;
+            const V pv = sp[t + kHwThreads * r];
+            e_t += pv.x * lr[r] + pv.y * li[r];
+            n_t += pv.x * pv.x + pv.y * pv.y;
+        }
+        if (last) {
+            e_acc += (double)e_t;
+            n_acc += (double)n_t;
+        }
+        __syncthreads();  // the next coset overwrites the LDS copy
+    }
+    if (!last) return;
+    red[0][t] = e_acc;
+    red[1][t] = n_acc;
+    __syncthreads();
+    for (int s2 = kHwThreads / 2; s2 > 0; s2 >>= 1) {
+        if (t < s2) {
+            red[0][t] += red[0][t + s2];
+            red[1][t] += red[1][t + s2];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        part[2 * blockIdx.x + 0] = red[0][0];
+        part[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
 // ---------------------------------------------------------------- one term
 // x != 0: visit each pair (b, b^x) once (bit h of b clear) and add
 // 2 Re(conj(psi_b) c (-1)^{z.b} psi_{b^x}); x = 0: sum (-1)^{z.b} |psi_b|^2.
@@ -1088,6 +1219,20 @@ hipError_t launch_window_jit(void* fn, const JitArgs& a, int S, const void* mats
 
 
 template <typename T>
+hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const HwGroup* groups,
+                       const HwTerm<T>* terms, bool first, bool last, double* part, uint32_t* nblocks,
+                       hipStream_t st) {
+    using V = typename VecOf<T>::type;
+    if (n < kHwBits) return hipErrorInvalidValue;
+    WinShape ws{};
+    grid_for_units(1ull << (n - kHwBits), true, ws);
+    *nblocks = ws.grid;
+    hipLaunchKernelGGL(hwin_kernel<T>, dim3(ws.grid), dim3(kHwThreads), 0, st, w, 1ull << (n - kHwBits), ws.cpt, ws.mlog,
+                       (const V*)psi, (V*)lam, groups, terms, first ? 1 : 0, last ? 1 : 0, part);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* groups, uint32_t n_groups,
                        const TermDesc<T>* terms, int mode, double* part, uint32_t* nblocks, hipStream_t st) {
     using V = typename VecOf<T>::type;
@@ -1142,6 +1287,8 @@ template hipError_t launch_window_fwd<float>(const PassArgs<float>&, int, const 
 template hipError_t launch_window_fwd<double>(const PassArgs<double>&, int, const void*, void*, hipStream_t);
 template hipError_t launch_window_rev<float>(const PassArgs<float>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
 template hipError_t launch_window_rev<double>(const PassArgs<double>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hwin<float>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwTerm<float>*, bool, bool, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hwin<double>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwTerm<double>*, bool, bool, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_expect_term<float>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);

@@ -207,6 +207,41 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
 int jit_prepare(const std::vector<std::string>& srcs, std::vector<void*>& fns, std::string& err);
 size_t jit_cached();
 
+// ---------------------------------------------------------------- H psi by window passes
+// lam = H psi as a few passes over qubit windows of kHwBits qubits that all
+// contain qubits 0 .. kHwLow-1 (contiguous runs per load): every X group lies
+// in one window, a pass stages each coset (the 2^kHwBits amplitudes that
+// differ only in the window bits) of psi in LDS and adds the contributions of
+// its groups to lam (written by the first pass, read-modify-written by the
+// others); the last pass also reduces (Re<psi|lam>, <psi|psi>).
+constexpr int kHwBits = 12;
+constexpr int kHwLow = 3;
+
+struct HwDesc {
+    uint32_t pos[kHwBits];    // window qubits, ascending
+    uint32_t g_begin, g_end;  // this window's groups in the group table
+};
+
+struct HwGroup {
+    uint32_t xl;              // x mask in window-local bits
+    uint32_t t_begin, t_end;  // terms in the term table
+    uint32_t pad;
+};
+
+template <typename T>
+struct HwTerm {
+    uint64_t zo;  // z bits outside the window (parity from the coset base)
+    uint32_t zl;  // z bits inside the window, window-local
+    uint32_t pad;
+    T cre, cim;   // folded coefficient, as in TermDesc
+};
+
+// One window pass; returns the block count (partials of the last pass).
+template <typename T>
+hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const HwGroup* groups,
+                       const HwTerm<T>* terms, bool first, bool last, double* part, uint32_t* nblocks,
+                       hipStream_t st);
+
 // H psi tile kernel.  mode 0: lam = H psi and (Re<psi|lam>, <psi|psi>) partials.
 // mode 1: energy partials only, off-tile groups visited once per pair.
 template <typename T>

@@ -235,3 +235,43 @@ def test_library_owned_state_and_errors():
     finally:
         _lib.vqe_state_free(sh)
         _lib.vqe_state_free(sh2)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("case", ["chain8", "ladder2x4", "molecule7"])
+def test_apply_hamiltonian_window_form(case, dt):
+    """lam = H psi and the energy by window passes (12-qubit windows over the
+    X groups) against the oracle's term-by-term H psi, element by element."""
+    dtype = DT[dt]
+    if case == "chain8":
+        n, H = 16, oham.hubbard(8, synth.chain_bonds(8), 1.0, 4.0)
+    elif case == "ladder2x4":
+        n, H = 16, oham.hubbard(8, synth.snake_bonds(2, 4, False), 1.0, 8.0)
+    else:
+        h1, g2 = synth.molecule_integrals(7, 4)
+        Hf = oham.molecule(h1, g2)
+        x, z, w = oham.to_masks(Hf)
+        k = np.abs(w) >= 1e-3
+        n, H = 14, oham.from_masks(14, x[k], z[k], w[k])
+    arr, P = ansatz.layered(n, 2), 4 * n
+    th = synth.theta(3, P)
+    say(f"case window-form H psi {case} n={n} {dt}")
+    psi_ref = osv.run(n, oracle_gates(arr), th)
+    E_ref, _ = oex.energy(psi_ref, n, H)
+    lam_ref = oex.apply_hamiltonian(psi_ref, n, H)
+    h, _ = _ham_from_oracle(H, n)
+    assert len(_lib.vqe_hamiltonian_plan(h)) >= 1
+    c = _lib.vqe_circuit_create(n, arr)
+    s, l = Dev(n, dtype), Dev(n, dtype)
+    try:
+        _lib.vqe_state_set_basis(s.h, 0)
+        _lib.vqe_apply_circuit(s.h, c, th)
+        E, _ = _lib.vqe_apply_hamiltonian(s.h, l.h, h)
+        assert rel_err(E, E_ref) <= tol_energy(dtype)
+        lam = l.read()
+        scale = max(np.max(np.abs(lam_ref)), 1.0)
+        assert np.max(np.abs(lam - lam_ref)) / scale <= (1e-12 if dtype == _lib.VQE_C128 else 2e-5)
+    finally:
+        s.free(), l.free()
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)

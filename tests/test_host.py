@@ -395,3 +395,43 @@ def test_cutoff_ratio_rule():
     assert cutoff_ratio(lambda k: E[k], 1e-5) == 0.9   # k = 8 misses
     assert cutoff_ratio(lambda k: E[k], 10.0) == 0.1   # never
     assert cutoff_ratio(lambda k: E[k], 0.0) == 1.1    # |E_10 - E_10| >= 0 at once
+
+
+@pytest.mark.parametrize("name,th", [("hubbard4x4", None), ("hubbard2x7", None), ("molecule_10", 1e-3),
+                                     ("molecule_10", 0.0)])
+def test_hamiltonian_window_plan_valid(name, th):
+    """Window form of H psi: 12-qubit windows holding qubits 0..2, every X mask
+    inside some window, chosen only when (3 m - 1) S < (D + 2) S."""
+    wl = synth.WORKLOADS[name]
+    if wl.kind == "molecule":
+        h, g = synth.molecule_integrals(wl.n_orb, wl.integral_seed)
+        x, z, w = lham.molecule(h, g)
+        keep, _, _ = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_THRESHOLD, th)
+        x, z, w = x[keep == 1], z[keep == 1], w[keep == 1]
+    else:
+        x, z, w = lham.from_lattice(wl.lattice)
+    h = _lib.vqe_hamiltonian_create(wl.n_qubits, x, z, w)
+    try:
+        wins = _lib.vqe_hamiltonian_plan(h)
+    finally:
+        _lib.vqe_hamiltonian_free(h)
+    D = len(set((np.unique(x) >> 10).tolist()) - {0})
+    assert wins, "expected the window form for this Hamiltonian"
+    assert 3 * len(wins) - 1 < D + 2
+    for W in wins:
+        assert bin(W).count("1") == 12 and W & 0b111 == 0b111 and W < (1 << wl.n_qubits)
+    for xm in np.unique(x).tolist():
+        assert any(int(xm) & ~W == 0 for W in wins)
+
+
+def test_hamiltonian_window_plan_small_n():
+    """At 12 qubits one window holds every qubit (one pass, 2 S); below 12
+    qubits H psi keeps the tile form."""
+    wl = synth.WORKLOADS["hubbard1d_6"]
+    x, z, w = lham.from_lattice(wl.lattice)
+    h = _lib.vqe_hamiltonian_create(wl.n_qubits, x, z, w)
+    assert _lib.vqe_hamiltonian_plan(h) == [(1 << 12) - 1]
+    _lib.vqe_hamiltonian_free(h)
+    h = _lib.vqe_hamiltonian_create(10, np.array([1, 3], np.uint64), np.array([0, 2], np.uint64), np.array([1.0, 0.5]))
+    assert _lib.vqe_hamiltonian_plan(h) == []
+    _lib.vqe_hamiltonian_free(h)
