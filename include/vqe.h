@@ -285,8 +285,11 @@ int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* byt
  *   Window form (*n_windows = m > 0): m passes over 12-qubit windows that
  *     all contain qubits 0..2, every X group inside one window; a pass reads
  *     psi and writes lam (the first) or reads and writes it (the others):
- *     (3 m - 1) S.  Chosen when it moves fewer bytes; n >= 12 only.
- * window_masks (capacity entries, may be NULL) receives each window's qubit
+ *     (3 m - 1) S.  Chosen when it moves fewer bytes; n >= 12 only.  Terms
+ *     of a group with equal z bits inside the window share one coefficient
+ *     per coset (a class); a window with more than 512 classes takes several
+ *     passes over the same qubits.
+ * window_masks (capacity entries, may be NULL) receives each pass's qubit
  * mask in pass order. */
 int vqe_hamiltonian_plan(const vqe_hamiltonian* h, size_t* n_windows, uint64_t* window_masks, size_t capacity);
 

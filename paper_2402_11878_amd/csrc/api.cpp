@@ -117,9 +117,11 @@ struct vqe_hamiltonian {
     // window-pass form of lam = H psi (empty when the tile kernel moves fewer bytes)
     std::vector<HwDesc> hw_wins;
     std::vector<HwGroup> hw_groups;
+    std::vector<HwClass> hw_classes;
     std::vector<HwTerm<float>> hw_t32;
     std::vector<HwTerm<double>> hw_t64;
     HwGroup* d_hw_groups = nullptr;
+    HwClass* d_hw_classes = nullptr;
     HwTerm<float>* d_hw_t32 = nullptr;
     HwTerm<double>* d_hw_t64 = nullptr;
 };
@@ -244,12 +246,15 @@ int upload_hamiltonian(const vqe_hamiltonian* ch) {
     VQE_HIP(hipMemcpy(h->d_t64, h->t64.data(), h->t64.size() * sizeof(TermDesc<double>), hipMemcpyHostToDevice));
     if (!h->hw_wins.empty()) {
         if (hipMalloc((void**)&h->d_hw_groups, h->hw_groups.size() * sizeof(HwGroup)) != hipSuccess ||
+            hipMalloc((void**)&h->d_hw_classes, h->hw_classes.size() * sizeof(HwClass)) != hipSuccess ||
             hipMalloc((void**)&h->d_hw_t32, h->hw_t32.size() * sizeof(HwTerm<float>)) != hipSuccess ||
             hipMalloc((void**)&h->d_hw_t64, h->hw_t64.size() * sizeof(HwTerm<double>)) != hipSuccess) {
             set_error("hipMalloc of the window-pass Hamiltonian tables failed");
             return VQE_ERR_OOM;
         }
         VQE_HIP(hipMemcpy(h->d_hw_groups, h->hw_groups.data(), h->hw_groups.size() * sizeof(HwGroup),
+                          hipMemcpyHostToDevice));
+        VQE_HIP(hipMemcpy(h->d_hw_classes, h->hw_classes.data(), h->hw_classes.size() * sizeof(HwClass),
                           hipMemcpyHostToDevice));
         VQE_HIP(hipMemcpy(h->d_hw_t32, h->hw_t32.data(), h->hw_t32.size() * sizeof(HwTerm<float>),
                           hipMemcpyHostToDevice));
@@ -265,7 +270,7 @@ int upload_hamiltonian(const vqe_hamiltonian* ch) {
 // sum over the uncovered masks containing it of 1 / (their bits still
 // outside the window), so that nearly complete masks weigh most; it takes
 // every mask inside it.  Kept only if its (3 m - 1) S of traffic (m
-// windows; psi read per pass, lam written once and read-modify-written
+// passes; psi read per pass, lam written once and read-modify-written
 // m - 1 times) is below the tile kernel's (D + 2) S.
 void plan_hwin(vqe_hamiltonian* h) {
     const int n = h->n;
@@ -314,12 +319,18 @@ void plan_hwin(vqe_hamiltonian* h) {
         rem.swap(left);
         wins.push_back(W);
     }
-    std::vector<uint64_t> hi;
-    for (const auto& g : h->groups)
-        if (g.x >> kTileBits) hi.push_back(g.x >> kTileBits);
-    std::sort(hi.begin(), hi.end());
-    const size_t D = std::unique(hi.begin(), hi.end()) - hi.begin();
-    if (3 * wins.size() - 1 >= D + 2) return;
+    // Passes: per window its groups, the terms of a group merged into classes
+    // of equal in-window z bits and sorted by them (register part first), at
+    // most kHwMaxClasses classes per pass.  A window with more classes takes
+    // several passes over the same qubits; lam accumulates over passes, so a
+    // group's classes may also be split between two of them.
+    std::vector<HwDesc> passes;
+    std::vector<HwGroup> hgroups;
+    std::vector<HwClass> hclasses;
+    std::vector<HwTerm<float>> ht32;
+    std::vector<HwTerm<double>> ht64;
+    constexpr int kBuckets = 1 << kHwRegBits;
+    const uint32_t tmask = (1u << kHwThreadBits) - 1;
     for (size_t wi = 0; wi < wins.size(); ++wi) {
         HwDesc d{};
         int k = 0, local[64];
@@ -334,34 +345,59 @@ void plan_hwin(vqe_hamiltonian* h) {
                 if ((m >> q) & 1) r |= 1u << local[q];
             return r;
         };
-        d.g_begin = (uint32_t)h->hw_groups.size();
+        d.g_begin = (uint32_t)hgroups.size();
+        d.c_begin = (uint32_t)hclasses.size();
         for (size_t g = 0; g < G; ++g) {
             if (win_of[g] != (int)wi) continue;
             const GroupDesc& gd = h->groups[g];
-            HwGroup hg{};
-            hg.xl = compress(gd.x);
-            hg.t_begin = (uint32_t)h->hw_t64.size();
-            for (uint32_t t = gd.begin; t < gd.end; ++t) {
-                const uint64_t z = h->t64[t].z;
-                HwTerm<double> t64{};
-                t64.zo = z & ~wins[wi];
-                t64.zl = compress(z & wins[wi]);
-                t64.cre = h->t64[t].cre;
-                t64.cim = h->t64[t].cim;
-                HwTerm<float> t32{};
-                t32.zo = t64.zo;
-                t32.zl = t64.zl;
-                t32.cre = h->t32[t].cre;
-                t32.cim = h->t32[t].cim;
-                h->hw_t64.push_back(t64);
-                h->hw_t32.push_back(t32);
+            std::map<uint32_t, std::vector<uint32_t>> cls;  // in-window z bits -> terms
+            for (uint32_t t = gd.begin; t < gd.end; ++t) cls[compress(h->t64[t].z & wins[wi])].push_back(t);
+            auto it = cls.begin();
+            while (it != cls.end()) {
+                if (hclasses.size() - d.c_begin == (size_t)kHwMaxClasses) {  // pass full
+                    d.g_end = (uint32_t)hgroups.size();
+                    d.c_end = (uint32_t)hclasses.size();
+                    passes.push_back(d);
+                    d.g_begin = d.g_end;
+                    d.c_begin = d.c_end;
+                }
+                HwGroup hg{};
+                hg.xl = compress(gd.x);
+                int u = 0;
+                hg.cb[0] = (uint32_t)hclasses.size();
+                for (; it != cls.end() && hclasses.size() - d.c_begin < (size_t)kHwMaxClasses; ++it) {
+                    const int bucket = (int)(it->first >> kHwThreadBits);
+                    while (u < bucket) hg.cb[++u] = (uint32_t)hclasses.size();
+                    HwClass hc{};
+                    hc.zt = it->first & tmask;
+                    hc.k_begin = (uint32_t)ht64.size();
+                    for (uint32_t t : it->second) {
+                        const uint64_t zo = h->t64[t].z & ~wins[wi];
+                        ht64.push_back(HwTerm<double>{zo, h->t64[t].cre, h->t64[t].cim});
+                        ht32.push_back(HwTerm<float>{zo, h->t32[t].cre, h->t32[t].cim});
+                    }
+                    hc.k_end = (uint32_t)ht64.size();
+                    hclasses.push_back(hc);
+                }
+                while (u < kBuckets) hg.cb[++u] = (uint32_t)hclasses.size();
+                hgroups.push_back(hg);
             }
-            hg.t_end = (uint32_t)h->hw_t64.size();
-            h->hw_groups.push_back(hg);
         }
-        d.g_end = (uint32_t)h->hw_groups.size();
-        h->hw_wins.push_back(d);
+        d.g_end = (uint32_t)hgroups.size();
+        d.c_end = (uint32_t)hclasses.size();
+        passes.push_back(d);
     }
+    std::vector<uint64_t> hi;
+    for (const auto& g : h->groups)
+        if (g.x >> kTileBits) hi.push_back(g.x >> kTileBits);
+    std::sort(hi.begin(), hi.end());
+    const size_t D = std::unique(hi.begin(), hi.end()) - hi.begin();
+    if (3 * passes.size() - 1 >= D + 2) return;
+    h->hw_wins.swap(passes);
+    h->hw_groups.swap(hgroups);
+    h->hw_classes.swap(hclasses);
+    h->hw_t32.swap(ht32);
+    h->hw_t64.swap(ht64);
 }
 
 // Per-block partial-sum buffer of a state: room for the largest launch
@@ -707,7 +743,8 @@ int apply_h(vqe_state* psi, void* lam, const vqe_hamiltonian* h, double* d_out) 
         const size_t m = h->hw_wins.size();
         for (size_t wi = 0; wi < m; ++wi) {
             ProfScope ps(VQE_KERNEL_HPSI, (wi ? 3.0 : 2.0) * (double)psi->bytes, st);
-            VQE_HIP(launch_hwin<T>(psi->n, h->hw_wins[wi], psi->data, lam, h->d_hw_groups, hw_terms_of<T>(h),
+            VQE_HIP(launch_hwin<T>(psi->n, h->hw_wins[wi], psi->data, lam, h->d_hw_groups, h->d_hw_classes,
+                                   hw_terms_of<T>(h),
                                    wi == 0, wi + 1 == m, psi->d_part, &nb, st));
         }
     } else {
@@ -1566,6 +1603,7 @@ int vqe_hamiltonian_free(vqe_hamiltonian* h) {
     if (h->d_t32) (void)hipFree(h->d_t32);
     if (h->d_t64) (void)hipFree(h->d_t64);
     if (h->d_hw_groups) (void)hipFree(h->d_hw_groups);
+    if (h->d_hw_classes) (void)hipFree(h->d_hw_classes);
     if (h->d_hw_t32) (void)hipFree(h->d_hw_t32);
     if (h->d_hw_t64) (void)hipFree(h->d_hw_t64);
     delete h;

@@ -819,25 +819,40 @@ hpsi_kernel(int n, int tb, uint32_t tpb, const typename VecOf<T>::type* __restri
 // One block per coset at a time (persistent grid, block-contiguous runs of
 // cosets in XCD-aware order).  Thread t of kHwThreads holds the window
 // patterns j = t + kHwThreads r (r < R): the coset of psi is staged in LDS,
-// the lam accumulators stay in registers.  For a group with x inside the window the
-// partner psi[b ^ x] is psi_coset[j ^ xl] from LDS; the Z parity of a term
-// splits into the coset base's outside bits (uniform) and the window bits
-// (per pattern).
-constexpr int kHwThreads = 512;  // 16 waves per CU at two 64 KiB blocks
+// the lam accumulators stay in registers.  For a group with x inside the
+// window the partner psi[b ^ x] is psi_coset[j ^ xl] from LDS.  Per coset the
+// block first computes every class coefficient A (its terms' coefficients
+// signed by the outside z bits against the coset base) into LDS; per group a
+// thread then sums its classes' A, signed by the thread part of their z
+// bits, into one bucket per register part, and a Walsh-Hadamard transform of
+// the R bucket sums gives D_x for its R patterns.
+constexpr int kHwThreads = 1 << kHwThreadBits;  // 16 waves per CU at two blocks
+
+// a with its sign flipped where m (0 or 1 << 31) is set
+__device__ __forceinline__ double flip_sign(double a, uint32_t m) {
+    return __hiloint2double(__double2hiint(a) ^ (int)m, __double2loint(a));
+}
+__device__ __forceinline__ float flip_sign(float a, uint32_t m) { return __int_as_float(__float_as_int(a) ^ (int)m); }
 
 template <typename T>
 __global__ void __launch_bounds__(kHwThreads)
 hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
             const typename VecOf<T>::type* __restrict__ psi, typename VecOf<T>::type* __restrict__ lam,
-            const HwGroup* __restrict__ groups, const HwTerm<T>* __restrict__ terms, int first, int last,
-            double* __restrict__ part) {
+            const HwGroup* __restrict__ groups, const HwClass* __restrict__ classes,
+            const HwTerm<T>* __restrict__ terms, int first, int last, double* __restrict__ part) {
     using V = typename VecOf<T>::type;
-    constexpr int R = (1 << kHwBits) / kHwThreads;
-    constexpr int TB = 9;  // log2(kHwThreads): window bits 0..8 come from the thread index
-    static_assert((1 << TB) == kHwThreads && R * kHwThreads == (1 << kHwBits), "window pass layout");
+    constexpr int R = 1 << kHwRegBits;
+    constexpr int TB = kHwThreadBits;
     __shared__ V sp[1 << kHwBits];
-    __shared__ double red[2][kHwThreads];
+    // class coefficients of the current coset; after the last coset, the block reduction
+    constexpr size_t kTabBytes = kHwMaxClasses * sizeof(V) > 2 * kHwThreads * sizeof(double)
+                                     ? kHwMaxClasses * sizeof(V)
+                                     : 2 * kHwThreads * sizeof(double);
+    __shared__ __align__(16) unsigned char tab[kTabBytes];
+    V* A = reinterpret_cast<V*>(tab);
+    double* red = reinterpret_cast<double*>(tab);
     const int t = threadIdx.x;
+    const uint32_t nc = w.c_end - w.c_begin;
     uint64_t bitval[kHwBits];
 #pragma unroll
     for (int k = 0; k < kHwBits; ++k) bitval[k] = 1ull << w.pos[k];
@@ -855,22 +870,17 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
             const uint64_t low = base & (bitval[k] - 1);
             base = ((base ^ low) << 1) | low;
         }
-        // Stage psi in LDS (all loads of the coset issued before the first
-        // write waits), then hold only the lam accumulators in registers.
         auto addr = [&](int r) {
             uint64_t idx = base + off_t;
 #pragma unroll
-            for (int k = 0; k < kHwBits - TB; ++k)
+            for (int k = 0; k < kHwRegBits; ++k)
                 if ((r >> k) & 1) idx += bitval[TB + k];
             return idx;
         };
-        {
-            V ps[R];
+        // All loads of the coset are issued before the first use waits.
+        V ps[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) ps[r] = psi[addr(r)];
-#pragma unroll
-            for (int r = 0; r < R; ++r) sp[t + kHwThreads * r] = ps[r];
-        }
+        for (int r = 0; r < R; ++r) ps[r] = psi[addr(r)];
         T lr[R], li[R];
         if (first) {
 #pragma unroll
@@ -886,30 +896,63 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
                 li[r] = l.y;
             }
         }
+        if ((uint32_t)t < nc) {
+            const HwClass C = classes[w.c_begin + t];
+            T ar = 0, ai = 0;
+            for (uint32_t k = C.k_begin; k < C.k_end; ++k) {
+                const HwTerm<T> tm = terms[k];
+                const uint32_t m = (uint32_t)(__popcll(tm.zo & base) & 1) << 31;
+                ar += flip_sign(tm.cre, m);
+                ai += flip_sign(tm.cim, m);
+            }
+            V a;
+            a.x = ar;
+            a.y = ai;
+            A[t] = a;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) sp[t + kHwThreads * r] = ps[r];
         __syncthreads();
         for (uint32_t g = w.g_begin; g < w.g_end; ++g) {
-            const HwGroup G = groups[g];
-            // D_x(b) for 4 patterns at a time (bounded registers), then lam += D psi[b ^ x]
+            const HwGroup& G = groups[g];
+            T er[R], ei[R];
 #pragma unroll
-            for (int r0 = 0; r0 < R; r0 += 4) {
-                T dr[4] = {0, 0, 0, 0}, di[4] = {0, 0, 0, 0};
-                for (uint32_t k = G.t_begin; k < G.t_end; ++k) {
-                    const HwTerm<T> tm = terms[k];
-                    const uint32_t s0 = (__popcll(tm.zo & base) ^ __popc(tm.zl & (uint32_t)t)) & 1u;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t par = s0 ^ (__popc(tm.zl & ((uint32_t)(r0 + q) << TB)) & 1u);
-                        dr[q] += par ? -tm.cre : tm.cre;
-                        di[q] += par ? -tm.cim : tm.cim;
-                    }
+            for (int u = 0; u < R; ++u) {
+                er[u] = 0;
+                ei[u] = 0;
+                for (uint32_t j = G.cb[u]; j < G.cb[u + 1]; ++j) {
+                    const uint32_t m = (uint32_t)(__popc(classes[j].zt & (uint32_t)t) & 1) << 31;
+                    const V a = A[j - w.c_begin];
+                    er[u] += flip_sign(a.x, m);
+                    ei[u] += flip_sign(a.y, m);
                 }
+            }
+            if (G.cb[1] != G.cb[R]) {
+                // D_r = sum_u (-1)^{popcount(u & r)} E_u
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = r0 + q;
-                    const V pv = sp[(t + kHwThreads * r) ^ G.xl];
-                    lr[r] += dr[q] * pv.x - di[q] * pv.y;
-                    li[r] += dr[q] * pv.y + di[q] * pv.x;
+                for (int bit = 1; bit < R; bit <<= 1)
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        if (!(i & bit)) {
+                            const T r0 = er[i], r1 = er[i | bit], i0 = ei[i], i1 = ei[i | bit];
+                            er[i] = r0 + r1;
+                            er[i | bit] = r0 - r1;
+                            ei[i] = i0 + i1;
+                            ei[i | bit] = i0 - i1;
+                        }
+            } else {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    er[r] = er[0];
+                    ei[r] = ei[0];
                 }
+            }
+            const uint32_t xl = G.xl;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const V pv = sp[(t + kHwThreads * r) ^ xl];
+                lr[r] += er[r] * pv.x - ei[r] * pv.y;
+                li[r] += er[r] * pv.y + ei[r] * pv.x;
             }
         }
         T e_t = 0, n_t = 0;
@@ -927,22 +970,22 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
             e_acc += (double)e_t;
             n_acc += (double)n_t;
         }
-        __syncthreads();  // the next coset overwrites the LDS copy
+        __syncthreads();  // the next coset overwrites both LDS tables
     }
     if (!last) return;
-    red[0][t] = e_acc;
-    red[1][t] = n_acc;
+    red[t] = e_acc;
+    red[kHwThreads + t] = n_acc;
     __syncthreads();
     for (int s2 = kHwThreads / 2; s2 > 0; s2 >>= 1) {
         if (t < s2) {
-            red[0][t] += red[0][t + s2];
-            red[1][t] += red[1][t + s2];
+            red[t] += red[t + s2];
+            red[kHwThreads + t] += red[kHwThreads + t + s2];
         }
         __syncthreads();
     }
     if (t == 0) {
-        part[2 * blockIdx.x + 0] = red[0][0];
-        part[2 * blockIdx.x + 1] = red[1][0];
+        part[2 * blockIdx.x + 0] = red[0];
+        part[2 * blockIdx.x + 1] = red[kHwThreads];
     }
 }
 
@@ -1220,15 +1263,16 @@ hipError_t launch_window_jit(void* fn, const JitArgs& a, int S, const void* mats
 
 template <typename T>
 hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const HwGroup* groups,
-                       const HwTerm<T>* terms, bool first, bool last, double* part, uint32_t* nblocks,
-                       hipStream_t st) {
+                       const HwClass* classes, const HwTerm<T>* terms, bool first, bool last, double* part,
+                       uint32_t* nblocks, hipStream_t st) {
     using V = typename VecOf<T>::type;
-    if (n < kHwBits) return hipErrorInvalidValue;
+    if (n < kHwBits || w.c_end < w.c_begin || w.c_end - w.c_begin > (uint32_t)kHwMaxClasses)
+        return hipErrorInvalidValue;
     WinShape ws{};
     grid_for_units(1ull << (n - kHwBits), true, ws);
     *nblocks = ws.grid;
     hipLaunchKernelGGL(hwin_kernel<T>, dim3(ws.grid), dim3(kHwThreads), 0, st, w, 1ull << (n - kHwBits), ws.cpt, ws.mlog,
-                       (const V*)psi, (V*)lam, groups, terms, first ? 1 : 0, last ? 1 : 0, part);
+                       (const V*)psi, (V*)lam, groups, classes, terms, first ? 1 : 0, last ? 1 : 0, part);
     return hipGetLastError();
 }
 
@@ -1287,8 +1331,10 @@ template hipError_t launch_window_fwd<float>(const PassArgs<float>&, int, const 
 template hipError_t launch_window_fwd<double>(const PassArgs<double>&, int, const void*, void*, hipStream_t);
 template hipError_t launch_window_rev<float>(const PassArgs<float>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
 template hipError_t launch_window_rev<double>(const PassArgs<double>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
-template hipError_t launch_hwin<float>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwTerm<float>*, bool, bool, double*, uint32_t*, hipStream_t);
-template hipError_t launch_hwin<double>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwTerm<double>*, bool, bool, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hwin<float>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwClass*,
+                                       const HwTerm<float>*, bool, bool, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hwin<double>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwClass*,
+                                        const HwTerm<double>*, bool, bool, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, double*, uint32_t*, hipStream_t);
 template hipError_t launch_expect_term<float>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);

@@ -214,33 +214,52 @@ size_t jit_cached();
 // differ only in the window bits) of psi in LDS and adds the contributions of
 // its groups to lam (written by the first pass, read-modify-written by the
 // others); the last pass also reduces (Re<psi|lam>, <psi|psi>).
+//
+// Window-local pattern j = t + 2^kHwThreadBits r: thread t of a block holds
+// the patterns of all r < 2^(kHwBits - kHwThreadBits).  For a group x,
+//   D_x(b) = sum_z c_z (-1)^{z.b} = sum_{zl} (-1)^{zl.j} A_{x,zl}(coset),
+//   A_{x,zl} = sum_{z: z & window = zl} c_z (-1)^{(z & ~window).base},
+// so the terms of a group with equal in-window z bits form one class whose
+// coefficient A is uniform over a coset (computed once per coset); the sign
+// (-1)^{zl.j} splits into a thread part (zl bits below kHwThreadBits) and a
+// register part, and the classes of a group are sorted into buckets by the
+// register part, whose 2^(kHwBits - kHwThreadBits) bucket sums give D for
+// every r through one Walsh-Hadamard transform.
 constexpr int kHwBits = 12;
 constexpr int kHwLow = 3;
+constexpr int kHwThreadBits = 9;        // 512 threads per block
+constexpr int kHwRegBits = kHwBits - kHwThreadBits;
+constexpr int kHwMaxClasses = 512;      // classes per pass (their coefficients are staged in LDS)
 
 struct HwDesc {
     uint32_t pos[kHwBits];    // window qubits, ascending
-    uint32_t g_begin, g_end;  // this window's groups in the group table
+    uint32_t g_begin, g_end;  // this pass's groups in the group table
+    uint32_t c_begin, c_end;  // this pass's classes in the class table (at most kHwMaxClasses)
 };
 
 struct HwGroup {
-    uint32_t xl;              // x mask in window-local bits
-    uint32_t t_begin, t_end;  // terms in the term table
+    uint32_t xl;                       // x mask in window-local bits
+    uint32_t cb[(1 << kHwRegBits) + 1];  // bucket u (register-part z bits = u): classes [cb[u], cb[u + 1])
+    uint32_t pad[2];
+};
+
+struct HwClass {
+    uint32_t zt;              // in-window z bits on the thread part (window-local bits below kHwThreadBits)
+    uint32_t k_begin, k_end;  // its terms in the term table
     uint32_t pad;
 };
 
 template <typename T>
 struct HwTerm {
     uint64_t zo;  // z bits outside the window (parity from the coset base)
-    uint32_t zl;  // z bits inside the window, window-local
-    uint32_t pad;
     T cre, cim;   // folded coefficient, as in TermDesc
 };
 
 // One window pass; returns the block count (partials of the last pass).
 template <typename T>
 hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const HwGroup* groups,
-                       const HwTerm<T>* terms, bool first, bool last, double* part, uint32_t* nblocks,
-                       hipStream_t st);
+                       const HwClass* classes, const HwTerm<T>* terms, bool first, bool last, double* part,
+                       uint32_t* nblocks, hipStream_t st);
 
 // H psi tile kernel.  mode 0: lam = H psi and (Re<psi|lam>, <psi|psi>) partials.
 // mode 1: energy partials only, off-tile groups visited once per pair.

@@ -237,13 +237,26 @@ def test_library_owned_state_and_errors():
         _lib.vqe_state_free(sh2)
 
 
+def _split_window_masks(n=14, seed=11):
+    """700 terms of one X group (qubit 0) with distinct z, more classes than
+    one pass holds, plus high-x groups that make the window form the cheaper."""
+    rng = np.random.default_rng(seed)
+    xs = [1] * 700 + [1 << 10, 1 << 11, 1 << 12, 1 << 13, (1 << 10) | (1 << 13)] * 4
+    zs = list(rng.choice(1 << n, 700, replace=False)) + list(rng.integers(0, 1 << n, 20))
+    return np.array(xs, np.uint64), np.array(zs, np.uint64), rng.normal(size=len(xs))
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("case", ["chain8", "ladder2x4", "molecule7"])
+@pytest.mark.parametrize("case", ["chain8", "ladder2x4", "molecule7", "split"])
 def test_apply_hamiltonian_window_form(case, dt):
     """lam = H psi and the energy by window passes (12-qubit windows over the
-    X groups) against the oracle's term-by-term H psi, element by element."""
+    X groups) against the oracle's term-by-term H psi, element by element;
+    "split" takes two passes over one window (more classes than a pass holds)."""
     dtype = DT[dt]
-    if case == "chain8":
+    if case == "split":
+        n = 14
+        H = oham.from_masks(n, *_split_window_masks(n))
+    elif case == "chain8":
         n, H = 16, oham.hubbard(8, synth.chain_bonds(8), 1.0, 4.0)
     elif case == "ladder2x4":
         n, H = 16, oham.hubbard(8, synth.snake_bonds(2, 4, False), 1.0, 8.0)
@@ -260,7 +273,10 @@ def test_apply_hamiltonian_window_form(case, dt):
     E_ref, _ = oex.energy(psi_ref, n, H)
     lam_ref = oex.apply_hamiltonian(psi_ref, n, H)
     h, _ = _ham_from_oracle(H, n)
-    assert len(_lib.vqe_hamiltonian_plan(h)) >= 1
+    plan = _lib.vqe_hamiltonian_plan(h)
+    assert len(plan) >= 1
+    if case == "split":
+        assert len(plan) == 2 and plan[0] == plan[1]
     c = _lib.vqe_circuit_create(n, arr)
     s, l = Dev(n, dtype), Dev(n, dtype)
     try:

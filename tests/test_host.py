@@ -424,6 +424,26 @@ def test_hamiltonian_window_plan_valid(name, th):
         assert any(int(xm) & ~W == 0 for W in wins)
 
 
+def test_hamiltonian_window_plan_splits_classes():
+    """One X group with 700 distinct z patterns on 14 qubits: its terms fall
+    into more classes (equal in-window z bits) than one pass holds (512), so
+    the window takes two passes over the same qubits."""
+    n = 14
+    rng = np.random.default_rng(11)
+    xs = [1] * 700 + [1 << 10, 1 << 11, 1 << 12, 1 << 13, (1 << 10) | (1 << 13)] * 4
+    zs = list(rng.choice(1 << n, 700, replace=False)) + list(rng.integers(0, 1 << n, 20))
+    x, z = np.array(xs, np.uint64), np.array(zs, np.uint64)
+    h = _lib.vqe_hamiltonian_create(n, x, z, rng.normal(size=len(xs)))
+    try:
+        plan = _lib.vqe_hamiltonian_plan(h)
+    finally:
+        _lib.vqe_hamiltonian_free(h)
+    assert len(plan) == 2 and plan[0] == plan[1]
+    high = 0b1111 << 10  # every x lies in qubits 0 and 10..13
+    assert plan[0] & (high | 0b111) == high | 0b111 and bin(plan[0]).count("1") == 12
+    assert 512 < len({int(zi) & plan[0] for zi in z[:700]}) <= 1024
+
+
 def test_hamiltonian_window_plan_small_n():
     """At 12 qubits one window holds every qubit (one pass, 2 S); below 12
     qubits H psi keeps the tile form."""
