@@ -264,42 +264,40 @@ int upload_hamiltonian(const vqe_hamiltonian* ch) {
     return VQE_OK;
 }
 
-// Window-pass plan of lam = H psi (see HwDesc): a greedy cover of the X
-// masks by windows of kHwBits qubits that contain qubits 0..kHwLow-1.  A
-// window grows one qubit at a time, taking the qubit with the largest
-// sum over the uncovered masks containing it of 1 / (their bits still
-// outside the window), so that nearly complete masks weigh most; it takes
-// every mask inside it.  Kept only if its (3 m - 1) S of traffic (m
-// passes; psi read per pass, lam written once and read-modify-written
-// m - 1 times) is below the tile kernel's (D + 2) S.
-void plan_hwin(vqe_hamiltonian* h) {
-    const int n = h->n;
-    if (n < kHwBits) return;
-    const uint64_t low = (1ull << kHwLow) - 1;
-    const size_t G = h->groups.size();
-    std::vector<int> win_of(G, -1);
-    std::vector<size_t> rem;
-    for (size_t g = 0; g < G; ++g) {
-        if (__builtin_popcountll(h->groups[g].x | low) > kHwBits) return;  // a mask no window can hold
-        if ((h->groups[g].x & ~low) == 0) win_of[g] = 0;
-        else rem.push_back(g);
-    }
-    if (rem.size() > 4096) return;  // planning cost; such Hamiltonians stay on the tile kernel
-    std::vector<uint64_t> wins;
+// Greedy cover of the X masks xs (none inside `low`) by windows of kHwBits
+// qubits that contain `low`.  A window grows one qubit at a time, taking the
+// qubit with the largest sum over the uncovered masks containing it (and
+// still fitting) of 1 / outside^p (outside = their bits not yet in the
+// window), so that nearly complete masks weigh most; it takes every mask
+// inside it.  With rng_state != 0 the scores are perturbed by a factor in
+// [1, 1.001) from a splitmix64 stream, which only reorders near-ties.
+// Returns the windows (empty if no progress is possible); *work counts the
+// inner-loop steps.
+std::vector<uint64_t> cover_windows(int n, const std::vector<uint64_t>& xs, uint64_t low, int p, uint64_t rng_state,
+                                    size_t* work) {
+    auto uniform = [&]() {
+        uint64_t z = (rng_state += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return (double)((z ^ (z >> 31)) >> 11) * 0x1.0p-53;
+    };
+    std::vector<uint64_t> rem = xs, wins;
     while (!rem.empty() || wins.empty()) {
         uint64_t W = low;
         while (__builtin_popcountll(W) < kHwBits) {
             int best = -1;
             double best_score = 0.0;
+            const int inside = __builtin_popcountll(W);
             for (int q = 0; q < n; ++q) {
                 if ((W >> q) & 1) continue;
                 double sc = 0.0;
-                for (size_t g : rem) {
-                    const uint64_t x = h->groups[g].x;
+                for (uint64_t x : rem) {
                     if (!((x >> q) & 1)) continue;
                     const int outside = __builtin_popcountll(x & ~W);
-                    if (__builtin_popcountll(W) + outside <= kHwBits) sc += 1.0 / outside;
+                    if (inside + outside <= kHwBits) sc += 1.0 / std::pow((double)outside, p);
                 }
+                *work += rem.size();
+                if (rng_state && sc > 0.0) sc *= 1.0 + 1e-3 * uniform();
                 if (sc > best_score) {
                     best_score = sc;
                     best = q;
@@ -309,16 +307,55 @@ void plan_hwin(vqe_hamiltonian* h) {
             W |= 1ull << best;
         }
         for (int q = 0; q < n && __builtin_popcountll(W) < kHwBits; ++q) W |= 1ull << q;  // fill up
-        const int wi = (int)wins.size();
-        std::vector<size_t> left;
-        for (size_t g : rem) {
-            if ((h->groups[g].x & ~W) == 0) win_of[g] = wi;
-            else left.push_back(g);
-        }
-        if (left.size() == rem.size() && !rem.empty()) return;  // no progress
+        std::vector<uint64_t> left;
+        for (uint64_t x : rem)
+            if (x & ~W) left.push_back(x);
+        if (left.size() == rem.size() && !rem.empty()) return {};  // no progress
         rem.swap(left);
         wins.push_back(W);
     }
+    return wins;
+}
+
+// Window-pass plan of lam = H psi (see HwDesc): the smallest of several
+// greedy covers (cover_windows with p = 1, 2, 3, each deterministic and
+// with seeded tie perturbations, as many restarts as a fixed work budget
+// allows); each group goes to the first window holding its X mask.  Kept
+// only if its (3 m - 1) S of traffic (m passes; psi read per pass, lam
+// written once and read-modify-written m - 1 times) is below the tile
+// kernel's (D + 2) S.
+void plan_hwin(vqe_hamiltonian* h) {
+    const int n = h->n;
+    if (n < kHwBits) return;
+    const uint64_t low = (1ull << kHwLow) - 1;
+    const size_t G = h->groups.size();
+    std::vector<uint64_t> xs;
+    for (size_t g = 0; g < G; ++g) {
+        if (__builtin_popcountll(h->groups[g].x | low) > kHwBits) return;  // a mask no window can hold
+        if (h->groups[g].x & ~low) xs.push_back(h->groups[g].x);
+    }
+    if (xs.size() > 4096) return;  // planning cost; such Hamiltonians stay on the tile kernel
+    constexpr size_t kWorkBudget = 200000000;  // inner-loop steps over all restarts (well under a second)
+    constexpr int kMaxRestarts = 12;
+    std::vector<uint64_t> wins;
+    size_t work = 0;
+    for (int p = 1; p <= 3; ++p) {
+        for (int r = 0; r <= kMaxRestarts; ++r) {
+            const size_t before = work;
+            std::vector<uint64_t> w = cover_windows(n, xs, low, p, r ? 0x5eedull * (uint64_t)(16 * p + r) : 0, &work);
+            if (w.empty()) return;
+            if (wins.empty() || w.size() < wins.size()) wins.swap(w);
+            if (work + 3 * (work - before) > kWorkBudget) break;  // a later restart could overrun the budget
+        }
+        if (work > kWorkBudget) break;
+    }
+    std::vector<int> win_of(G, -1);
+    for (size_t g = 0; g < G; ++g)
+        for (size_t wi = 0; wi < wins.size(); ++wi)
+            if ((h->groups[g].x & ~wins[wi]) == 0) {
+                win_of[g] = (int)wi;
+                break;
+            }
     // Passes: per window its groups, the terms of a group merged into classes
     // of equal in-window z bits and sorted by them (register part first), at
     // most kHwMaxClasses classes per pass.  A window with more classes takes
