@@ -405,6 +405,7 @@ void plan_hwin(vqe_hamiltonian* h) {
                 for (; it != cls.end() && hclasses.size() - d.c_begin < (size_t)kHwMaxClasses; ++it) {
                     const int bucket = (int)(it->first >> kHwThreadBits);
                     while (u < bucket) hg.cb[++u] = (uint32_t)hclasses.size();
+                    hg.zrm |= (uint32_t)bucket;
                     HwClass hc{};
                     hc.zt = it->first & tmask;
                     hc.k_begin = (uint32_t)ht64.size();

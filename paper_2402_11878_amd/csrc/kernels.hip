@@ -828,11 +828,88 @@ hpsi_kernel(int n, int tb, uint32_t tpb, const typename VecOf<T>::type* __restri
 // the R bucket sums gives D_x for its R patterns.
 constexpr int kHwThreads = 1 << kHwThreadBits;  // 16 waves per CU at two blocks
 
-// a with its sign flipped where m (0 or 1 << 31) is set
-__device__ __forceinline__ double flip_sign(double a, uint32_t m) {
-    return __hiloint2double(__double2hiint(a) ^ (int)m, __double2loint(a));
+// (-1)^cnt as a floating-point factor: the sign bit set from the low bit of
+// cnt on the bit pattern of 1.0.
+__device__ __forceinline__ void parity_sign(uint32_t cnt, double& s) {
+    s = __hiloint2double((int)((cnt << 31) | 0x3ff00000u), 0);
 }
-__device__ __forceinline__ float flip_sign(float a, uint32_t m) { return __int_as_float(__float_as_int(a) ^ (int)m); }
+__device__ __forceinline__ void parity_sign(uint32_t cnt, float& s) { s = __uint_as_float((cnt << 31) | 0x3f800000u); }
+
+// One group of a window pass for the patterns t + kHwThreads r of thread t:
+// bucket sums E_u over the classes (A and zt staged in LDS at local index
+// j - cbase), D_r = sum_{u in M} (-1)^{popcount(u & r)} E_u (a transform over
+// the register bits in M only: buckets outside M are empty, so D_r = D_{r & M}),
+// then lam_r += D_r psi[(t + kHwThreads r) ^ xl].
+template <typename T, int M>
+__device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint32_t t,
+                                         const typename VecOf<T>::type* A, const uint32_t* zt,
+                                         const typename VecOf<T>::type* sp, T* lr, T* li) {
+    using V = typename VecOf<T>::type;
+    constexpr int R = 1 << kHwRegBits;
+    T er[R], ei[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        if (u & ~M) continue;
+        T sr = 0, si = 0;
+        uint32_t j = G.cb[u] - cbase;
+        const uint32_t e = G.cb[u + 1] - cbase;
+        // The class index is uniform; holding a copy in a vector register lets
+        // the unrolled LDS reads share one address with immediate offsets.
+        uint32_t jv = j;
+        asm volatile("" : "+v"(jv));
+        for (; j + 4 <= e; j += 4, jv += 4) {
+            uint32_t z[4];
+            V a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                z[q] = zt[jv + q];
+                a[q] = A[jv + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T sg;
+                parity_sign((uint32_t)__popc(z[q] & t), sg);
+                sr = fma(sg, a[q].x, sr);
+                si = fma(sg, a[q].y, si);
+            }
+        }
+        for (; j < e; ++j, ++jv) {
+            T sg;
+            parity_sign((uint32_t)__popc(zt[jv] & t), sg);
+            const V a = A[jv];
+            sr = fma(sg, a.x, sr);
+            si = fma(sg, a.y, si);
+        }
+        er[u] = sr;
+        ei[u] = si;
+    }
+#pragma unroll
+    for (int bit = 1; bit < R; bit <<= 1) {
+        if (!(M & bit)) continue;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (!(i & ~M) && !(i & bit)) {
+                const T r0 = er[i], r1 = er[i | bit], i0 = ei[i], i1 = ei[i | bit];
+                er[i] = r0 + r1;
+                er[i | bit] = r0 - r1;
+                ei[i] = i0 + i1;
+                ei[i | bit] = i0 - i1;
+            }
+    }
+    // partner of pattern t + kHwThreads r: byte offset a0 + (r ^ xr) kHwThreads sizeof(V)
+    const uint32_t a0 = (t ^ (G.xl & (kHwThreads - 1))) * (uint32_t)sizeof(V);
+    const uint32_t xr = G.xl >> kHwThreadBits;
+    const char* spb = reinterpret_cast<const char*>(sp);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const V pv = *reinterpret_cast<const V*>(spb + a0 + (r ^ xr) * (uint32_t)(kHwThreads * sizeof(V)));
+        const T dr = er[r & M], di = ei[r & M];
+        lr[r] = fma(dr, pv.x, lr[r]);
+        lr[r] = fma(-di, pv.y, lr[r]);
+        li[r] = fma(dr, pv.y, li[r]);
+        li[r] = fma(di, pv.x, li[r]);
+    }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kHwThreads)
@@ -843,14 +920,20 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
     using V = typename VecOf<T>::type;
     constexpr int R = 1 << kHwRegBits;
     constexpr int TB = kHwThreadBits;
-    __shared__ V sp[1 << kHwBits];
-    // class coefficients of the current coset; after the last coset, the block reduction
+    // One LDS block, the small tables first so that their addresses fit the
+    // immediate offsets of LDS reads: the class coefficients of the current
+    // coset (after the last coset, the block reduction), their thread-part z
+    // bits, then the psi coset.
     constexpr size_t kTabBytes = kHwMaxClasses * sizeof(V) > 2 * kHwThreads * sizeof(double)
                                      ? kHwMaxClasses * sizeof(V)
                                      : 2 * kHwThreads * sizeof(double);
-    __shared__ __align__(16) unsigned char tab[kTabBytes];
-    V* A = reinterpret_cast<V*>(tab);
-    double* red = reinterpret_cast<double*>(tab);
+    constexpr size_t kZtOff = kTabBytes, kSpOff = kTabBytes + kHwMaxClasses * sizeof(uint32_t);
+    static_assert(kSpOff % 16 == 0, "psi coset alignment");
+    __shared__ __align__(16) unsigned char lds[kSpOff + (1 << kHwBits) * sizeof(V)];
+    V* A = reinterpret_cast<V*>(lds);
+    double* red = reinterpret_cast<double*>(lds);
+    uint32_t* zt = reinterpret_cast<uint32_t*>(lds + kZtOff);
+    V* sp = reinterpret_cast<V*>(lds + kSpOff);
     const int t = threadIdx.x;
     const uint32_t nc = w.c_end - w.c_begin;
     uint64_t bitval[kHwBits];
@@ -901,58 +984,32 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
             T ar = 0, ai = 0;
             for (uint32_t k = C.k_begin; k < C.k_end; ++k) {
                 const HwTerm<T> tm = terms[k];
-                const uint32_t m = (uint32_t)(__popcll(tm.zo & base) & 1) << 31;
-                ar += flip_sign(tm.cre, m);
-                ai += flip_sign(tm.cim, m);
+                T sg;
+                parity_sign((uint32_t)__popcll(tm.zo & base), sg);
+                ar = fma(sg, tm.cre, ar);
+                ai = fma(sg, tm.cim, ai);
             }
             V a;
             a.x = ar;
             a.y = ai;
             A[t] = a;
+            zt[t] = C.zt;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) sp[t + kHwThreads * r] = ps[r];
         __syncthreads();
         for (uint32_t g = w.g_begin; g < w.g_end; ++g) {
             const HwGroup& G = groups[g];
-            T er[R], ei[R];
-#pragma unroll
-            for (int u = 0; u < R; ++u) {
-                er[u] = 0;
-                ei[u] = 0;
-                for (uint32_t j = G.cb[u]; j < G.cb[u + 1]; ++j) {
-                    const uint32_t m = (uint32_t)(__popc(classes[j].zt & (uint32_t)t) & 1) << 31;
-                    const V a = A[j - w.c_begin];
-                    er[u] += flip_sign(a.x, m);
-                    ei[u] += flip_sign(a.y, m);
-                }
-            }
-            if (G.cb[1] != G.cb[R]) {
-                // D_r = sum_u (-1)^{popcount(u & r)} E_u
-#pragma unroll
-                for (int bit = 1; bit < R; bit <<= 1)
-#pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (!(i & bit)) {
-                            const T r0 = er[i], r1 = er[i | bit], i0 = ei[i], i1 = ei[i | bit];
-                            er[i] = r0 + r1;
-                            er[i | bit] = r0 - r1;
-                            ei[i] = i0 + i1;
-                            ei[i | bit] = i0 - i1;
-                        }
-            } else {
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    er[r] = er[0];
-                    ei[r] = ei[0];
-                }
-            }
-            const uint32_t xl = G.xl;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const V pv = sp[(t + kHwThreads * r) ^ xl];
-                lr[r] += er[r] * pv.x - ei[r] * pv.y;
-                li[r] += er[r] * pv.y + ei[r] * pv.x;
+            static_assert(kHwRegBits == 3, "one case per register-bit subset");
+            switch (G.zrm) {
+                case 0: hw_group<T, 0>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 1: hw_group<T, 1>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 2: hw_group<T, 2>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 3: hw_group<T, 3>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 4: hw_group<T, 4>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 5: hw_group<T, 5>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 6: hw_group<T, 6>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                default: hw_group<T, 7>(G, w.c_begin, t, A, zt, sp, lr, li); break;
             }
         }
         T e_t = 0, n_t = 0;

@@ -240,7 +240,8 @@ struct HwDesc {
 struct HwGroup {
     uint32_t xl;                       // x mask in window-local bits
     uint32_t cb[(1 << kHwRegBits) + 1];  // bucket u (register-part z bits = u): classes [cb[u], cb[u + 1])
-    uint32_t pad[2];
+    uint32_t zrm;                      // OR of the register-part z bits of its classes (empty buckets outside it)
+    uint32_t pad;
 };
 
 struct HwClass {
