@@ -82,6 +82,33 @@ def apply_1q(psi, n, q, U):
     return psi
 
 
+def apply_dense(psi, n, qubits, U):
+    """psi <- U psi for a dense 2^k x 2^k matrix on k listed qubits (a fused
+    window of the circuit of eq. 6 as one matrix).  Bit i of U's row and
+    column indices is qubit qubits[i].  Definition, for every basis index b:
+        psi'[b] = sum_p U[pat(b), p] psi[rest(b) | off(p)],
+    pat(b) = the window bits of b in list order, rest(b) = b with the window
+    bits cleared, off(p) = the window bits of pattern p placed at their
+    qubits."""
+    k = len(qubits)
+    idx = np.arange(1 << n, dtype=np.int64)
+    pat = np.zeros_like(idx)
+    rest = idx.copy()
+    for i, q in enumerate(qubits):
+        pat |= ((idx >> q) & 1) << i
+        rest &= ~(1 << q)
+    src = psi.copy()
+    out = np.zeros_like(psi)
+    for p in range(1 << k):
+        off = 0
+        for i, q in enumerate(qubits):
+            if (p >> i) & 1:
+                off |= 1 << q
+        out += U[pat, p] * src[rest | off]
+    psi[:] = out
+    return psi
+
+
 def apply_cnot(psi, n, c, t):
     """Swap the target pairs inside the control = 1 slice."""
     idx = np.arange(1 << n, dtype=np.int64)

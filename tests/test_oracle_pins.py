@@ -410,3 +410,51 @@ def test_excitation_vqe_reaches_sector_ground_state():
         assert f(synth.theta(seed, P)) >= E0 - 1e-12
     best = minimize(f, np.zeros(P) + 0.1, method="BFGS", options={"gtol": 1e-10})
     assert abs(best.fun - E0) < 1e-9
+
+
+def _random_unitary(k, rng):
+    a = rng.normal(size=(1 << k, 1 << k)) + 1j * rng.normal(size=(1 << k, 1 << k))
+    q, r = np.linalg.qr(a)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _random_state(n, rng):
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("q0,k", [(0, 5), (2, 3), (4, 2)])
+def test_dense_window_contiguous_is_kron(q0, k):
+    """On qubits q0 .. q0+k-1 in ascending order the dense window is the full
+    operator I (x) U (x) I (numpy kron, most significant factor first)."""
+    n = 7
+    rng = np.random.default_rng(20 + q0)
+    U = _random_unitary(k, rng)
+    psi = _random_state(n, rng)
+    full = np.kron(np.kron(np.eye(1 << (n - q0 - k)), U), np.eye(1 << q0))
+    got = sv.apply_dense(psi.copy(), n, list(range(q0, q0 + k)), U)
+    assert np.max(np.abs(got - full @ psi)) <= 1e-13
+
+
+def test_dense_window_product_and_permutation():
+    """Any qubit order: a Kronecker product of 2x2 matrices (pattern bit i on
+    qubits[i]) equals one 2x2 per qubit; a permutation matrix of CNOT between
+    pattern bits equals the CNOT on their qubits; a unitary keeps the norm."""
+    n, qubits = 8, [6, 1, 7, 3, 4]
+    rng = np.random.default_rng(7)
+    singles = [_random_unitary(1, rng) for _ in qubits]
+    U = np.array([[1.0 + 0j]])
+    for m in singles:  # bit i of the pattern is factor i counted from the right
+        U = np.kron(m, U)
+    psi = _random_state(n, rng)
+    want = psi.copy()
+    for q, m in zip(qubits, singles):
+        sv.apply_1q(want, n, q, m)
+    assert np.max(np.abs(sv.apply_dense(psi.copy(), n, qubits, U) - want)) <= 1e-13
+    P = np.zeros((32, 32))
+    for p in range(32):
+        P[p ^ (((p >> 3) & 1) << 1), p] = 1.0  # control pattern bit 3, target bit 1
+    want = sv.apply_cnot(psi.copy(), n, qubits[3], qubits[1])
+    assert np.max(np.abs(sv.apply_dense(psi.copy(), n, qubits, P) - want)) == 0.0
+    W = _random_unitary(5, rng)
+    assert abs(np.linalg.norm(sv.apply_dense(psi.copy(), n, qubits, W)) - 1.0) <= 1e-13
