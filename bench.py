@@ -39,7 +39,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "jit.cpp", "api.cpp", "plan.cpp", "vqe_internal.h")
+KERNEL_SOURCES = ("kernels.hip", "dense.hip", "jit.cpp", "api.cpp", "plan.cpp", "vqe_internal.h")
 
 
 def kernel_sources_sha256():
@@ -317,6 +317,62 @@ def copy_calibration(args):
                       "copies": 3, "gbs": 2 * nbytes / dt / 1e9}), flush=True)
 
 
+def dense_bench(args):
+    """Dense window on the matrix cores against the gate-by-gate window pass,
+    at 32 qubits: one 5-qubit window applied as a dense 32 x 32 unitary
+    (vqe_apply_dense: FP32 MFMA on complex64, FP64 MFMA on complex128) and the
+    specialised window pass of vqe_apply_circuit for a 14-gate circuit on the
+    same qubits (RY and RZ on each, a CNOT chain: one pass).  Both are timed
+    with the library's HIP events; both move 2 S per pass."""
+    import numpy as np
+    import torch
+    from paper_2402_11878_amd import _lib as L, ansatz
+
+    n, qubits = 32, [8, 9, 10, 11, 12]
+    gates = [(0, q, -1, 2 * i, 0.0) for i, q in enumerate(qubits)] + \
+            [(1, q, -1, 2 * i + 1, 0.0) for i, q in enumerate(qubits)] + \
+            [(5, a, b, -1, 0.0) for a, b in zip(qubits, qubits[1:])]
+    rng = np.random.default_rng(5)
+    theta = rng.uniform(-np.pi, np.pi, 2 * len(qubits))
+    a = rng.normal(size=(32, 32)) + 1j * rng.normal(size=(32, 32))
+    U, _ = np.linalg.qr(a)
+    out = {"mode": "dense", "n_qubits": n, "qubits": qubits, "reps": args.reps,
+           "note": "per pass; algorithmic bytes 2 S; dense flops 2^(n-5) x 64 x 64 x 2 real"}
+    peaks = {"c64": 157.3, "c128": 78.6}  # dense MFMA TFLOP/s: FP32, FP64
+    for dt, dtype, tdt in (("c64", L.VQE_C64, torch.complex64), ("c128", L.VQE_C128, torch.complex128)):
+        buf = torch.zeros(1 << n, dtype=tdt, device="cuda")
+        st = torch.cuda.current_stream().cuda_stream
+        s = L.vqe_state_alloc(n, dtype, buf.data_ptr(), buf.numel() * buf.element_size(), st)
+        c = L.vqe_circuit_create(n, ansatz.gates_array(gates))
+        try:
+            L.vqe_circuit_prepare(c, dtype)
+            L.vqe_state_set_basis(s, 0)
+            L.vqe_apply_circuit(s, c, theta)
+            L.vqe_apply_dense(s, qubits, U)
+            torch.cuda.synchronize()
+            L.vqe_profile_enable(1)
+            L.vqe_profile_reset()
+            for _ in range(args.reps):
+                L.vqe_apply_circuit(s, c, theta)
+            for _ in range(args.reps):
+                L.vqe_apply_dense(s, qubits, U)
+            torch.cuda.synchronize()
+            nf, msf, bf = L.vqe_profile_read(L.KERNEL_WINDOW_FWD)
+            nd, msd, bd = L.vqe_profile_read(L.KERNEL_DENSE)
+            L.vqe_profile_enable(0)
+            flops = float(1 << (n - 5)) * 64 * 64 * 2
+            out[dt] = {"window_fwd_ms": msf / nf, "window_fwd_gbs": bf / msf / 1e6, "window_passes": nf // args.reps,
+                       "dense_ms": msd / nd, "dense_gbs": bd / msd / 1e6,
+                       "dense_tflops": flops / (msd / nd) / 1e9, "mfma_peak_tflops": peaks[dt]}
+            log(f"[dense] {dt}: window pass {msf / nf:.2f} ms, dense MFMA {msd / nd:.2f} ms")
+        finally:
+            L.vqe_circuit_free(c)
+            L.vqe_state_free(s)
+            del buf
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,9 +386,10 @@ def main():
     ap.add_argument("--skip-c64", action="store_true")
     ap.add_argument("--skip-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "serving", "copy"],
+    ap.add_argument("--mode", default="step", choices=["step", "serving", "copy", "dense"],
                     help="step: the 32-qubit energy+gradient step (default); serving: the served stream; "
-                         "copy: a plain 8 GiB device copy (counter calibration)")
+                         "copy: a plain 8 GiB device copy (counter calibration); dense: a 5-qubit window "
+                         "as a dense unitary on the matrix cores against the gate-by-gate window pass")
     ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--requests", type=int, default=96)
     ap.add_argument("--reps", type=int, default=2)
@@ -357,6 +414,9 @@ def main():
         return
     if args.mode == "copy":
         copy_calibration(args)
+        return
+    if args.mode == "dense":
+        dense_bench(args)
         return
     wl = synth.WORKLOADS[args.workload]
     thetas = wl.thetas()

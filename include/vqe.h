@@ -185,6 +185,24 @@ int vqe_circuit_pass(const vqe_circuit* c, int dtype, size_t pass, int* window, 
 /* psi <- U(params) psi  (eq. 6).  params has n_params doubles (host). */
 int vqe_apply_circuit(vqe_state* s, const vqe_circuit* c, const double* params, size_t n_params);
 
+/* psi <- U psi for a dense 2^k x 2^k complex unitary U on k = VQE_DENSE_K
+ * qubits (one fused window of the ansatz of eq. 6 as a matrix), on the matrix
+ * cores: FP32 MFMA for a complex64 state, FP64 MFMA for complex128.  This is
+ * the dense alternative to the gate-by-gate window passes of
+ * vqe_apply_circuit, kept for comparing the two (it is not used by the other
+ * calls).
+ *   qubits: k distinct qubits, each in [4, n): bit i of a row or column index
+ *           of U is qubit qubits[i]; the four lowest qubits stay outside the
+ *           window so that the 16 cosets a wave takes are contiguous.
+ *   u:      host, 2^k x 2^k complex row-major (row = output pattern) as
+ *           interleaved (re, im) doubles; copied before the call returns.
+ *           Unitarity is not checked.
+ * Enqueued on the state's stream, no synchronisation.  Errors: VQE_ERR_ARG
+ * (null, k != VQE_DENSE_K, a qubit outside [4, n) or repeated),
+ * VQE_ERR_DEVICE. */
+#define VQE_DENSE_K 5
+int vqe_apply_dense(vqe_state* s, const int* qubits, int k, const double* u);
+
 /* ------------------------------------------------------------------ Hamiltonians
  * H = sum_i w_i P(x_i, z_i)  (eqs. 2-4).  Masks must have no bit >= n and the
  * weights must be finite.  Repeated (x, z) pairs are summed.  The terms are
@@ -272,7 +290,8 @@ int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* it
 #define VQE_KERNEL_HPSI        2
 #define VQE_KERNEL_EXPECT_HALF 3   /* grouped energy-only sweep (H psi without the write) */
 #define VQE_KERNEL_PER_TERM    4
-#define VQE_KERNEL_KINDS       5
+#define VQE_KERNEL_DENSE       5   /* vqe_apply_dense (2 S) */
+#define VQE_KERNEL_KINDS       6
 int vqe_profile_enable(int on);
 int vqe_profile_reset(void);
 int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* bytes);

@@ -22,7 +22,9 @@ SLIM_THRESHOLD, SLIM_REMOVE_PERCENT, SLIM_BUDGET = 0, 1, 2
 SPECIALIZE_NEVER, SPECIALIZE_AUTO, SPECIALIZE_ALWAYS = 0, 1, 2
 SPECIALIZE_AUTO_MIN_QUBITS = 20
 MAX_WINDOW = 7
-KERNEL_WINDOW_FWD, KERNEL_WINDOW_REV, KERNEL_HPSI, KERNEL_EXPECT_HALF, KERNEL_PER_TERM = range(5)
+KERNEL_WINDOW_FWD, KERNEL_WINDOW_REV, KERNEL_HPSI, KERNEL_EXPECT_HALF, KERNEL_PER_TERM, KERNEL_DENSE = range(6)
+KERNEL_KINDS = 6
+DENSE_K = 5
 
 
 class VqeError(RuntimeError):
@@ -72,6 +74,7 @@ _SIGS = {
     "vqe_circuit_pass": (C.c_int, [_P, C.c_int, _SZ, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(_SZ), C.POINTER(C.c_int32), _SZ]),
     "vqe_apply_circuit": (C.c_int, [_P, _P, C.POINTER(C.c_double), _SZ]),
+    "vqe_apply_dense": (C.c_int, [_P, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_double)]),
     "vqe_hamiltonian_create": (C.c_int, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                          C.POINTER(C.c_double), _SZ, C.POINTER(_P)]),
     "vqe_hamiltonian_free": (C.c_int, [_P]),
@@ -201,6 +204,17 @@ def vqe_circuit_pass(c, dtype, p):
 def vqe_apply_circuit(s, c, params):
     p, pp = _arr(params, np.float64, C.c_double)
     check("vqe_apply_circuit", lib().vqe_apply_circuit(s, c, pp, len(p)))
+
+
+def vqe_apply_dense(s, qubits, u):
+    """psi <- U psi on `qubits` (bit i of U's indices is qubits[i]); u is a
+    complex (2^k, 2^k) array, k = DENSE_K."""
+    q, qp = _arr(qubits, np.int32, C.c_int)
+    u = np.ascontiguousarray(u, dtype=np.complex128)
+    if u.shape != (1 << len(q), 1 << len(q)):
+        raise ValueError("u must be 2^k x 2^k for k = len(qubits)")
+    uf, up = _arr(u.view(np.float64).reshape(-1), np.float64, C.c_double)
+    check("vqe_apply_dense", lib().vqe_apply_dense(s, qp, len(q), up))
 
 
 def vqe_hamiltonian_create(n_qubits, x, z, w):

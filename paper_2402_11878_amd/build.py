@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libvqe.so")
-SOURCES = ["kernels.hip", "batch.hip", "api.cpp", "plan.cpp", "slim.cpp", "jit.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "dense.hip", "api.cpp", "plan.cpp", "slim.cpp", "jit.cpp"]
 ARCH = "gfx950"
 
 

@@ -686,9 +686,9 @@ int ensure_jit(const vqe_circuit* c, const Plan& cpl, int d) {
 // Fills the matrix table of a specialised plan (every pass, both directions)
 // for these parameters and uploads it on the state's stream.  The pinned
 // staging buffer is reused only after its previous upload has completed.
-template <typename T>
-int upload_mats(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* params, const Mat2<T>** out) {
-    const size_t bytes = std::max<size_t>(pl.mat_total, 1) * sizeof(Mat2<T>);
+// The state's matrix table (device) and its pinned staging copy, at least
+// `bytes` long; waits until the previous upload from the staging copy is done.
+int stage_mats(vqe_state* s, size_t bytes) {
     if (!s->mats_ev) VQE_HIP(hipEventCreateWithFlags(&s->mats_ev, hipEventDisableTiming));
     if (bytes > s->mats_cap) {
         VQE_HIP(hipStreamSynchronize(s->stream));
@@ -704,6 +704,13 @@ int upload_mats(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double
     } else {
         VQE_HIP(hipEventSynchronize(s->mats_ev));
     }
+    return VQE_OK;
+}
+
+template <typename T>
+int upload_mats(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* params, const Mat2<T>** out) {
+    const size_t bytes = std::max<size_t>(pl.mat_total, 1) * sizeof(Mat2<T>);
+    if (int rc = stage_mats(s, bytes)) return rc;
     Mat2<T>* h = (Mat2<T>*)s->h_mats;
     for (size_t pi = 0; pi < pl.passes.size(); ++pi)
         for (int dir = 0; dir < 2; ++dir) {
@@ -717,6 +724,27 @@ int upload_mats(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double
     VQE_HIP(hipMemcpyAsync(s->d_mats, s->h_mats, bytes, hipMemcpyHostToDevice, s->stream));
     VQE_HIP(hipEventRecord(s->mats_ev, s->stream));
     *out = (const Mat2<T>*)s->d_mats;
+    return VQE_OK;
+}
+
+// psi <- U psi on one dense window (see DenseArgs).
+template <typename T>
+int apply_dense(vqe_state* s, const DenseArgs& a, const double* u) {
+    constexpr int P = 1 << kDenseK, RR = 2 * P;
+    if (int rc = stage_mats(s, sizeof(T) * RR * RR)) return rc;
+    T* h = (T*)s->h_mats;
+    for (int r = 0; r < P; ++r)
+        for (int c = 0; c < P; ++c) {
+            const double re = u[2 * (r * P + c)], im = u[2 * (r * P + c) + 1];
+            h[r * RR + c] = (T)re;
+            h[r * RR + P + c] = (T)-im;
+            h[(P + r) * RR + c] = (T)im;
+            h[(P + r) * RR + P + c] = (T)re;
+        }
+    VQE_HIP(hipMemcpyAsync(s->d_mats, s->h_mats, sizeof(T) * RR * RR, hipMemcpyHostToDevice, s->stream));
+    VQE_HIP(hipEventRecord(s->mats_ev, s->stream));
+    ProfScope ps(VQE_KERNEL_DENSE, 2.0 * (double)s->bytes, s->stream);
+    VQE_HIP(launch_dense<T>(a, (const T*)s->d_mats, s->data, s->data, s->stream));
     return VQE_OK;
 }
 
@@ -1561,6 +1589,35 @@ int vqe_apply_circuit(vqe_state* s, const vqe_circuit* c, const double* params, 
     const std::vector<void*> nock;
     const Plan& pl = plan_now(c);
     return s->dtype == VQE_C64 ? forward<float>(s, c, pl, params, nob, nock) : forward<double>(s, c, pl, params, nob, nock);
+    VQE_GUARD_END
+}
+
+int vqe_apply_dense(vqe_state* s, const int* qubits, int k, const double* u) {
+    VQE_GUARD_BEGIN
+    if (int rc = check_state(s, "vqe_apply_dense")) return rc;
+    if (!qubits || !u) {
+        set_error("vqe_apply_dense: null argument");
+        return VQE_ERR_ARG;
+    }
+    if (k != kDenseK) {
+        set_error("vqe_apply_dense: k must be " + std::to_string(kDenseK));
+        return VQE_ERR_ARG;
+    }
+    DenseArgs a{};
+    uint64_t seen = 0;
+    for (int i = 0; i < k; ++i) {
+        if (qubits[i] < 4 || qubits[i] >= s->n || ((seen >> qubits[i]) & 1)) {
+            set_error("vqe_apply_dense: qubits must be distinct and in [4, n)");
+            return VQE_ERR_ARG;
+        }
+        seen |= 1ull << qubits[i];
+        a.q[i] = (uint32_t)qubits[i];
+    }
+    for (int i = 0, q = 0; q < s->n; ++q)
+        if ((seen >> q) & 1) a.sorted[i++] = (uint32_t)q;
+    a.n_tiles = 1ull << (s->n - kDenseK - 4);
+    VQE_HIP(hipSetDevice(s->device));
+    return s->dtype == VQE_C64 ? apply_dense<float>(s, a, u) : apply_dense<double>(s, a, u);
     VQE_GUARD_END
 }
 

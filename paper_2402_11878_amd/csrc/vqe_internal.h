@@ -262,6 +262,22 @@ hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const
                        const HwClass* classes, const HwTerm<T>* terms, bool first, bool last, double* part,
                        uint32_t* nblocks, hipStream_t st);
 
+// ---------------------------------------------------------------- dense window by MFMA
+// psi' = U psi on kDenseK qubits, all >= 4 (16 consecutive cosets are 16
+// consecutive amplitudes), U given to the kernel as the real 2^(k+1) square
+// matrix [[Re U, -Im U], [Im U, Re U]] in row-major order, rows = output
+// pattern (bit i of a pattern is qubit q[i]).  In place allowed.
+constexpr int kDenseK = 5;
+
+struct DenseArgs {
+    uint64_t n_tiles;           // 2^(n - kDenseK) / 16
+    uint32_t q[kDenseK];        // window qubits in pattern-bit order
+    uint32_t sorted[kDenseK];   // the same, ascending
+};
+
+template <typename T>
+hipError_t launch_dense(const DenseArgs& a, const T* ur, const void* in, void* out, hipStream_t st);
+
 // H psi tile kernel.  mode 0: lam = H psi and (Re<psi|lam>, <psi|psi>) partials.
 // mode 1: energy partials only, off-tile groups visited once per pair.
 template <typename T>
