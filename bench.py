@@ -146,9 +146,9 @@ def cpu_baseline(wl_name):
 
     The 28- and 32-qubit states do not fit the oracle's NumPy temporaries on
     the host, so the sample is the same workload shape at 20 qubits: a 2 x 5
-    open Hubbard lattice (t = 1, U = 4, snake order), the same ansatz at 4
-    layers, energy + adjoint gradient by the oracle's gate-by-gate reverse
-    sweep.  Its time is scaled to the workload's step by 2^(n-20) (state
+    open Hubbard lattice (t = 1, U = 4, snake order), the same ansatz with the
+    workload's layer count, energy + adjoint gradient by the oracle's
+    gate-by-gate reverse sweep (about 10 s for 8 layers on one core).  Its time is scaled to the workload's step by 2^(n-20) (state
     size) times the ratio of (3 gates + terms) (gate sweeps of psi forward
     and of psi, lam in reverse, plus one sweep per Hamiltonian term).
     Lattice workloads only.
@@ -159,7 +159,7 @@ def cpu_baseline(wl_name):
     ns = 20
     bonds = synth.snake_bonds(2, 5, False)
     Hs = oham.hubbard(10, bonds, 1.0, 4.0)
-    ls = 4
+    ls = wl.layers
     gates = osv.layered_ansatz(ns, ls)
     th = synth.theta(0, 2 * ns * ls)
     t0 = time.perf_counter()
