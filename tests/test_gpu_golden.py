@@ -5,6 +5,9 @@ molecule_10: 20-qubit molecule-shaped Hamiltonian (14 251 terms), 8-layer
 ansatz; the library's Jordan-Wigner masks and its slimming (Sec. II-D) at
 each cutoff threshold, the energy (eq. 7) and, at thresholds 0 and 1e-3, the
 adjoint gradient, for both state precisions and both kernel forms.
+hubbard2x7_v0: the 28-qubit 2x7 Hubbard step at its full size (16 layers,
+1328 gates, parameter vector 0): the energy through the adjoint evaluation
+(window passes of H psi) and through the grouped expectation (tile form).
 Tolerances as in test_gpu_parity (relative errors over max(|ref|, 1)).
 """
 import json
@@ -77,3 +80,34 @@ def test_molecule_10_energies_and_gradients(molecule_10, dt, form):
     finally:
         s.free(), l.free()
         _lib.vqe_set_specialize(prev)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_hubbard2x7_full_size_energy(dt):
+    path = os.path.join(HERE, "golden", "hubbard2x7_v0.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/hubbard2x7_v0.json not written (make_golden.py hubbard2x7_v0)")
+    ref = _load("hubbard2x7_v0")
+    wl = synth.WORKLOADS["hubbard2x7"]
+    n, dtype = wl.n_qubits, (_lib.VQE_C128 if dt == "c128" else _lib.VQE_C64)
+    assert n == ref["n_qubits"] == 28 and wl.layers == ref["layers"]
+    from paper_2402_11878_amd import ansatz
+    x, z, w = lham.from_lattice(wl.lattice)
+    th = wl.thetas()[ref["vector"]]
+    c = _lib.vqe_circuit_create(n, ansatz.layered(n, wl.layers))
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    s, l = Dev(n, dtype), Dev(n, dtype)
+    try:
+        say(f"case hubbard2x7 vector 0 at 28 qubits {dt}")
+        assert len(_lib.vqe_hamiltonian_plan(h)) >= 1  # lam = H psi by window passes
+        E, _ = _lib.vqe_energy_grad(s.h, l.h, c, th, h)
+        assert rel_err(E, ref["energy"]) <= tol_energy(dtype), (E, ref["energy"])
+        _lib.vqe_state_set_basis(s.h, 0)
+        _lib.vqe_apply_circuit(s.h, c, th)
+        E2, nrm = _lib.vqe_expect_pauli(s.h, h, _lib.EXPECT_GROUPED)
+        assert rel_err(E2, ref["energy"]) <= tol_energy(dtype), (E2, ref["energy"])
+        assert abs(nrm - 1.0) <= (1e-10 if dtype == _lib.VQE_C128 else 1e-5)
+    finally:
+        s.free(), l.free()
+        _lib.vqe_hamiltonian_free(h)
+        _lib.vqe_circuit_free(c)

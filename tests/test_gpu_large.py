@@ -121,3 +121,53 @@ def test_c64_vs_c128_generic_30q(ham30):
     assert np.max(np.abs(g64 - g128)) / max(np.max(np.abs(g128)), 1.0) <= 1e-4
     _lib.vqe_circuit_free(c)
     _lib.vqe_hamiltonian_free(h)
+
+
+def test_bench_configuration_32q_clifford():
+    """The benchmark step at its full size and in its launch configuration:
+    32-qubit 4x4 Hubbard (145 terms, lam = H psi by window passes), 8-layer
+    ansatz (23 specialised passes per sweep), complex128 with one checkpoint
+    and complex64 with four, on Clifford angles (multiples of pi/2, about 2 %
+    of them odd).  The stabiliser tableau gives the exact energy and, from two
+    runs per parameter at +-pi/2 (still Clifford), the exact gradient of all
+    512 parameters."""
+    wl = synth.WORKLOADS["hubbard4x4"]
+    n, L = wl.n_qubits, wl.layers
+    x, z, w = lham.from_lattice(wl.lattice)
+    arr = ansatz.layered(n, L)
+    og = oracle_gates(arr)
+    terms = list(zip(x.tolist(), z.tolist()))
+    P = 2 * n * L
+    rng = np.random.default_rng(5)
+    th = np.where(rng.random(P) < 0.02, rng.choice([math.pi / 2, -math.pi / 2], size=P),
+                  rng.choice([0.0, math.pi], size=P))
+
+    def energy(t):
+        return _energy_from(cf.clifford_expectations(n, og, t, terms), w)
+
+    E_ref = energy(th)
+    g_ref = np.zeros(P)
+    for k in range(P):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += math.pi / 2
+        tm[k] -= math.pi / 2
+        g_ref[k] = 0.5 * (energy(tp) - energy(tm))
+    assert np.count_nonzero(g_ref) >= 3 and E_ref != float(w[(x == 0) & (z == 0)].sum())
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    c = _lib.vqe_circuit_create(n, arr)
+    try:
+        assert len(_lib.vqe_hamiltonian_plan(h)) == 5
+        for dt, n_ck, te, tg in ((_lib.VQE_C128, 1, 1e-10, 1e-9), (_lib.VQE_C64, 4, 1e-5, 1e-4)):
+            say(f"case bench configuration 32q dtype={dt} checkpoints={n_ck}")
+            bufs = [Dev(n, dt) for _ in range(2 + n_ck)]
+            try:
+                E, g = _lib.vqe_energy_grad(bufs[0].h, bufs[1].h, c, th, h, ckpt=[b.h for b in bufs[2:]])
+                assert rel_err(E, E_ref) <= te, (E, E_ref)
+                gs = max(np.max(np.abs(g_ref)), 1.0)
+                assert np.max(np.abs(g - g_ref)) / gs <= tg, np.max(np.abs(g - g_ref))
+            finally:
+                for b in bufs:
+                    b.free()
+    finally:
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
