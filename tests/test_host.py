@@ -455,3 +455,29 @@ def test_hamiltonian_window_plan_small_n():
     h = _lib.vqe_hamiltonian_create(10, np.array([1, 3], np.uint64), np.array([0, 2], np.uint64), np.array([1.0, 0.5]))
     assert _lib.vqe_hamiltonian_plan(h) == []
     _lib.vqe_hamiltonian_free(h)
+
+
+def test_hamiltonian_window_plan_deterministic_and_compact():
+    """The window cover is a deterministic function of the Hamiltonian (its
+    restarts use a fixed seeded stream) and keeps the pass counts reached by
+    the multi-start greedy: 5 for the 32-qubit Hubbard step, 4 at 28 qubits,
+    at most 26 for the 32-qubit molecule-shaped Hamiltonian slimmed at 1e-3."""
+    cases = [("hubbard4x4", None, 5), ("hubbard2x7", None, 4), ("molecule_16", 1e-3, 26)]
+    for name, th, most in cases:
+        wl = synth.WORKLOADS[name]
+        if wl.kind == "molecule":
+            h1, g2 = synth.molecule_integrals(wl.n_orb, wl.integral_seed)
+            x, z, w = lham.molecule(h1, g2)
+            keep, _, _ = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_THRESHOLD, th)
+            x, z, w = x[keep == 1], z[keep == 1], w[keep == 1]
+        else:
+            x, z, w = lham.from_lattice(wl.lattice)
+        plans = []
+        for _ in range(2):
+            h = _lib.vqe_hamiltonian_create(wl.n_qubits, x, z, w)
+            try:
+                plans.append(_lib.vqe_hamiltonian_plan(h))
+            finally:
+                _lib.vqe_hamiltonian_free(h)
+        assert plans[0] == plans[1], name
+        assert 1 <= len(plans[0]) <= most, (name, len(plans[0]))
