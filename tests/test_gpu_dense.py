@@ -28,8 +28,10 @@ def _state(n, rng):
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("n,qubits", [(9, [4, 5, 6, 7, 8]), (12, [11, 4, 9, 6, 7]), (14, [13, 5, 10, 4, 8])])
+@pytest.mark.parametrize("n,qubits", [(9, [4, 5, 6, 7, 8]), (10, [9, 4, 6, 5, 8]), (11, [4, 10, 7, 5, 6]),
+                                      (12, [11, 4, 9, 6, 7]), (14, [13, 5, 10, 4, 8])])
 def test_dense_matches_oracle(n, qubits, dt):
+    """n = 9, 10, 11: one block with 1, 2 or 4 of its 4 waves holding a tile."""
     dtype = DT[dt]
     rng = np.random.default_rng(n)
     U, psi = _unitary(5, rng), _state(n, rng)
