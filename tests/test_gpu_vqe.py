@@ -22,6 +22,15 @@ def _sector_ground(H, n, ne):
     return float(np.linalg.eigvalsh(M[np.ix_(sector, sector)]).min())
 
 
+def _sector_ground_sparse(H, n, ne):
+    """As _sector_ground, from the oracle's sparse operator (12 qubits and up)."""
+    M = ed.sparse(H, n).tocsr()
+    up_mask = sum(1 << q for q in range(0, n, 2))
+    sector = [b for b in range(1 << n)
+              if bin(b & up_mask).count("1") == (ne + 1) // 2 and bin(b & ~up_mask).count("1") == ne // 2]
+    return float(np.linalg.eigvalsh(M[sector][:, sector].toarray()).min())
+
+
 def _problem(n_orb, seed):
     h, g = synth.molecule_integrals(n_orb, seed)
     x, z, w = lham.molecule(h, g)
@@ -95,3 +104,36 @@ def test_cutoff_ratio_on_device():
         assert set(E) == set(range(10, max(int(round(10 * ratio)) - 2, 0), -1)) or ratio == 0.1
     finally:
         _lib.vqe_circuit_free(c)
+
+
+def test_vqe_window_form_12_qubits():
+    """12 qubits (6-site Hubbard chain, 2 electrons, one S/D layer from
+    Hartree-Fock), where lam = H psi runs as one window pass: BFGS with the
+    device gradient; at its final angles the oracle's energy and adjoint
+    gradient agree with the device's, and the energy lies between the sector's
+    lowest eigenvalue and the Hartree-Fock energy."""
+    from gpu_util import Dev
+    n, ne = 12, 2
+    wl = synth.WORKLOADS["hubbard1d_6"]
+    x, z, w = lham.from_lattice(wl.lattice)
+    H = oham.from_masks(n, x, z, w)
+    E0 = _sector_ground_sparse(H, n, ne)
+    arr, P = ansatz.excitations(n, ne)
+    og = oracle_gates(arr)
+    E_hf = expect.energy(osv.run(n, og, np.zeros(P)), n, H)[0]
+    c = _lib.vqe_circuit_create(n, arr)
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    s, l = Dev(n, _lib.VQE_C128), Dev(n, _lib.VQE_C128)
+    say("case vqe n=12 window form")
+    try:
+        assert _lib.vqe_hamiltonian_plan(h) == [(1 << 12) - 1]
+        r = vqe.minimize(n, c, h, np.full(P, 0.05), method="BFGS")
+        assert E0 - 1e-10 <= r["energy"] < E_hf - 1e-3, (E0, r["energy"], E_hf)
+        E_d, g_d = _lib.vqe_energy_grad(s.h, l.h, c, r["theta"], h)
+        E_o, g_o = ogr.adjoint(n, og, r["theta"], H)
+        assert abs(E_d - E_o) <= 1e-10 * max(1.0, abs(E_o))
+        assert np.max(np.abs(g_d - g_o)) <= 1e-9 * max(1.0, np.max(np.abs(g_o)))
+    finally:
+        s.free(), l.free()
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
