@@ -398,8 +398,8 @@ def main():
     ap.add_argument("--slim", type=float, default=1e-3)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (the path is single-device; "
-              f"multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (the library is "
+              f"single-device; sharding over several GPUs is a design, not an implemented path)", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
