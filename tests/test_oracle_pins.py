@@ -458,3 +458,199 @@ def test_dense_window_product_and_permutation():
     assert np.max(np.abs(sv.apply_dense(psi.copy(), n, qubits, P) - want)) == 0.0
     W = _random_unitary(5, rng)
     assert abs(np.linalg.norm(sv.apply_dense(psi.copy(), n, qubits, W)) - 1.0) <= 1e-13
+
+
+# ------------------------------------------------------------------ gates beyond RY / RZ / CNOT
+def _bloch(psi):
+    """(<X>, <Y>, <Z>) of a one-qubit state read off its two amplitudes:
+    2 Re(a* b), 2 Im(a* b), |a|^2 - |b|^2."""
+    a, b = psi[0], psi[1]
+    ab = np.conj(a) * b
+    return (2 * ab.real, 2 * ab.imag, abs(a) ** 2 - abs(b) ** 2)
+
+
+def _rand_state(n, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("t", [0.3, 2.9, -1.7])
+def test_rx_bloch_vector(t):
+    """RX(t)|0> = exp(-i t X/2)|0> rotates the Bloch vector about x: (0, -sin t, cos t)."""
+    psi = sv.run(1, [("RX", 0, -1, 0, 0.0)], [t])
+    assert np.allclose(_bloch(psi), (0.0, -math.sin(t), math.cos(t)), atol=1e-15)
+
+
+def test_rx_is_ry_conjugated_by_rz():
+    """A rotation about x is the rotation about y conjugated by RZ(pi/2):
+    RX(t) = RZ(-pi/2) RY(t) RZ(pi/2) exactly (the RZ phases cancel), on any qubit
+    of a random state; RY and RZ are pinned by their Bloch vectors."""
+    n = 5
+    for q, t in ((0, 0.7), (3, -2.3), (4, 1.9)):
+        psi = _rand_state(n, 40 + q)
+        a = sv.run(n, [("RX", q, -1, 0, 0.0)], [t], psi=psi)
+        b = sv.run(n, [("RZ", q, -1, -1, math.pi / 2), ("RY", q, -1, 0, 0.0),
+                       ("RZ", q, -1, -1, -math.pi / 2)], [t], psi=psi)
+        assert np.max(np.abs(a - b)) < 1e-14
+
+
+def test_x_and_hadamard_closed_forms():
+    """X|0> = |1>, X|1> = |0>; H|0> = (|0>+|1>)/sqrt2 (Bloch (1,0,0)),
+    H|1> = (|0>-|1>)/sqrt2 (Bloch (-1,0,0)); H = X RY(pi/2) exactly
+    (RY(pi/2) = [[1,-1],[1,1]]/sqrt2, then X swaps the rows); H^2 = I and
+    H Z H = X on a random state."""
+    assert np.array_equal(sv.run(1, [("X", 0, -1, -1, 0.0)], [], psi=sv.basis_state(1, 0)), [0, 1])
+    assert np.array_equal(sv.run(1, [("X", 0, -1, -1, 0.0)], [], psi=sv.basis_state(1, 1)), [1, 0])
+    h0 = sv.run(1, [("H", 0, -1, -1, 0.0)], [], psi=sv.basis_state(1, 0))
+    h1 = sv.run(1, [("H", 0, -1, -1, 0.0)], [], psi=sv.basis_state(1, 1))
+    assert np.allclose(_bloch(h0), (1, 0, 0), atol=1e-15)
+    assert np.allclose(_bloch(h1), (-1, 0, 0), atol=1e-15)
+    assert np.allclose(h0, [2 ** -0.5, 2 ** -0.5], atol=1e-16)
+    assert np.allclose(h1, [2 ** -0.5, -(2 ** -0.5)], atol=1e-16)
+    n = 4
+    for q in range(n):
+        psi = _rand_state(n, 50 + q)
+        a = sv.run(n, [("H", q, -1, -1, 0.0)], [], psi=psi)
+        b = sv.run(n, [("RY", q, -1, -1, math.pi / 2), ("X", q, -1, -1, 0.0)], [], psi=psi)
+        assert np.max(np.abs(a - b)) < 1e-15
+        assert np.max(np.abs(sv.run(n, [("H", q, -1, -1, 0.0)], [], psi=a) - psi)) < 1e-15
+        # H Z H = X: <psi|H Z H|psi> = <psi|X_q|psi>, Z and X by their masks
+        zq = expect.expect_term_masks(a, n, 0, 1 << q)
+        xq = expect.expect_term_masks(psi, n, 1 << q, 0)
+        assert abs(zq - xq) < 1e-14
+
+
+def test_cz_truth_table_and_cnot_identity():
+    """CZ multiplies |11> by -1 and leaves |00>, |01>, |10> unchanged; it is
+    symmetric in its qubits and equals H_t CNOT(c -> t) H_t."""
+    for b in range(4):
+        psi = sv.apply_cz(sv.basis_state(2, b), 2, 0, 1)
+        want = sv.basis_state(2, b) * (-1.0 if b == 3 else 1.0)
+        assert np.array_equal(psi, want)
+    n = 5
+    for (c, t) in ((0, 1), (4, 1), (2, 3)):
+        psi = _rand_state(n, 60 + c + t)
+        a = sv.run(n, [("CZ", c, t, -1, 0.0)], [], psi=psi)
+        b = sv.run(n, [("CZ", t, c, -1, 0.0)], [], psi=psi)
+        h = sv.run(n, [("H", t, -1, -1, 0.0), ("CNOT", c, t, -1, 0.0), ("H", t, -1, -1, 0.0)], [], psi=psi)
+        assert np.max(np.abs(a - b)) == 0.0
+        assert np.max(np.abs(a - h)) < 1e-15
+
+
+# ------------------------------------------------------------------ two-body term of eq. (1)
+def test_molecule_two_electron_slater_condon():
+    """Two spatial orbitals, generic h and 8-fold-symmetric chemist integrals
+    g_pqrs = (pq|rs).  The diagonal of H on a determinant is the textbook
+    Slater-Condon energy: sum of h_ii over occupied spin-orbitals plus, per
+    occupied pair, the Coulomb integral J_ij = (ii|jj) minus the exchange
+    integral K_ij = (ij|ji) when the two spins are equal.  So (spin-orbital
+    2p + sigma):
+      |0up 1up>, |0dn 1dn>:  h00 + h11 + J - K
+      |0up 1dn>, |0dn 1up>:  h00 + h11 + J
+      |0up 0dn>:             2 h00 + (00|00);  |1up 1dn>: 2 h11 + (11|11)
+      |0up 0dn 1up>:         2 h00 + h11 + (00|00) + 2 J - K
+    and the triplet energy h00 + h11 + J - K is an eigenvalue three times in
+    the two-electron sector (S_z = 1, 0, -1)."""
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(2, 2))
+    h = a + a.T
+    g = np.zeros((2, 2, 2, 2))
+    for p in range(2):
+        for q in range(2):
+            for r in range(2):
+                for s in range(2):
+                    key = tuple(sorted((tuple(sorted((p, q))), tuple(sorted((r, s))))))
+                    g[p, q, r, s] = {((0, 0), (0, 0)): 0.61, ((0, 0), (0, 1)): 0.13,
+                                     ((0, 0), (1, 1)): 0.47, ((0, 1), (0, 1)): 0.19,
+                                     ((0, 1), (1, 1)): -0.08, ((1, 1), (1, 1)): 0.55}[key]
+    J, K = g[0, 0, 1, 1], g[0, 1, 1, 0]
+    assert abs(J - K) > 0.2                 # exchange and Coulomb distinguishable
+    D = ed.dense(ham.molecule(h, g), 4)
+    bit = lambda *so: sum(1 << s for s in so)
+    want = {
+        bit(0, 2): h[0, 0] + h[1, 1] + J - K, bit(1, 3): h[0, 0] + h[1, 1] + J - K,
+        bit(0, 3): h[0, 0] + h[1, 1] + J, bit(1, 2): h[0, 0] + h[1, 1] + J,
+        bit(0, 1): 2 * h[0, 0] + g[0, 0, 0, 0], bit(2, 3): 2 * h[1, 1] + g[1, 1, 1, 1],
+        bit(0, 1, 2): 2 * h[0, 0] + h[1, 1] + g[0, 0, 0, 0] + 2 * J - K,
+        bit(0): h[0, 0], bit(2): h[1, 1],
+    }
+    for b, e in want.items():
+        assert abs(D[b, b] - e) < 1e-14, (bin(b), D[b, b], e)
+    two = [b for b in range(16) if bin(b).count("1") == 2]
+    ev = np.linalg.eigvalsh(D[np.ix_(two, two)])
+    trip = h[0, 0] + h[1, 1] + J - K
+    assert int(np.sum(np.abs(ev - trip) < 1e-12)) == 3
+
+
+# ------------------------------------------------------------------ terms with an odd number of Y
+def _random_pauli_sum(n, n_terms, seed):
+    """Hermitian Pauli sum over arbitrary strings, odd numbers of Y included
+    (JW images of real integrals never hold those, so the phases i and -i of
+    eq. 3's Y = iXZ are only exercised here)."""
+    rng = np.random.default_rng(seed)
+    H = {}
+    for _ in range(n_terms):
+        s = tuple(rng.choice(list("IXYZ"), size=n))
+        H[s] = H.get(s, 0.0) + float(rng.normal())
+    assert any(s.count("Y") % 2 == 1 for s in H)
+    return H
+
+
+def test_hamiltonian_apply_and_sparse_match_kron_with_odd_y():
+    """H psi of the oracle (signed permutations per term) and the sparse
+    matrix equal the Kronecker-built dense H for strings with odd Y counts."""
+    n = 5
+    H = _random_pauli_sum(n, 30, 8)
+    D = ed.dense(H, n)
+    psi = _rand_state(n, 9)
+    assert np.max(np.abs(expect.apply_hamiltonian(psi, n, H) - D @ psi)) < 1e-13
+    assert np.max(np.abs(ed.sparse(H, n).toarray() - D)) < 1e-14
+    E, _ = expect.energy(psi, n, H)
+    assert abs(E - float(np.vdot(psi, D @ psi).real)) < 1e-13
+
+
+def test_gradients_three_ways_all_gate_kinds():
+    """Adjoint, parameter shift and central differences agree on a random
+    circuit of RX, RY, RZ, H, X, CNOT and CZ gates against a Pauli sum with odd
+    Y counts; the energy equals <psi|D|psi> with the Kronecker-built D."""
+    n = 4
+    rng = np.random.default_rng(12)
+    gates, k = [], 0
+    for _ in range(14):
+        kind = str(rng.choice(["RX", "RY", "RZ", "H", "X", "CNOT", "CZ"]))
+        q0 = int(rng.integers(0, n))
+        if kind in ("CNOT", "CZ"):
+            q1 = int((q0 + 1 + rng.integers(0, n - 1)) % n)
+            gates.append((kind, q0, q1, -1, 0.0))
+        elif kind in ("RX", "RY", "RZ"):
+            gates.append((kind, q0, -1, k, 0.0))
+            k += 1
+        else:
+            gates.append((kind, q0, -1, -1, 0.0))
+    assert any(g[0] == "RX" for g in gates)
+    H = _random_pauli_sum(n, 12, 13)
+    th = rng.uniform(-math.pi, math.pi, size=k)
+    E, g_adj = grad.adjoint(n, gates, th, H)
+    ps = grad.param_shift(n, gates, th, H)
+    fd = grad.finite_diff(n, gates, th, H)
+    g_ps = np.array([ps[i] for i in range(k)])
+    g_fd = np.array([fd[i] for i in range(k)])
+    assert np.max(np.abs(g_adj - g_ps)) < 1e-12
+    assert np.max(np.abs(g_fd - g_ps)) < 1e-7
+    psi = sv.run(n, gates, th)
+    assert abs(E - float(np.vdot(psi, ed.dense(H, n) @ psi).real)) < 1e-13
+
+
+def test_energy_is_a_rayleigh_quotient():
+    """Eq. 7 divides by <psi|psi>: scaling psi by any non-zero c leaves E
+    unchanged and multiplies the reported norm by |c|^2 (both energy routes)."""
+    n = 5
+    H = _random_pauli_sum(n, 20, 14)
+    x, z, w = ham.to_masks(H)
+    psi = _rand_state(n, 15)
+    E1, n1 = expect.energy(psi, n, H)
+    E2, n2 = expect.energy((1.7 - 0.4j) * psi, n, H)
+    E3, _ = expect.energy_masks(0.3j * psi, n, x, z, w)
+    assert abs(n1 - 1.0) < 1e-14 and abs(n2 - abs(1.7 - 0.4j) ** 2) < 1e-13
+    assert abs(E1 - E2) < 1e-13 and abs(E1 - E3) < 1e-13
