@@ -218,9 +218,14 @@ int vqe_hamiltonian_info(const vqe_hamiltonian* h, size_t* n_terms, size_t* n_gr
                          double* identity_weight);
 
 /* energy = <psi|H|psi> / <psi|psi>  (eq. 7); norm (nullable) = <psi|psi>.
- * mode VQE_EXPECT_GROUPED sweeps the state once per X-mask group,
- * VQE_EXPECT_PER_TERM once per term.  Reductions across blocks are FP64 in a
- * fixed order, so repeated calls give identical bits. */
+ * mode VQE_EXPECT_GROUPED serves every Z pattern of an X-mask group from one
+ * read of the partner amplitudes: either m passes over 12-qubit windows (the
+ * window form of vqe_hamiltonian_plan, reading psi once per pass, m S in
+ * all), when that reads less than the tile form, or one sweep over tiles of
+ * 1024 amplitudes that reads each distinct out-of-tile partner tile once per
+ * pair ((1 + D/2) S; D as for vqe_hamiltonian_plan; S = state bytes).
+ * VQE_EXPECT_PER_TERM sweeps the state once per term.  Reductions across
+ * blocks are FP64 in a fixed order, so repeated calls give identical bits. */
 int vqe_expect_pauli(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy, double* norm);
 
 /* lam <- H psi (out of place) and energy = Re<psi|lam>/<psi|psi>. */
@@ -288,7 +293,7 @@ int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* it
 #define VQE_KERNEL_WINDOW_FWD  0
 #define VQE_KERNEL_WINDOW_REV  1
 #define VQE_KERNEL_HPSI        2
-#define VQE_KERNEL_EXPECT_HALF 3   /* grouped energy-only sweep (H psi without the write) */
+#define VQE_KERNEL_EXPECT_HALF 3   /* grouped energy-only sweep: S per window pass, or (1 + D/2) S */
 #define VQE_KERNEL_PER_TERM    4
 #define VQE_KERNEL_DENSE       5   /* vqe_apply_dense (2 S) */
 #define VQE_KERNEL_KINDS       6

@@ -110,11 +110,15 @@ struct vqe_hamiltonian {
     std::vector<TermDesc<float>> t32;
     std::vector<TermDesc<double>> t64;
     double identity = 0.0;
-    // device tables, uploaded on first use on a device
+    // device tables, uploaded on first use on a device (all of them, then d_ready)
+    bool d_ready = false;
     GroupDesc* d_groups = nullptr;
     TermDesc<float>* d_t32 = nullptr;
     TermDesc<double>* d_t64 = nullptr;
-    // window-pass form of lam = H psi (empty when the tile kernel moves fewer bytes)
+    // window-pass form of H psi (empty when the tile kernel moves fewer bytes
+    // for both uses): hw_lam selects it for lam = H psi, hw_energy for the
+    // energy-only sweep
+    bool hw_lam = false, hw_energy = false;
     std::vector<HwDesc> hw_wins;
     std::vector<HwGroup> hw_groups;
     std::vector<HwClass> hw_classes;
@@ -226,41 +230,58 @@ int ensure_res(vqe_state* s, size_t count) {
 int upload_plan(const Plan& cpl);
 bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps& out);
 
+// Device copies of a Hamiltonian's tables; the handle publishes them only
+// when every one was allocated and copied (d_ready), so a failed upload
+// leaves nothing half-built behind.
+void free_hamiltonian_tables(vqe_hamiltonian* h) {
+    void* ptrs[] = {h->d_groups, h->d_t32, h->d_t64, h->d_hw_groups, h->d_hw_classes, h->d_hw_t32, h->d_hw_t64};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    h->d_groups = nullptr;
+    h->d_t32 = nullptr;
+    h->d_t64 = nullptr;
+    h->d_hw_groups = nullptr;
+    h->d_hw_classes = nullptr;
+    h->d_hw_t32 = nullptr;
+    h->d_hw_t64 = nullptr;
+    h->d_ready = false;
+}
+
+template <typename E>
+int upload_table(E** dst, const std::vector<E>& src) {
+    const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(E);
+    if (hipMalloc((void**)dst, bytes) != hipSuccess) {
+        *dst = nullptr;
+        set_error("hipMalloc of a Hamiltonian table failed");
+        return VQE_ERR_OOM;
+    }
+    if (!src.empty() && hipMemcpy(*dst, src.data(), src.size() * sizeof(E), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("hipMemcpy of a Hamiltonian table failed");
+        return VQE_ERR_DEVICE;
+    }
+    return VQE_OK;
+}
+
 // Uploads the grouped term tables to the current device (once).
 int upload_hamiltonian(const vqe_hamiltonian* ch) {
     vqe_hamiltonian* h = const_cast<vqe_hamiltonian*>(ch);
     std::lock_guard<std::mutex> g(g_upload_mu);
-    if (h->d_groups) return VQE_OK;
-    if (hipMalloc((void**)&h->d_groups, h->groups.size() * sizeof(GroupDesc)) != hipSuccess ||
-        hipMalloc((void**)&h->d_t32, h->t32.size() * sizeof(TermDesc<float>)) != hipSuccess ||
-        hipMalloc((void**)&h->d_t64, h->t64.size() * sizeof(TermDesc<double>)) != hipSuccess) {
-        if (h->d_groups) (void)hipFree(h->d_groups);
-        if (h->d_t32) (void)hipFree(h->d_t32);
-        h->d_groups = nullptr;
-        h->d_t32 = nullptr;
-        set_error("hipMalloc of the Hamiltonian tables failed");
-        return VQE_ERR_OOM;
+    if (h->d_ready) return VQE_OK;
+    free_hamiltonian_tables(h);  // leftovers of an earlier failed attempt
+    int rc = upload_table(&h->d_groups, h->groups);
+    if (!rc) rc = upload_table(&h->d_t32, h->t32);
+    if (!rc) rc = upload_table(&h->d_t64, h->t64);
+    if (!rc && !h->hw_wins.empty()) {
+        rc = upload_table(&h->d_hw_groups, h->hw_groups);
+        if (!rc) rc = upload_table(&h->d_hw_classes, h->hw_classes);
+        if (!rc) rc = upload_table(&h->d_hw_t32, h->hw_t32);
+        if (!rc) rc = upload_table(&h->d_hw_t64, h->hw_t64);
     }
-    VQE_HIP(hipMemcpy(h->d_groups, h->groups.data(), h->groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
-    VQE_HIP(hipMemcpy(h->d_t32, h->t32.data(), h->t32.size() * sizeof(TermDesc<float>), hipMemcpyHostToDevice));
-    VQE_HIP(hipMemcpy(h->d_t64, h->t64.data(), h->t64.size() * sizeof(TermDesc<double>), hipMemcpyHostToDevice));
-    if (!h->hw_wins.empty()) {
-        if (hipMalloc((void**)&h->d_hw_groups, h->hw_groups.size() * sizeof(HwGroup)) != hipSuccess ||
-            hipMalloc((void**)&h->d_hw_classes, h->hw_classes.size() * sizeof(HwClass)) != hipSuccess ||
-            hipMalloc((void**)&h->d_hw_t32, h->hw_t32.size() * sizeof(HwTerm<float>)) != hipSuccess ||
-            hipMalloc((void**)&h->d_hw_t64, h->hw_t64.size() * sizeof(HwTerm<double>)) != hipSuccess) {
-            set_error("hipMalloc of the window-pass Hamiltonian tables failed");
-            return VQE_ERR_OOM;
-        }
-        VQE_HIP(hipMemcpy(h->d_hw_groups, h->hw_groups.data(), h->hw_groups.size() * sizeof(HwGroup),
-                          hipMemcpyHostToDevice));
-        VQE_HIP(hipMemcpy(h->d_hw_classes, h->hw_classes.data(), h->hw_classes.size() * sizeof(HwClass),
-                          hipMemcpyHostToDevice));
-        VQE_HIP(hipMemcpy(h->d_hw_t32, h->hw_t32.data(), h->hw_t32.size() * sizeof(HwTerm<float>),
-                          hipMemcpyHostToDevice));
-        VQE_HIP(hipMemcpy(h->d_hw_t64, h->hw_t64.data(), h->hw_t64.size() * sizeof(HwTerm<double>),
-                          hipMemcpyHostToDevice));
+    if (rc) {
+        free_hamiltonian_tables(h);
+        return rc;
     }
+    h->d_ready = true;
     return VQE_OK;
 }
 
@@ -320,10 +341,11 @@ std::vector<uint64_t> cover_windows(int n, const std::vector<uint64_t>& xs, uint
 // Window-pass plan of lam = H psi (see HwDesc): the smallest of several
 // greedy covers (cover_windows with p = 1, 2, 3, each deterministic and
 // with seeded tie perturbations, as many restarts as a fixed work budget
-// allows); each group goes to the first window holding its X mask.  Kept
-// only if its (3 m - 1) S of traffic (m passes; psi read per pass, lam
+// allows); each group goes to the first window holding its X mask.  Used for
+// lam = H psi if its (3 m - 1) S of traffic (m passes; psi read per pass, lam
 // written once and read-modify-written m - 1 times) is below the tile
-// kernel's (D + 2) S.
+// kernel's (D + 2) S, and for the energy-only sweep if its m S (psi read per
+// pass) is below the tile kernel's (1 + D / 2) S; kept if either holds.
 void plan_hwin(vqe_hamiltonian* h) {
     const int n = h->n;
     if (n < kHwBits) return;
@@ -430,7 +452,10 @@ void plan_hwin(vqe_hamiltonian* h) {
         if (g.x >> kTileBits) hi.push_back(g.x >> kTileBits);
     std::sort(hi.begin(), hi.end());
     const size_t D = std::unique(hi.begin(), hi.end()) - hi.begin();
-    if (3 * passes.size() - 1 >= D + 2) return;
+    const size_t m = passes.size();
+    h->hw_lam = 3 * m - 1 < D + 2;
+    h->hw_energy = 2 * m < 2 + D;
+    if (!h->hw_lam && !h->hw_energy) return;
     h->hw_wins.swap(passes);
     h->hw_groups.swap(hgroups);
     h->hw_classes.swap(hclasses);
@@ -805,7 +830,7 @@ template <typename T>
 int apply_h(vqe_state* psi, void* lam, const vqe_hamiltonian* h, double* d_out) {
     hipStream_t st = psi->stream;
     uint32_t nb = 0;
-    if (!h->hw_wins.empty()) {
+    if (h->hw_lam) {
         const size_t m = h->hw_wins.size();
         for (size_t wi = 0; wi < m; ++wi) {
             ProfScope ps(VQE_KERNEL_HPSI, (wi ? 3.0 : 2.0) * (double)psi->bytes, st);
@@ -838,10 +863,24 @@ double hpsi_bytes(const vqe_hamiltonian* h, const vqe_state* s, bool write) {
     return write ? (1.0 + (double)D) * S + S : (1.0 + 0.5 * (double)D) * S;
 }
 
-// Grouped energy partials reduced into d_res[off], d_res[off+1].
+// Grouped energy sums (Re<psi|H|psi>, <psi|psi>) reduced into d_res[off],
+// d_res[off+1]: m energy-only window passes (m S read; per pass, its
+// partials reduced and added in pass order) or one tile sweep that visits
+// each out-of-tile pair once ((1 + D/2) S read).
 template <typename T>
 int energy_grouped(vqe_state* s, const vqe_hamiltonian* h, size_t off) {
     uint32_t nb = 0;
+    if (h->hw_energy) {
+        const size_t m = h->hw_wins.size();
+        for (size_t wi = 0; wi < m; ++wi) {
+            ProfScope ps(VQE_KERNEL_EXPECT_HALF, (double)s->bytes, s->stream);
+            VQE_HIP(launch_hwin<T>(s->n, h->hw_wins[wi], s->data, nullptr, h->d_hw_groups, h->d_hw_classes,
+                                   hw_terms_of<T>(h), wi == 0, wi + 1 == m, s->d_part, &nb, s->stream));
+            ps.end();
+            VQE_HIP(launch_reduce(s->d_part, nb, 2, nullptr, s->d_res + off, wi ? 1 : 0, s->stream));
+        }
+        return VQE_OK;
+    }
     {
         ProfScope ps(VQE_KERNEL_EXPECT_HALF, hpsi_bytes(h, s, false), s->stream);
         VQE_HIP(launch_hpsi<T>(s->n, s->data, nullptr, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 1,
@@ -1694,13 +1733,7 @@ int vqe_hamiltonian_create(int n_qubits, const uint64_t* x, const uint64_t* z, c
 
 int vqe_hamiltonian_free(vqe_hamiltonian* h) {
     if (!h) return VQE_OK;
-    if (h->d_groups) (void)hipFree(h->d_groups);
-    if (h->d_t32) (void)hipFree(h->d_t32);
-    if (h->d_t64) (void)hipFree(h->d_t64);
-    if (h->d_hw_groups) (void)hipFree(h->d_hw_groups);
-    if (h->d_hw_classes) (void)hipFree(h->d_hw_classes);
-    if (h->d_hw_t32) (void)hipFree(h->d_hw_t32);
-    if (h->d_hw_t64) (void)hipFree(h->d_hw_t64);
+    free_hamiltonian_tables(h);
     delete h;
     return VQE_OK;
 }
@@ -1710,16 +1743,17 @@ int vqe_hamiltonian_plan(const vqe_hamiltonian* h, size_t* n_windows, uint64_t* 
         set_error("vqe_hamiltonian_plan: null argument");
         return VQE_ERR_ARG;
     }
-    *n_windows = h->hw_wins.size();
+    const size_t m = h->hw_lam ? h->hw_wins.size() : 0;
+    *n_windows = m;
     if (window_masks) {
-        if (capacity < h->hw_wins.size()) {
+        if (capacity < m) {
             set_error("vqe_hamiltonian_plan: window_masks capacity too small");
             return VQE_ERR_ARG;
         }
-        for (size_t i = 0; i < h->hw_wins.size(); ++i) {
-            uint64_t m = 0;
-            for (int k = 0; k < kHwBits; ++k) m |= 1ull << h->hw_wins[i].pos[k];
-            window_masks[i] = m;
+        for (size_t i = 0; i < m; ++i) {
+            uint64_t wm = 0;
+            for (int k = 0; k < kHwBits; ++k) wm |= 1ull << h->hw_wins[i].pos[k];
+            window_masks[i] = wm;
         }
     }
     return VQE_OK;

@@ -920,7 +920,10 @@ __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint3
     }
 }
 
-template <typename T>
+// EONLY: the energy-only form of the grouped expectation (eq. 7).  No lam is
+// read or written: each pass adds Re sum_b conj(psi_b) (H_w psi)_b over its
+// own groups H_w to per-block partials, the first pass also <psi|psi>.
+template <typename T, bool EONLY>
 __global__ void __launch_bounds__(kHwThreads)
 hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
             const typename VecOf<T>::type* __restrict__ psi, typename VecOf<T>::type* __restrict__ lam,
@@ -974,7 +977,7 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
 #pragma unroll
         for (int r = 0; r < R; ++r) ps[r] = psi[addr(r)];
         T lr[R], li[R];
-        if (first) {
+        if (first || EONLY) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 lr[r] = 0;
@@ -1024,21 +1027,21 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
         T e_t = 0, n_t = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            V o;
-            o.x = lr[r];
-            o.y = li[r];
-            lam[addr(r)] = o;
+            if (!EONLY) {
+                V o;
+                o.x = lr[r];
+                o.y = li[r];
+                lam[addr(r)] = o;
+            }
             const V pv = sp[t + kHwThreads * r];
             e_t += pv.x * lr[r] + pv.y * li[r];
             n_t += pv.x * pv.x + pv.y * pv.y;
         }
-        if (last) {
-            e_acc += (double)e_t;
-            n_acc += (double)n_t;
-        }
+        if (EONLY || last) e_acc += (double)e_t;
+        if (EONLY ? first : last) n_acc += (double)n_t;
         __syncthreads();  // the next coset overwrites both LDS tables
     }
-    if (!last) return;
+    if (!EONLY && !last) return;
     red[t] = e_acc;
     red[kHwThreads + t] = n_acc;
     __syncthreads();
@@ -1337,8 +1340,14 @@ hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const
     WinShape ws{};
     grid_for_units(1ull << (n - kHwBits), true, ws);
     *nblocks = ws.grid;
-    hipLaunchKernelGGL(hwin_kernel<T>, dim3(ws.grid), dim3(kHwThreads), 0, st, w, 1ull << (n - kHwBits), ws.cpt, ws.mlog,
-                       (const V*)psi, (V*)lam, groups, classes, terms, first ? 1 : 0, last ? 1 : 0, part);
+    if (lam)
+        hipLaunchKernelGGL((hwin_kernel<T, false>), dim3(ws.grid), dim3(kHwThreads), 0, st, w, 1ull << (n - kHwBits),
+                           ws.cpt, ws.mlog, (const V*)psi, (V*)lam, groups, classes, terms, first ? 1 : 0,
+                           last ? 1 : 0, part);
+    else
+        hipLaunchKernelGGL((hwin_kernel<T, true>), dim3(ws.grid), dim3(kHwThreads), 0, st, w, 1ull << (n - kHwBits),
+                           ws.cpt, ws.mlog, (const V*)psi, (V*)nullptr, groups, classes, terms, first ? 1 : 0,
+                           last ? 1 : 0, part);
     return hipGetLastError();
 }
 

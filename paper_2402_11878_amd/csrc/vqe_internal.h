@@ -257,6 +257,8 @@ struct HwTerm {
 };
 
 // One window pass; returns the block count (partials of the last pass).
+// lam == nullptr: energy-only pass (no lam traffic); its partials hold this
+// pass's share of Re<psi|H psi> and, for the first pass, <psi|psi>.
 template <typename T>
 hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const HwGroup* groups,
                        const HwClass* classes, const HwTerm<T>* terms, bool first, bool last, double* part,

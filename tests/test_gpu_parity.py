@@ -253,7 +253,8 @@ def test_apply_hamiltonian_window_form(case, dt):
     X groups) against the oracle's term-by-term H psi, element by element;
     "split" takes two passes over one window (more classes than a pass holds);
     at 12 qubits one pass holds one coset (a one-block grid), at 13 qubits two
-    passes hold two cosets each."""
+    passes hold two cosets each.  The grouped energy-only sweep (eq. 7) runs
+    over the same windows without lam and must match the oracle's energy."""
     dtype = DT[dt]
     if case == "split":
         n = 14
@@ -303,6 +304,18 @@ def test_apply_hamiltonian_window_form(case, dt):
         lam = l.read()
         scale = max(np.max(np.abs(lam_ref)), 1.0)
         assert np.max(np.abs(lam - lam_ref)) / scale <= (1e-12 if dtype == _lib.VQE_C128 else 2e-5)
+        # the energy-only sweep takes the same windows (m S read, one launch per pass)
+        _lib.vqe_profile_enable(True)
+        _lib.vqe_profile_reset()
+        try:
+            E2, nrm = _lib.vqe_expect_pauli(s.h, h, _lib.EXPECT_GROUPED)
+            launches, _, nbytes = _lib.vqe_profile_read(_lib.KERNEL_EXPECT_HALF)
+        finally:
+            _lib.vqe_profile_enable(False)
+        assert launches == len(plan) and nbytes == len(plan) * (1 << n) * (16 if dtype == _lib.VQE_C128 else 8)
+        assert rel_err(E2, E_ref) <= tol_energy(dtype), (E2, E_ref)
+        assert abs(nrm - 1.0) <= (1e-12 if dtype == _lib.VQE_C128 else 1e-5)
+        assert (E2, nrm) == _lib.vqe_expect_pauli(s.h, h, _lib.EXPECT_GROUPED)  # bitwise repeatable
     finally:
         s.free(), l.free()
         _lib.vqe_circuit_free(c)
