@@ -141,6 +141,13 @@ WORKLOADS = {
     # 32 qubits: 4x4 Hubbard, open, t=1, U=4; 8 layers; seed 0.
     "hubbard4x4": Workload("hubbard4x4", 32, 8, 0, "hubbard",
                            lattice=_hub(16, snake_bonds(4, 4, False), 1.0, 4.0)),
+    # 24 qubits: 2x6 Hubbard, open, t=1, U=4; 8 layers; seed 2 (generic-angle
+    # gradient parity where reverse passes walk several units per block).
+    "hubbard2x6": Workload("hubbard2x6", 24, 8, 2, "hubbard",
+                           lattice=_hub(12, snake_bonds(2, 6, False), 1.0, 4.0)),
+    # 26 qubits: 1-D Hubbard, 13 sites, open, t=1, U=4; 4 layers; seed 3.
+    "hubbard1d_13": Workload("hubbard1d_13", 26, 4, 3, "hubbard",
+                             lattice=_hub(13, chain_bonds(13), 1.0, 4.0)),
     # 32 qubits: molecule-shaped, 16 orbitals, slimmed at 1e-4 and 1e-3; 8 layers.
     "molecule_16": Workload("molecule_16", 32, 8, 0, "molecule", n_orb=16,
                             integral_seed=0, thresholds=(1e-4, 1e-3)),

@@ -10,8 +10,12 @@ GPU path).
                      at 1e-3 as a cross-check.
   hubbard2x7_v0.json 28-qubit 2x7 Hubbard (periodic long axis, t=1, U=8),
                      16 layers, angle batch seed 1, vector 0: the energy.
+  hubbard2x6_grad.json, hubbard1d_13_grad.json
+                     24-qubit 2x6 Hubbard (8 layers) and 26-qubit 13-site
+                     chain (4 layers) at generic angles: the energy, the full
+                     adjoint gradient and parameter shift on 2 seeded indices.
 
-Usage: python tests/golden/make_golden.py [molecule_10|hubbard2x7_v0]
+Usage: python tests/golden/make_golden.py [molecule_10|hubbard2x7_v0|hubbard2x6_grad|hubbard1d_13_grad]
 """
 import json
 import math
@@ -83,6 +87,34 @@ def hubbard2x7_v0():
     print(f"E={E:.15f} norm={norm:.15f} ({time.time() - t0:.0f} s)", flush=True)
     return {"workload": wl.name, "n_qubits": n, "layers": wl.layers, "theta_seed": wl.theta_seed,
             "vector": 0, "n_terms": len(H), "energy": E, "norm": norm}
+
+
+def _lattice_grad(name):
+    """Energy, full adjoint gradient and parameter shift on 2 seeded indices."""
+    wl = synth.WORKLOADS[name]
+    n = wl.n_qubits
+    lat = wl.lattice
+    t0 = time.time()
+    H = ham.hubbard(lat.n_sites, list(lat.bonds), lat.t, lat.U)
+    gates = sv.layered_ansatz(n, wl.layers)
+    th = wl.thetas()[0]
+    E, gr = grad.adjoint(n, gates, th, H)
+    print(f"{name}: E={E:.15f}, adjoint done ({time.time() - t0:.0f} s)", flush=True)
+    idx = sorted(np.random.default_rng(7).choice(len(th), size=2, replace=False).tolist())
+    ps = grad.param_shift(n, gates, th, H, indices=idx)
+    print(f"{name}: parameter shift on {idx} ({time.time() - t0:.0f} s); max |adj-ps| "
+          f"{max(abs(gr[i] - v) for i, v in ps.items()):.2e}", flush=True)
+    return {"workload": name, "n_qubits": n, "layers": wl.layers, "theta_seed": wl.theta_seed,
+            "n_terms": len(H), "energy": E, "grad": gr.tolist(),
+            "param_shift": {str(i): v for i, v in ps.items()}}
+
+
+def hubbard2x6_grad():
+    return _lattice_grad("hubbard2x6")
+
+
+def hubbard1d_13_grad():
+    return _lattice_grad("hubbard1d_13")
 
 
 if __name__ == "__main__":

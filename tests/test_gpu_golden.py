@@ -111,3 +111,52 @@ def test_hubbard2x7_full_size_energy(dt):
         s.free(), l.free()
         _lib.vqe_hamiltonian_free(h)
         _lib.vqe_circuit_free(c)
+
+
+@pytest.mark.parametrize("name", ["hubbard2x6_grad", "hubbard1d_13_grad"])
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_generic_angle_gradient_golden(name, dt):
+    """24-qubit 2x6 Hubbard (8 layers) and 26-qubit 13-site chain (4 layers)
+    at generic angles, where the reverse passes and the H psi window passes
+    walk several work units per block: the energy and every gradient entry
+    against the oracle's adjoint gradient (and its parameter-shift checks),
+    in the launch configuration of the benchmark step (specialised 7-qubit
+    windows, window-form H psi, one checkpoint in complex128 and four in
+    complex64); the grouped energy-only sweep on the same state too."""
+    path = os.path.join(HERE, "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"tests/golden/{name}.json not written (make_golden.py {name})")
+    ref = _load(name)
+    wl = synth.WORKLOADS[ref["workload"]]
+    n, dtype = wl.n_qubits, (_lib.VQE_C128 if dt == "c128" else _lib.VQE_C64)
+    assert n == ref["n_qubits"] and wl.layers == ref["layers"]
+    from paper_2402_11878_amd import ansatz
+    x, z, w = lham.from_lattice(wl.lattice)
+    th = wl.thetas()[0]
+    c = _lib.vqe_circuit_create(n, ansatz.layered(n, wl.layers))
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    n_ckpt = 1 if dtype == _lib.VQE_C128 else 4
+    states = [Dev(n, dtype) for _ in range(2 + n_ckpt)]
+    prev = _lib.vqe_set_specialize(_lib.SPECIALIZE_AUTO)
+    try:
+        say(f"case {name} generic-angle gradient at {n} qubits {dt}")
+        assert len(_lib.vqe_hamiltonian_plan(h)) >= 1
+        E, grad = _lib.vqe_energy_grad(states[0].h, states[1].h, c, th, h, ckpt=[s.h for s in states[2:]])
+        g_ref = np.array(ref["grad"])
+        scale = max(np.max(np.abs(g_ref)), 1.0)
+        assert rel_err(E, ref["energy"]) <= tol_energy(dtype), (E, ref["energy"])
+        err = np.max(np.abs(grad - g_ref)) / scale
+        say(f"  energy rel err {rel_err(E, ref['energy']):.2e}, gradient max err {err:.2e} over {len(g_ref)}")
+        assert err <= GRAD_TOL[dtype], err
+        for i, v in ref["param_shift"].items():
+            assert abs(grad[int(i)] - v) / scale <= GRAD_TOL[dtype]
+        _lib.vqe_state_set_basis(states[0].h, 0)
+        _lib.vqe_apply_circuit(states[0].h, c, th)
+        E2, nrm = _lib.vqe_expect_pauli(states[0].h, h, _lib.EXPECT_GROUPED)
+        assert rel_err(E2, ref["energy"]) <= tol_energy(dtype), (E2, ref["energy"])
+    finally:
+        _lib.vqe_set_specialize(prev)
+        for s in states:
+            s.free()
+        _lib.vqe_hamiltonian_free(h)
+        _lib.vqe_circuit_free(c)
