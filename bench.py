@@ -245,13 +245,30 @@ def serving_bench(args):
                 time.sleep(min(0.001, max(t_next - time.perf_counter(), 0)))
             d = insts[order[k]]
             futs.append(srv.submit(d["i"], draw(d)))
+        t_last_arrival = time.perf_counter()
         for f in futs:
             f.result()
         t_end = time.perf_counter()
         lat = srv.latencies()
-        loads[str(frac)] = dict(offered=rate, achieved=len(futs) / (t_end - t_start),
+        # completions inside the arrival window measure the sustained rate; the drain after the
+        # last arrival (the largest requests still running) is reported on its own
+        in_window = sum(1 for r in srv.completed if r.done_t <= t_last_arrival)
+        by_n, svc_n = {}, {}
+        for r in srv.completed:
+            by_n.setdefault(r.inst.n, []).append(r.done_t - r.submit_t)
+            svc_n.setdefault(r.inst.n, []).append(r.done_t - r.start_t)
+        loads[str(frac)] = dict(offered=rate, offered_measured=args.requests / (t_last_arrival - t_start),
+                                achieved=len(futs) / (t_end - t_start),
+                                achieved_in_window=in_window / (t_last_arrival - t_start),
+                                drain_s=t_end - t_last_arrival,
                                 p50_ms=percentile(lat, 50) * 1e3, p99_ms=percentile(lat, 99) * 1e3,
-                                batches=len(srv.batches), mean_batch=float(np.mean(srv.batches)) if srv.batches else 0)
+                                by_qubits={str(k): dict(count=len(v), p50_ms=percentile(v, 50) * 1e3,
+                                                        p99_ms=percentile(v, 99) * 1e3,
+                                                        service_p50_ms=percentile(svc_n[k], 50) * 1e3,
+                                                        service_max_ms=max(svc_n[k]) * 1e3)
+                                           for k, v in sorted(by_n.items())},
+                                batches=len(srv.batches), mean_batch=float(np.mean(srv.batches)) if srv.batches else 0,
+                                max_concurrent=srv.max_concurrent, evictions=srv.evictions)
         log(f"[serving] load {frac}: {loads[str(frac)]}")
         srv.close()
     ex.close()
@@ -315,6 +332,72 @@ def copy_calibration(args):
     dt = (time.perf_counter() - t0) / 3
     print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
                       "copies": 3, "gbs": 2 * nbytes / dt / 1e9}), flush=True)
+
+
+def energy_bench(args):
+    """The grouped energy-only sweep (vqe_expect_pauli, eq. 7) on the state
+    of the workload's ansatz at its first parameter vector, for both state
+    precisions: time per energy from the library's HIP events, the bytes it
+    reads in units of S (one S per window pass, or (1 + D/2) S for the tile
+    sweep) and Pauli terms per second; then the per-term form of the paper's
+    evaluation order (one sweep per term, S each) on the same state."""
+    import torch
+    import synth
+    from paper_2402_11878_amd import _lib as L, core
+
+    wl = synth.WORKLOADS[args.workload]
+    n = wl.n_qubits
+    (x, z, w), th_used = workload_hamiltonian(wl, args.threshold)
+    H = core.Hamiltonian(n, x, z, w)
+    circ = core.Circuit.layered(n, wl.layers)
+    theta = wl.thetas()[0]
+    out = {"mode": "energy", "workload": wl.name, "n_qubits": n, "n_terms": H.n_terms, "n_groups": H.n_groups,
+           "threshold": th_used, "reps": args.reps,
+           "window_passes_lam": len(L.vqe_hamiltonian_plan(H.handle))}
+    for dt, dtype, tdt in (("c128", L.VQE_C128, torch.complex128), ("c64", L.VQE_C64, torch.complex64)):
+        if (dt == "c128" and args.skip_c128) or (dt == "c64" and args.skip_c64):
+            continue
+        buf = torch.empty(1 << n, dtype=tdt, device="cuda")
+        st = torch.cuda.current_stream().cuda_stream
+        s = L.vqe_state_alloc(n, dtype, buf.data_ptr(), buf.numel() * buf.element_size(), st)
+        S = buf.numel() * buf.element_size()
+        try:
+            L.vqe_state_set_basis(s, 0)
+            L.vqe_apply_circuit(s, circ.handle, theta)
+            E0, _ = L.vqe_expect_pauli(s, H.handle, L.EXPECT_GROUPED)
+            torch.cuda.synchronize()
+            L.vqe_profile_reset()
+            L.vqe_profile_enable(True)
+            t0 = time.perf_counter()
+            for i in range(args.reps):
+                E, nrm = L.vqe_expect_pauli(s, H.handle, L.EXPECT_GROUPED)
+                log(f"[energy] {dt} rep {i + 1}/{args.reps} E={E:.12f}")
+            t1 = time.perf_counter()
+            cnt, ms, nbytes = L.vqe_profile_read(L.KERNEL_EXPECT_HALF)
+            L.vqe_profile_enable(False)
+            L.vqe_profile_reset()
+            r = {"energy": E, "sec_per_energy": (t1 - t0) / args.reps, "kernel_ms_per_energy": ms / args.reps,
+                 "launches_per_energy": cnt / args.reps, "bytes_per_energy_in_S": nbytes / args.reps / S,
+                 "gbs": nbytes / (ms * 1e-3) / 1e9, "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "pauli_terms_per_s": H.n_terms / ((t1 - t0) / args.reps)}
+            if args.per_term:
+                L.vqe_profile_enable(True)
+                t0 = time.perf_counter()
+                Ep, _ = L.vqe_expect_pauli(s, H.handle, L.EXPECT_PER_TERM)
+                t1 = time.perf_counter()
+                cnt, ms, nbytes = L.vqe_profile_read(L.KERNEL_PER_TERM)
+                L.vqe_profile_enable(False)
+                L.vqe_profile_reset()
+                r["per_term"] = {"energy": Ep, "sec_per_energy": t1 - t0, "sweeps": cnt,
+                                 "gbs": nbytes / (ms * 1e-3) / 1e9, "pauli_terms_per_s": H.n_terms / (t1 - t0)}
+            out[dt] = r
+            log(f"[energy] {dt}: {r['kernel_ms_per_energy']:.1f} ms per energy, {r['bytes_per_energy_in_S']:.2f} S, "
+                f"{r['gbs']:.0f} GB/s")
+        finally:
+            L.vqe_state_free(s)
+            del buf
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
 
 
 def dense_bench(args):
@@ -386,10 +469,15 @@ def main():
     ap.add_argument("--skip-c64", action="store_true")
     ap.add_argument("--skip-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "serving", "copy", "dense"],
+    ap.add_argument("--mode", default="step", choices=["step", "serving", "copy", "dense", "energy"],
                     help="step: the 32-qubit energy+gradient step (default); serving: the served stream; "
                          "copy: a plain 8 GiB device copy (counter calibration); dense: a 5-qubit window "
-                         "as a dense unitary on the matrix cores against the gate-by-gate window pass")
+                         "as a dense unitary on the matrix cores against the gate-by-gate window pass; "
+                         "energy: the grouped energy-only sweep of the workload")
+    ap.add_argument("--per-term", action="store_true", help="energy mode: also time the per-term form once")
+    ap.add_argument("--specialize", default="auto", choices=["never", "auto", "always"],
+                    help="kernel form of the window passes (vqe_set_specialize): interpreted 5-qubit windows "
+                         "(never), specialised 7-qubit windows from 20 qubits on (auto, the default), or always")
     ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--requests", type=int, default=96)
     ap.add_argument("--reps", type=int, default=2)
@@ -409,6 +497,8 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     L.lib()
+    L.vqe_set_specialize({"never": L.SPECIALIZE_NEVER, "auto": L.SPECIALIZE_AUTO,
+                          "always": L.SPECIALIZE_ALWAYS}[args.specialize])
     if args.mode == "serving":
         serving_bench(args)
         return
@@ -417,6 +507,9 @@ def main():
         return
     if args.mode == "dense":
         dense_bench(args)
+        return
+    if args.mode == "energy":
+        energy_bench(args)
         return
     wl = synth.WORKLOADS[args.workload]
     thetas = wl.thetas()

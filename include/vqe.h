@@ -92,6 +92,7 @@ extern "C" {
 #define VQE_SLIM_THRESHOLD       0  /* keep iff |w| >= value */
 #define VQE_SLIM_REMOVE_PERCENT  1  /* remove floor(N * value / 100) smallest terms */
 #define VQE_SLIM_BUDGET          2  /* remove smallest terms while sum |w| <= value */
+#define VQE_SLIM_KEEP_TOP        3  /* keep the value most important non-identity terms */
 
 typedef struct vqe_state vqe_state;
 typedef struct vqe_circuit vqe_circuit;
@@ -358,6 +359,10 @@ int vqe_circuit_prepare(const vqe_circuit* c, int dtype);
  *                    floor(N p / 100) non-identity terms of that order.
  *   BUDGET:          walk that order from its end adding |w| into an FP64
  *                    running sum; drop while the sum stays <= value.
+ *   KEEP_TOP:        value = integer count K >= 0; keep the first K
+ *                    non-identity terms of that order (all if K >= N): the
+ *                    "top N x ratio terms" of the cutoff-ratio search
+ *                    (Algorithm 1), with K = floor(N x ratio).
  * keep[i] (out, n_terms bytes) = 1 to keep term i, else 0; n_kept (nullable)
  * = number kept; dropped_abs_sum (nullable) = sum of the dropped |w|, added in
  * ascending order of importance: a bound on |E_full - E_slim| for any

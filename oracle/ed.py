@@ -65,3 +65,40 @@ def free_fermion_energy(n_sites, bonds, t):
         T[j, i] += -t
     eps = np.linalg.eigvalsh(T)
     return 2.0 * float(eps[eps < 0].sum())
+
+
+def restricted(H, n, basis):
+    """P H P on the span of the basis states `basis` (a list of indices), as a
+    dense matrix M[i, j] = <basis_i|H|basis_j>, built term by term from
+    P|b> = i^y (-1)^{z.b} |b^x>.  Its lowest eigenvalue bounds <psi|H|psi>
+    from below for every normalised psi inside that span (e.g. a particle-number
+    and spin sector), whether or not H itself conserves the span."""
+    basis = np.asarray(basis, dtype=np.int64)
+    order = np.argsort(basis)
+    srt = basis[order]
+    M = np.zeros((len(basis), len(basis)), dtype=np.complex128)
+    bu = basis.astype(np.uint64)
+    cols = np.arange(len(basis))
+    for s, w in H.items():
+        x = z = 0
+        for j, c in enumerate(s):
+            if c in "XY":
+                x |= 1 << j
+            if c in "ZY":
+                z |= 1 << j
+        y = bin(x & z).count("1") % 4
+        sign = 1.0 - 2.0 * (np.bitwise_count(bu & np.uint64(z)) & 1)
+        tgt = (bu ^ np.uint64(x)).astype(np.int64)
+        val = w * (1, 1j, -1, -1j)[y] * sign
+        k = np.minimum(np.searchsorted(srt, tgt), len(srt) - 1)
+        inside = srt[k] == tgt                      # b^x is a basis state of the span
+        np.add.at(M, (order[k[inside]], cols[inside]), val[inside])
+    return M
+
+
+def sector_basis(n, n_up, n_dn):
+    """Basis indices with n_up electrons on the even (up) spin-orbitals and
+    n_dn on the odd (down) ones (spin-orbital 2 i + sigma)."""
+    up = sum(1 << q for q in range(0, n, 2))
+    return [b for b in range(1 << n) if bin(b & up).count("1") == n_up and bin(b & ~up).count("1") == n_dn]
+

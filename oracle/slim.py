@@ -12,6 +12,8 @@ Readings used here:
   * budget mode: walk that order from its end, adding |w| into an FP64 running
     sum left to right; drop while the sum stays <= budget and stop at the first
     term that would exceed it.
+  * keep-top mode (Algorithm 1's "top N x ratio terms"): keep the first K
+    non-identity terms of that order, K = floor(N x ratio) given as a count.
 In every mode the identity term (x = z = 0) is kept: it costs no sweep and is
 a constant shift.  Each mode returns (keep mask, dropped sum of |w|), the
 dropped sum being accumulated in the order the terms are dropped.
@@ -51,6 +53,16 @@ def remove_percent(x, z, w, pct):
     keep = np.ones(len(w), dtype=np.uint8)
     dropped = 0.0
     for i in reversed(order[len(order) - n_drop:]):
+        keep[i] = 0
+        dropped += abs(float(w[i]))
+    return keep, dropped
+
+
+def keep_top(x, z, w, count):
+    order = _order(x, z, w)
+    keep = np.ones(len(w), dtype=np.uint8)
+    dropped = 0.0
+    for i in reversed(order[int(count):]):
         keep[i] = 0
         dropped += abs(float(w[i]))
     return keep, dropped

@@ -18,7 +18,7 @@ VQE_C64, VQE_C128 = 1, 2
 GATE_RY, GATE_RZ, GATE_RX, GATE_H, GATE_X, GATE_CNOT, GATE_CZ, GATE_SEXC, GATE_DEXC = range(9)
 EXPECT_GROUPED, EXPECT_PER_TERM = 0, 1
 GRAD_ADJOINT, GRAD_PARAM_SHIFT = 0, 1
-SLIM_THRESHOLD, SLIM_REMOVE_PERCENT, SLIM_BUDGET = 0, 1, 2
+SLIM_THRESHOLD, SLIM_REMOVE_PERCENT, SLIM_BUDGET, SLIM_KEEP_TOP = 0, 1, 2, 3
 SPECIALIZE_NEVER, SPECIALIZE_AUTO, SPECIALIZE_ALWAYS = 0, 1, 2
 SPECIALIZE_AUTO_MIN_QUBITS = 20
 MAX_WINDOW = 7

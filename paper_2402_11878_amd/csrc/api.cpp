@@ -110,6 +110,9 @@ struct vqe_hamiltonian {
     std::vector<TermDesc<float>> t32;
     std::vector<TermDesc<double>> t64;
     double identity = 0.0;
+    // every folded coefficient real (each term has an even number of Y, as for
+    // any real symmetric H): the window passes of H psi skip imaginary parts
+    bool real_coeffs = true;
     // device tables, uploaded on first use on a device (all of them, then d_ready)
     bool d_ready = false;
     GroupDesc* d_groups = nullptr;
@@ -169,6 +172,8 @@ struct ProfScope {
     ProfScope(int kind, double bytes, hipStream_t s) : on(false), st(s) {
         std::lock_guard<std::mutex> g(g_prof_mu);
         if (!g_prof_on) return;
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
         if (hipEventCreate(&r.a) != hipSuccess) return;
         if (hipEventCreate(&r.b) != hipSuccess) {
             (void)hipEventDestroy(r.a);
@@ -835,13 +840,13 @@ int apply_h(vqe_state* psi, void* lam, const vqe_hamiltonian* h, double* d_out) 
         for (size_t wi = 0; wi < m; ++wi) {
             ProfScope ps(VQE_KERNEL_HPSI, (wi ? 3.0 : 2.0) * (double)psi->bytes, st);
             VQE_HIP(launch_hwin<T>(psi->n, h->hw_wins[wi], psi->data, lam, h->d_hw_groups, h->d_hw_classes,
-                                   hw_terms_of<T>(h),
+                                   hw_terms_of<T>(h), h->real_coeffs,
                                    wi == 0, wi + 1 == m, psi->d_part, &nb, st));
         }
     } else {
         ProfScope ps(VQE_KERNEL_HPSI, hpsi_bytes(h, psi, true), st);
         VQE_HIP(launch_hpsi<T>(psi->n, psi->data, lam, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 0,
-                               psi->d_part, &nb, st));
+                               (uint32_t)kMaxPartBlocks, psi->d_part, &nb, st));
     }
     VQE_HIP(launch_reduce(psi->d_part, nb, 2, nullptr, d_out, 0, st));
     return VQE_OK;
@@ -863,30 +868,31 @@ double hpsi_bytes(const vqe_hamiltonian* h, const vqe_state* s, bool write) {
     return write ? (1.0 + (double)D) * S + S : (1.0 + 0.5 * (double)D) * S;
 }
 
-// Grouped energy sums (Re<psi|H|psi>, <psi|psi>) reduced into d_res[off],
-// d_res[off+1]: m energy-only window passes (m S read; per pass, its
-// partials reduced and added in pass order) or one tile sweep that visits
-// each out-of-tile pair once ((1 + D/2) S read).
+// Grouped energy sums (Re<psi|H|psi>, <psi|psi>) reduced into sums[0..1]
+// on the device, with per-block partials in part (at most
+// kEnergyPartBlocks blocks of 2): m energy-only window passes (m S read;
+// per pass, its partials reduced and added in pass order) or one tile sweep
+// that visits each out-of-tile pair once ((1 + D/2) S read).
 template <typename T>
-int energy_grouped(vqe_state* s, const vqe_hamiltonian* h, size_t off) {
+int energy_grouped(vqe_state* s, const vqe_hamiltonian* h, double* part, double* sums) {
     uint32_t nb = 0;
     if (h->hw_energy) {
         const size_t m = h->hw_wins.size();
         for (size_t wi = 0; wi < m; ++wi) {
             ProfScope ps(VQE_KERNEL_EXPECT_HALF, (double)s->bytes, s->stream);
             VQE_HIP(launch_hwin<T>(s->n, h->hw_wins[wi], s->data, nullptr, h->d_hw_groups, h->d_hw_classes,
-                                   hw_terms_of<T>(h), wi == 0, wi + 1 == m, s->d_part, &nb, s->stream));
+                                   hw_terms_of<T>(h), h->real_coeffs, wi == 0, wi + 1 == m, part, &nb, s->stream));
             ps.end();
-            VQE_HIP(launch_reduce(s->d_part, nb, 2, nullptr, s->d_res + off, wi ? 1 : 0, s->stream));
+            VQE_HIP(launch_reduce(part, nb, 2, nullptr, sums, wi ? 1 : 0, s->stream));
         }
         return VQE_OK;
     }
     {
         ProfScope ps(VQE_KERNEL_EXPECT_HALF, hpsi_bytes(h, s, false), s->stream);
         VQE_HIP(launch_hpsi<T>(s->n, s->data, nullptr, h->d_groups, (uint32_t)h->groups.size(), terms_of<T>(h), 1,
-                               s->d_part, &nb, s->stream));
+                               kEnergyPartBlocks, part, &nb, s->stream));
     }
-    VQE_HIP(launch_reduce(s->d_part, nb, 2, nullptr, s->d_res + off, 0, s->stream));
+    VQE_HIP(launch_reduce(part, nb, 2, nullptr, sums, 0, s->stream));
     return VQE_OK;
 }
 
@@ -929,7 +935,7 @@ int expect_impl(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy
         *energy = e / nrm;
         if (norm) *norm = nrm;
     } else {
-        rc = energy_grouped<T>(s, h, 0);
+        rc = energy_grouped<T>(s, h, s->d_part, s->d_res);
         if (rc) return rc;
         VQE_HIP(hipMemcpyAsync(s->h_res, s->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
         VQE_HIP(hipStreamSynchronize(s->stream));
@@ -1032,7 +1038,8 @@ int param_shift_impl(vqe_state* psi, const vqe_circuit* c, const double* params,
         VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, psi->stream));
         rc = forward<T>(psi, c, plan_now(c), th.data(), nob, nock);
         if (rc) return rc;
-        rc = mode == VQE_EXPECT_PER_TERM ? energy_per_term<T>(psi, h, e * per) : energy_grouped<T>(psi, h, e * per);
+        rc = mode == VQE_EXPECT_PER_TERM ? energy_per_term<T>(psi, h, e * per)
+                                         : energy_grouped<T>(psi, h, psi->d_part, psi->d_res + e * per);
         if (rc) return rc;
     }
     VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, per * n_eval * sizeof(double), hipMemcpyDeviceToHost, psi->stream));
@@ -1724,6 +1731,7 @@ int vqe_hamiltonian_create(int n_qubits, const uint64_t* x, const uint64_t* z, c
         const double cim = (y == 1) ? -wv : (y == 3 ? wv : 0.0);
         t64[t] = TermDesc<double>{h->z[t], cre, cim};
         t32[t] = TermDesc<float>{h->z[t], (float)cre, (float)cim};
+        if (y & 1) h->real_coeffs = false;
     }
     plan_hwin(h);
     *out = h;
@@ -1979,3 +1987,4 @@ int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* byt
 }
 
 }  // extern "C"
+

@@ -849,7 +849,10 @@ __device__ __forceinline__ void parity_sign(uint32_t cnt, float& s) { s = __uint
 // j - cbase), D_r = sum_{u in M} (-1)^{popcount(u & r)} E_u (a transform over
 // the register bits in M only: buckets outside M are empty, so D_r = D_{r & M}),
 // then lam_r += D_r psi[(t + kHwThreads r) ^ xl].
-template <typename T, int M>
+// REAL: every folded coefficient is real (a real symmetric H: each term holds
+// an even number of Y, so w (-i)^popcount(x&z) = +-w); D is then real and the
+// imaginary halves of the class sums, the transform and the update vanish.
+template <typename T, int M, bool REAL>
 __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint32_t t,
                                          const typename VecOf<T>::type* A, const uint32_t* zt,
                                          const typename VecOf<T>::type* sp, T* lr, T* li) {
@@ -879,7 +882,7 @@ __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint3
                 T sg;
                 parity_sign((uint32_t)__popc(z[q] & t), sg);
                 sr = fma(sg, a[q].x, sr);
-                si = fma(sg, a[q].y, si);
+                if (!REAL) si = fma(sg, a[q].y, si);
             }
         }
         for (; j < e; ++j, ++jv) {
@@ -887,7 +890,7 @@ __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint3
             parity_sign((uint32_t)__popc(zt[jv] & t), sg);
             const V a = A[jv];
             sr = fma(sg, a.x, sr);
-            si = fma(sg, a.y, si);
+            if (!REAL) si = fma(sg, a.y, si);
         }
         er[u] = sr;
         ei[u] = si;
@@ -898,11 +901,14 @@ __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint3
 #pragma unroll
         for (int i = 0; i < R; ++i)
             if (!(i & ~M) && !(i & bit)) {
-                const T r0 = er[i], r1 = er[i | bit], i0 = ei[i], i1 = ei[i | bit];
+                const T r0 = er[i], r1 = er[i | bit];
                 er[i] = r0 + r1;
                 er[i | bit] = r0 - r1;
-                ei[i] = i0 + i1;
-                ei[i | bit] = i0 - i1;
+                if (!REAL) {
+                    const T i0 = ei[i], i1 = ei[i | bit];
+                    ei[i] = i0 + i1;
+                    ei[i | bit] = i0 - i1;
+                }
             }
     }
     // partner of pattern t + kHwThreads r: byte offset a0 + (r ^ xr) kHwThreads sizeof(V)
@@ -912,18 +918,21 @@ __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint3
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const V pv = *reinterpret_cast<const V*>(spb + a0 + (r ^ xr) * (uint32_t)(kHwThreads * sizeof(V)));
-        const T dr = er[r & M], di = ei[r & M];
+        const T dr = er[r & M];
         lr[r] = fma(dr, pv.x, lr[r]);
-        lr[r] = fma(-di, pv.y, lr[r]);
         li[r] = fma(dr, pv.y, li[r]);
-        li[r] = fma(di, pv.x, li[r]);
+        if (!REAL) {
+            const T di = ei[r & M];
+            lr[r] = fma(-di, pv.y, lr[r]);
+            li[r] = fma(di, pv.x, li[r]);
+        }
     }
 }
 
 // EONLY: the energy-only form of the grouped expectation (eq. 7).  No lam is
 // read or written: each pass adds Re sum_b conj(psi_b) (H_w psi)_b over its
 // own groups H_w to per-block partials, the first pass also <psi|psi>.
-template <typename T, bool EONLY>
+template <typename T, bool EONLY, bool REAL>
 __global__ void __launch_bounds__(kHwThreads)
 hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
             const typename VecOf<T>::type* __restrict__ psi, typename VecOf<T>::type* __restrict__ lam,
@@ -999,7 +1008,7 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
                 T sg;
                 parity_sign((uint32_t)__popcll(tm.zo & base), sg);
                 ar = fma(sg, tm.cre, ar);
-                ai = fma(sg, tm.cim, ai);
+                if (!REAL) ai = fma(sg, tm.cim, ai);
             }
             V a;
             a.x = ar;
@@ -1014,14 +1023,14 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
             const HwGroup& G = groups[g];
             static_assert(kHwRegBits == 3, "one case per register-bit subset");
             switch (G.zrm) {
-                case 0: hw_group<T, 0>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 1: hw_group<T, 1>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 2: hw_group<T, 2>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 3: hw_group<T, 3>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 4: hw_group<T, 4>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 5: hw_group<T, 5>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 6: hw_group<T, 6>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                default: hw_group<T, 7>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 0: hw_group<T, 0, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 1: hw_group<T, 1, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 2: hw_group<T, 2, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 3: hw_group<T, 3, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 4: hw_group<T, 4, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 5: hw_group<T, 5, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 6: hw_group<T, 6, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                default: hw_group<T, 7, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
             }
         }
         T e_t = 0, n_t = 0;
@@ -1332,33 +1341,37 @@ hipError_t launch_window_jit(void* fn, const JitArgs& a, int S, const void* mats
 
 template <typename T>
 hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const HwGroup* groups,
-                       const HwClass* classes, const HwTerm<T>* terms, bool first, bool last, double* part,
-                       uint32_t* nblocks, hipStream_t st) {
+                       const HwClass* classes, const HwTerm<T>* terms, bool real, bool first, bool last,
+                       double* part, uint32_t* nblocks, hipStream_t st) {
     using V = typename VecOf<T>::type;
     if (n < kHwBits || w.c_end < w.c_begin || w.c_end - w.c_begin > (uint32_t)kHwMaxClasses)
         return hipErrorInvalidValue;
     WinShape ws{};
     grid_for_units(1ull << (n - kHwBits), true, ws);
     *nblocks = ws.grid;
-    if (lam)
-        hipLaunchKernelGGL((hwin_kernel<T, false>), dim3(ws.grid), dim3(kHwThreads), 0, st, w, 1ull << (n - kHwBits),
-                           ws.cpt, ws.mlog, (const V*)psi, (V*)lam, groups, classes, terms, first ? 1 : 0,
-                           last ? 1 : 0, part);
-    else
-        hipLaunchKernelGGL((hwin_kernel<T, true>), dim3(ws.grid), dim3(kHwThreads), 0, st, w, 1ull << (n - kHwBits),
-                           ws.cpt, ws.mlog, (const V*)psi, (V*)nullptr, groups, classes, terms, first ? 1 : 0,
-                           last ? 1 : 0, part);
+#define VQE_HWIN(EO, RE)                                                                                      \
+    hipLaunchKernelGGL((hwin_kernel<T, EO, RE>), dim3(ws.grid), dim3(kHwThreads), 0, st, w, 1ull << (n - kHwBits), \
+                       ws.cpt, ws.mlog, (const V*)psi, (V*)lam, groups, classes, terms, first ? 1 : 0, last ? 1 : 0, \
+                       part)
+    if (lam) {
+        if (real) VQE_HWIN(false, true); else VQE_HWIN(false, false);
+    } else {
+        if (real) VQE_HWIN(true, true); else VQE_HWIN(true, false);
+    }
+#undef VQE_HWIN
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* groups, uint32_t n_groups,
-                       const TermDesc<T>* terms, int mode, double* part, uint32_t* nblocks, hipStream_t st) {
+                       const TermDesc<T>* terms, int mode, uint32_t max_blocks, double* part, uint32_t* nblocks,
+                       hipStream_t st) {
     using V = typename VecOf<T>::type;
     const int tb = n < kTileBits ? n : kTileBits;
     const uint64_t n_tiles = 1ull << (n - tb);
+    if (max_blocks < 1) return hipErrorInvalidValue;
     uint32_t tpb = 1;
-    while ((n_tiles + tpb - 1) / tpb > (uint64_t)kMaxPartBlocks) tpb *= 2;
+    while ((n_tiles + tpb - 1) / tpb > (uint64_t)max_blocks) tpb *= 2;
     const uint32_t g = (uint32_t)((n_tiles + tpb - 1) / tpb);
     *nblocks = g;
     const int tile = 1 << tb;
@@ -1407,11 +1420,11 @@ template hipError_t launch_window_fwd<double>(const PassArgs<double>&, int, cons
 template hipError_t launch_window_rev<float>(const PassArgs<float>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
 template hipError_t launch_window_rev<double>(const PassArgs<double>&, int, const void*, void*, const void*, void*, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hwin<float>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwClass*,
-                                       const HwTerm<float>*, bool, bool, double*, uint32_t*, hipStream_t);
+                                       const HwTerm<float>*, bool, bool, bool, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hwin<double>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwClass*,
-                                        const HwTerm<double>*, bool, bool, double*, uint32_t*, hipStream_t);
-template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, double*, uint32_t*, hipStream_t);
-template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, double*, uint32_t*, hipStream_t);
+                                        const HwTerm<double>*, bool, bool, bool, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, uint32_t, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, uint32_t, double*, uint32_t*, hipStream_t);
 template hipError_t launch_expect_term<float>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);
 template hipError_t launch_expect_term<double>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);
 

@@ -26,7 +26,12 @@ extern "C" int vqe_slim_hamiltonian(const uint64_t* x, const uint64_t* z, const 
         set_error("vqe_slim_hamiltonian: percentage must be an integer in [0, 100]");
         return VQE_ERR_ARG;
     }
-    if (mode != VQE_SLIM_THRESHOLD && mode != VQE_SLIM_REMOVE_PERCENT && mode != VQE_SLIM_BUDGET) {
+    if (mode == VQE_SLIM_KEEP_TOP && (value != std::floor(value) || value > 1e18)) {
+        set_error("vqe_slim_hamiltonian: the kept count must be a non-negative integer");
+        return VQE_ERR_ARG;
+    }
+    if (mode != VQE_SLIM_THRESHOLD && mode != VQE_SLIM_REMOVE_PERCENT && mode != VQE_SLIM_BUDGET &&
+        mode != VQE_SLIM_KEEP_TOP) {
         set_error("vqe_slim_hamiltonian: unknown mode");
         return VQE_ERR_ARG;
     }
@@ -56,8 +61,10 @@ extern "C" int vqe_slim_hamiltonian(const uint64_t* x, const uint64_t* z, const 
                 dropped += std::fabs(w[*it]);
             }
         }
-    } else if (mode == VQE_SLIM_REMOVE_PERCENT) {
-        size_t n_drop = (order.size() * (size_t)value) / 100;
+    } else if (mode == VQE_SLIM_REMOVE_PERCENT || mode == VQE_SLIM_KEEP_TOP) {
+        const size_t n_keep = (size_t)value;
+        const size_t n_drop = mode == VQE_SLIM_REMOVE_PERCENT ? (order.size() * (size_t)value) / 100
+                              : (n_keep < order.size() ? order.size() - n_keep : 0);
         for (size_t j = 0; j < n_drop; ++j) {
             size_t i = order[order.size() - 1 - j];
             k[i] = 0;

@@ -259,10 +259,12 @@ struct HwTerm {
 // One window pass; returns the block count (partials of the last pass).
 // lam == nullptr: energy-only pass (no lam traffic); its partials hold this
 // pass's share of Re<psi|H psi> and, for the first pass, <psi|psi>.
+// real: every folded coefficient has a zero imaginary part (the real form
+// of the pass, half the arithmetic).
 template <typename T>
 hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const HwGroup* groups,
-                       const HwClass* classes, const HwTerm<T>* terms, bool first, bool last, double* part,
-                       uint32_t* nblocks, hipStream_t st);
+                       const HwClass* classes, const HwTerm<T>* terms, bool real, bool first, bool last,
+                       double* part, uint32_t* nblocks, hipStream_t st);
 
 // ---------------------------------------------------------------- dense window by MFMA
 // psi' = U psi on kDenseK qubits, all >= 4 (16 consecutive cosets are 16
@@ -281,11 +283,16 @@ template <typename T>
 hipError_t launch_dense(const DenseArgs& a, const T* ur, const void* in, void* out, hipStream_t st);
 
 // H psi tile kernel.  mode 0: lam = H psi and (Re<psi|lam>, <psi|psi>) partials.
-// mode 1: energy partials only, off-tile groups visited once per pair.
+// mode 1: energy partials only, off-tile groups visited once per pair.  At
+// most max_blocks blocks (each owns a contiguous run of tiles), each writing
+// two partials.
 template <typename T>
 hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* groups, uint32_t n_groups,
-                       const TermDesc<T>* terms, int mode, double* part, uint32_t* nblocks,
+                       const TermDesc<T>* terms, int mode, uint32_t max_blocks, double* part, uint32_t* nblocks,
                        hipStream_t st);
+// Grouped energy-only sweeps launch at most this many blocks.
+constexpr uint32_t kEnergyPartBlocks = 4096;
+
 
 // One term: partials of Re<psi|P(x,z)|psi> (pair-halved) and <psi|psi>.
 template <typename T>

@@ -55,6 +55,7 @@ class Request:
     theta: np.ndarray
     submit_t: float
     future: Future = field(default_factory=Future)
+    start_t: float = 0.0   # when a worker or a batch launch took it
     done_t: float = 0.0
 
 
@@ -85,6 +86,7 @@ class Server:
         self._closing = False
         self.completed = []
         self.batches = []          # sizes of the launched batches
+        self.evictions = 0         # resident instances released to admit others
         self.max_concurrent = 0
         self._running = 0
         self._threads = [threading.Thread(target=self._batch_loop, daemon=True)]
@@ -106,14 +108,20 @@ class Server:
         return inst
 
     def submit(self, iid, theta):
-        inst = self.instances[iid]
-        req = Request(inst, np.asarray(theta, dtype=np.float64), self.clock())
+        return self.submit_many([(iid, theta)])[0]
+
+    def submit_many(self, items):
+        """Queues a burst of requests [(iid, theta), ...] at once (one lock
+        hold, so the loops see all of them together); returns their futures."""
+        reqs = [Request(self.instances[iid], np.asarray(theta, dtype=np.float64), self.clock())
+                for iid, theta in items]
         with self._cv:
             if self._closing:
                 raise RuntimeError("server is closed")
-            (self._small if self.ex.is_small(inst) else self._large).append(req)
+            for req in reqs:
+                (self._small if self.ex.is_small(req.inst) else self._large).append(req)
             self._cv.notify_all()
-        return req.future
+        return [r.future for r in reqs]
 
     def close(self):
         with self._cv:
@@ -147,6 +155,9 @@ class Server:
                 if not self._small and self._closing:
                     return
                 batch = [self._small.popleft() for _ in range(min(self.max_batch, len(self._small)))]
+                t_start = self.clock()
+                for r in batch:
+                    r.start_t = t_start
                 self._running += 1
                 self.max_concurrent = max(self.max_concurrent, self._running)
             self.batches.append(len(batch))
@@ -176,6 +187,7 @@ class Server:
                 self.ex.release(victim)
                 victim.resident = False
                 self.used -= victim.footprint
+                self.evictions += 1
         if self.used + need > self.budget:
             return False
         self.ex.make_resident(inst)
@@ -208,6 +220,7 @@ class Server:
                         break
                     self._cv.wait(timeout=0.05)
                 req.inst.busy = True
+                req.start_t = self.clock()
                 self._running += 1
                 self.max_concurrent = max(self.max_concurrent, self._running)
             try:

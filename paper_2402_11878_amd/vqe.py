@@ -8,11 +8,11 @@ Sec. II-B); here the gradient comes from one adjoint sweep instead of one
 circuit run per parameter.
 
 Algorithm 1 as printed is garbled (no decrement of the ratio, mismatched
-names); it is read as: with the terms ordered by importance and E_k the
-converged energy with the top k tenths of the terms kept (k = 10 is the full
-Hamiltonian), walk k = 10, 9, ..., 1 and return (k + 1)/10 at the first k
-with |E_k - E_10| >= delta_E, or 0.1 if none.  Integer tenths avoid the drift
-of repeated `ratio - 0.1`.
+names); it is read as: with the N non-identity terms ordered by importance
+and E_k the converged energy with the top floor(N k / 10) of them kept (k = 10
+is the full Hamiltonian), walk k = 10, 9, ..., 1 and return (k + 1)/10 at the
+first k with |E_k - E_10| >= delta_E, or 0.1 if none.  Integer tenths avoid
+the drift of repeated `ratio - 0.1`.  The identity term is always kept.
 """
 from __future__ import annotations
 
@@ -54,10 +54,20 @@ def minimize(n, circuit, hamiltonian, theta0, dtype=_lib.VQE_C128, method="SLSQP
         lam.free()
 
 
+def kept_terms(x, z, w, k):
+    """Keep mask of the top floor(N k / 10) non-identity terms (N of them) in
+    the order of importance, plus the identity, and the number of terms kept
+    (vqe_slim_hamiltonian, KEEP_TOP)."""
+    n_nonid = int(np.count_nonzero((np.asarray(x) != 0) | (np.asarray(z) != 0)))
+    keep, n_kept, _ = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_KEEP_TOP, (n_nonid * k) // 10)
+    return keep, n_kept
+
+
 def cutoff_ratio(energy_of_tenths, delta_e):
     """Algorithm 1 (read as in the module docstring): energy_of_tenths(k)
     returns the converged energy with the top k tenths of the terms kept;
-    returns the kept fraction as a float in {0.1, ..., 1.1}."""
+    returns the kept fraction as a float in {0.1, ..., 1.0} (1.0 when already
+    the first cut, to 9 tenths, moves the energy by delta_e or more)."""
     e_full = energy_of_tenths(10)
     for k in range(10, 0, -1):
         e_k = e_full if k == 10 else energy_of_tenths(k)
@@ -67,14 +77,14 @@ def cutoff_ratio(energy_of_tenths, delta_e):
 
 
 def cutoff_ratio_vqe(n, x, z, w, circuit, theta0, delta_e, dtype=_lib.VQE_C128, method="SLSQP"):
-    """Algorithm 1 on the device: for each k the Hamiltonian keeps all but
-    floor(N (10 - k) / 10) of its non-identity terms in the order of importance
-    (vqe_slim_hamiltonian, REMOVE_PERCENT), is minimised from theta0, and the
-    rule of `cutoff_ratio` picks the ratio.  Returns (ratio, {k: energy})."""
+    """Algorithm 1 on the device: for each k the Hamiltonian keeps the top
+    floor(N k / 10) of its N non-identity terms in the order of importance
+    (`kept_terms`), is minimised from theta0, and the rule of `cutoff_ratio`
+    picks the ratio.  Returns (ratio, {k: energy})."""
     energies = {}
 
     def energy_of_tenths(k):
-        keep, _, _ = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_REMOVE_PERCENT, 10 * (10 - k))
+        keep, _ = kept_terms(x, z, w, k)
         m = keep == 1
         h = _lib.vqe_hamiltonian_create(n, x[m], z[m], w[m])
         try:

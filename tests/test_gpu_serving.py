@@ -42,10 +42,24 @@ def test_energy_fn_autograd():
     ws.clear()
 
 
+def _serve(ex, budget, insts, reqs, n_workers):
+    from paper_2402_11878_amd.serving import Server
+    srv = Server(ex, budget, n_workers=n_workers)
+    for i, (n, C, H, *_r) in enumerate(insts):
+        srv.add_instance(i, n, C, H)
+    futs = srv.submit_many(reqs)
+    out = [f.result(timeout=120) for f in futs]
+    srv.close()
+    return srv, out
+
+
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_served_equals_alone(dt):
-    import torch
-    from paper_2402_11878_amd.serving import GpuExecutor, Server
+    """Every request in a burst served concurrently (small ones batched into
+    one launch, large ones overlapping on worker streams, a budget that
+    forces evictions and re-admissions) equals the same request run alone,
+    bit for bit, and matches the oracle."""
+    from paper_2402_11878_amd.serving import GpuExecutor
     say(f"case serving {dt}")
     specs = [(8, 2, 0), (12, 3, 1), (14, 2, 2), (16, 2, 3), (10, 4, 4), (18, 1, 5)]
     insts = []
@@ -53,23 +67,22 @@ def test_served_equals_alone(dt):
         x, z, w = _chain(n)
         insts.append((n, Circuit.layered(n, L), Hamiltonian(n, x, z, w), x, z, w, seed))
     ex = GpuExecutor(dt, n_ckpt=1)
-    budget = 64 << 20
     reqs = [(i, synth.theta(100 * i + k, insts[i][1].n_params)) for k in range(3) for i in range(len(insts))]
-    # alone: one request at a time
-    srv = Server(ex, budget, n_workers=1)
-    for i, (n, C, H, *_r) in enumerate(insts):
-        srv.add_instance(i, n, C, H)
-    alone = [srv.submit(i, th).result(timeout=120) for i, th in reqs]
-    srv.close()
-    # mix: everything in flight at once
-    srv = Server(ex, budget, n_workers=4)
-    for i, (n, C, H, *_r) in enumerate(insts):
-        srv.add_instance(i, n, C, H)
-    futs = [srv.submit(i, th) for i, th in reqs]
-    mixed = [f.result(timeout=120) for f in futs]
-    srv.close()
+    amp = 8 if dt == "c64" else 16
+    footprints = [3 * amp * (1 << n) for n, *_r in insts if n > ex.small_n_max]   # psi, lam, 1 checkpoint
+    # alone: one request at a time, everything fits
+    alone = []
+    for i, th in reqs:
+        _, (res,) = _serve(ex, 64 << 20, insts, [(i, th)], 1)
+        alone.append(res)
+    # mix: the whole burst in flight at once, budget below the summed footprints
+    budget = max(footprints) + min(footprints)
+    assert budget < sum(footprints)
+    srv, mixed = _serve(ex, budget, insts, reqs, 4)
     ex.close()
-    assert max(srv.batches) >= 1
+    assert max(srv.batches) >= 2, srv.batches          # several small requests in one launch
+    assert srv.max_concurrent >= 2                     # work in flight together
+    assert srv.evictions >= 1 and srv.peak_used <= budget
     for (E1, g1), (E2, g2) in zip(alone, mixed):
         assert E1 == E2 and np.array_equal(g1, g2)
     # and against the oracle
@@ -79,3 +92,28 @@ def test_served_equals_alone(dt):
         E_ref, g_ref = ogr.adjoint(n, oracle_gates(C.gates), th, oham.from_masks(n, x, z, w))
         assert rel_err(E, E_ref) <= te
         assert np.max(np.abs(g - g_ref)) / max(np.max(np.abs(g_ref)), 1) <= tg
+
+
+def test_served_c64_without_checkpoints_at_20_qubits():
+    """The form the served stream runs: complex64, no checkpoints, a 20-qubit
+    instance (specialised kernels) beside small batched ones; each result
+    against the oracle and against the same request alone."""
+    from paper_2402_11878_amd.serving import GpuExecutor
+    say("case serving c64 n_ckpt=0 20q")
+    specs = [(20, 2), (12, 2), (10, 3)]
+    insts = []
+    for n, L in specs:
+        x, z, w = _chain(n)
+        insts.append((n, Circuit.layered(n, L), Hamiltonian(n, x, z, w), x, z, w))
+    ex = GpuExecutor("c64", n_ckpt=0)
+    reqs = [(i, synth.theta(500 + 10 * i + k, insts[i][1].n_params)) for k in range(2) for i in range(len(insts))]
+    _, mixed = _serve(ex, 1 << 30, insts, reqs, 2)
+    alone = [_serve(ex, 1 << 30, insts, [r], 1)[1][0] for r in reqs]
+    ex.close()
+    for (E1, g1), (E2, g2) in zip(alone, mixed):
+        assert E1 == E2 and np.array_equal(g1, g2)
+    for (i, th), (E, g) in list(zip(reqs, mixed))[:len(insts)]:
+        n, C, H, x, z, w = insts[i]
+        E_ref, g_ref = ogr.adjoint(n, oracle_gates(C.gates), th, oham.from_masks(n, x, z, w))
+        assert rel_err(E, E_ref) <= 1e-5
+        assert np.max(np.abs(g - g_ref)) / max(np.max(np.abs(g_ref)), 1) <= 1e-4

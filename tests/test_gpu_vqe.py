@@ -137,3 +137,61 @@ def test_vqe_window_form_12_qubits():
         s.free(), l.free()
         _lib.vqe_circuit_free(c)
         _lib.vqe_hamiltonian_free(h)
+
+
+@pytest.mark.parametrize("n_orb,seed", [(6, 31), (8, 32)])
+def test_cutoff_curve_against_sector_ed(n_orb, seed):
+    """The shape of Fig. 8 on a molecule-shaped stand-in (2 n_orb qubits, 2 up
+    and 2 down electrons, one S/D layer from Hartree-Fock): for k = 10 .. 1
+    tenths of the N non-identity terms kept (removed fraction 0 .. 90 %) the
+    device VQE is run to convergence on the slimmed H_k, the full H from
+    theta = 0 and every slimmed one from the full H's optimum (so that the
+    curve follows the cutoff, not which local minimum the optimiser finds).
+    Each converged energy lies above the lowest eigenvalue of H_k restricted
+    to the electron sector (the ansatz stays in it) and equals the oracle's
+    energy at the same angles; the full H's lies below the Hartree-Fock
+    energy; the distance to the exact sector ground energy of the full H is
+    the accuracy Fig. 8 plots; Algorithm 1's ratio follows its rule on these
+    energies."""
+    n, ne = 2 * n_orb, 4
+    x, z, w, H = _problem(n_orb, seed)
+    basis = ed.sector_basis(n, 2, 2)
+    E_exact = float(np.linalg.eigvalsh(ed.restricted(H, n, basis)).min())
+    arr, P = ansatz.excitations(n, ne)
+    og = oracle_gates(arr)
+    c = _lib.vqe_circuit_create(n, arr)
+    N = int(np.count_nonzero((x != 0) | (z != 0)))
+    E_hf = expect.energy(osv.run(n, og, np.zeros(P)), n, H)[0]
+    rows = {}
+    theta_full = np.zeros(P)
+    try:
+        for k in range(10, 0, -1):
+            keep, n_kept = vqe.kept_terms(x, z, w, k)
+            m = keep == 1
+            assert n_kept - 1 == (N * k) // 10
+            Hk = oham.from_masks(n, x[m], z[m], w[m])
+            h = _lib.vqe_hamiltonian_create(n, x[m], z[m], w[m])
+            say(f"case cutoff curve n={n} k={k}")
+            try:
+                r = vqe.minimize(n, c, h, theta_full, method="BFGS", tol=1e-8)
+            finally:
+                _lib.vqe_hamiltonian_free(h)
+            if k == 10:
+                theta_full = r["theta"]
+            lo = float(np.linalg.eigvalsh(ed.restricted(Hk, n, basis)).min())
+            E_o = expect.energy(osv.run(n, og, r["theta"]), n, Hk)[0]
+            assert r["energy"] >= lo - 1e-9, (k, r["energy"], lo)
+            assert abs(r["energy"] - E_o) <= 1e-10 * max(1.0, abs(E_o)), (k, r["energy"], E_o)
+            rows[k] = (r["energy"], lo, r["n_evals"])
+    finally:
+        _lib.vqe_circuit_free(c)
+    say(f"cutoff curve n={n} N={N} P={P} exact sector ground (full H) {E_exact:.10f}, Hartree-Fock {E_hf:.10f}")
+    for k in range(10, 0, -1):
+        E, lo, ev = rows[k]
+        say(f"  removed {10 * (10 - k):3d} %: E_vqe {E:.10f}  |E_vqe - E_exact| {abs(E - E_exact):.3e}  "
+            f"sector bound of H_k {lo:.10f}  evals {ev}")
+    ratio = vqe.cutoff_ratio(lambda k: rows[k][0], 1.6e-3)
+    say(f"  Algorithm 1 (dE = 1.6e-3): kept fraction {ratio}")
+    assert E_exact - 1e-9 <= rows[10][0] < E_hf - 1e-2    # one S/D layer improves on Hartree-Fock
+    expect_ratio = next(((k + 1) / 10 for k in range(10, 0, -1) if abs(rows[k][0] - rows[10][0]) >= 1.6e-3), 0.1)
+    assert ratio == expect_ratio

@@ -117,6 +117,25 @@ def test_slim_matches_oracle_bit_exact(seed, ties):
         keep, nk, dropped = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_BUDGET, lim)
         ok, od = oslim.budget(x, z, w, lim)
         assert np.array_equal(keep, ok) and dropped == od
+    for cnt in (0, 1, 7, 150, 297, 298, 299, 1000):
+        keep, nk, dropped = _lib.vqe_slim_hamiltonian(x, z, w, _lib.SLIM_KEEP_TOP, cnt)
+        ok, od = oslim.keep_top(x, z, w, cnt)
+        assert np.array_equal(keep, ok) and nk == int(ok.sum()) and dropped == od
+
+
+def test_cutoff_search_keeps_floor_of_tenths():
+    """Algorithm 1 keeps the top N x ratio terms: with N = 23 non-identity
+    terms, k tenths keep floor(23 k / 10) of them (2, 4, 6, 9, 11, 13, 16, 18,
+    20, 23), not the ceiling that removing floor(N (10 - k) / 10) would give."""
+    from paper_2402_11878_amd import vqe
+    rng = np.random.default_rng(4)
+    x = np.concatenate([[0], rng.integers(1, 1 << 8, size=23)]).astype(np.uint64)
+    z = rng.integers(0, 1 << 8, size=24).astype(np.uint64)
+    z[0] = 0                                   # term 0 is the identity
+    w = rng.normal(size=24)
+    kept = [vqe.kept_terms(x, z, w, k)[1] - 1 for k in range(1, 11)]
+    assert kept == [2, 4, 6, 9, 11, 13, 16, 18, 20, 23]
+    assert kept != [int(np.ceil(23 * k / 10)) for k in range(1, 11)]
 
 
 def test_slim_molecule_counts_monotone():
@@ -136,6 +155,8 @@ def test_slim_argument_errors():
         _lib.vqe_slim_hamiltonian(x, x, w, 7, 0.1)
     with pytest.raises(_lib.VqeError):
         _lib.vqe_slim_hamiltonian(x, x, w, _lib.SLIM_REMOVE_PERCENT, 12.5)
+    with pytest.raises(_lib.VqeError):
+        _lib.vqe_slim_hamiltonian(x, x, w, _lib.SLIM_KEEP_TOP, 2.5)
     with pytest.raises(_lib.VqeError):
         _lib.vqe_slim_hamiltonian(x, x, w, _lib.SLIM_THRESHOLD, -1.0)
     with pytest.raises(_lib.VqeError):

@@ -110,6 +110,22 @@ def test_molecule_matches_one_body_diagonal():
     assert np.max(np.abs(block - h)) < 1e-13
 
 
+def test_restricted_matrix_is_a_block_of_the_dense_matrix():
+    """P H P on a sector equals the rows and columns of the Kronecker-built
+    dense H at those basis states, for a particle-conserving molecule-shaped
+    H and for an arbitrary Pauli sum (which leaks out of the sector)."""
+    h, g = synth.molecule_integrals(4, seed=9)
+    H = ham.molecule(h, g)
+    basis = ed.sector_basis(8, 2, 1)
+    assert len(basis) == 6 * 4 and all(bin(b).count("1") == 3 for b in basis)
+    D = ed.dense(H, 8)
+    assert np.max(np.abs(ed.restricted(H, 8, basis) - D[np.ix_(basis, basis)])) < 1e-14
+    rng = np.random.default_rng(2)
+    Hr = {tuple(rng.choice(list("IXYZ"), size=6)): float(rng.normal()) for _ in range(25)}
+    b6 = ed.sector_basis(6, 1, 2)
+    assert np.max(np.abs(ed.restricted(Hr, 6, b6) - ed.dense(Hr, 6)[np.ix_(b6, b6)])) < 1e-14
+
+
 def test_mask_round_trip():
     H = ham.hubbard(3, synth.chain_bonds(3), 1.0, 3.0)
     x, z, w = ham.to_masks(H)
@@ -289,6 +305,21 @@ def test_slim_remove_percent_and_budget(seed, ties):
         kept = np.abs(w[1:][keep[1:] == 1])
         if len(kept):
             assert s + kept.min() > lim     # the next term would exceed the budget
+
+
+@pytest.mark.parametrize("seed,ties", [(5, False), (6, True)])
+def test_slim_keep_top_bruteforce(seed, ties):
+    """Keep-top mode keeps exactly the K non-identity terms of largest |w|
+    (ties by x, then z), and the identity; the dropped sum is the rest's |w|."""
+    x, z, w = _rand_terms(seed, ties=ties)
+    N = len(w) - 1
+    for K in (0, 1, 17, N - 1, N, N + 5):
+        keep, dropped = slim.keep_top(x, z, w, K)
+        assert keep[0] == 1 and int(keep[1:].sum()) == min(K, N)
+        key = lambda i: (-abs(w[i]), int(x[i]), int(z[i]))
+        ranked = sorted(range(1, N + 1), key=key)
+        assert set(np.nonzero(keep[1:])[0] + 1) == set(ranked[:K])
+        assert abs(dropped - math.fsum(abs(w[i]) for i in ranked[K:])) < 1e-12
 
 
 def test_slim_energy_bound():

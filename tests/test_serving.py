@@ -174,3 +174,22 @@ def test_percentile_matches_numpy():
     v = rng.exponential(size=101).tolist()
     for q in (50, 90, 99):
         assert abs(percentile(v, q) - np.percentile(v, q)) < 1e-12
+
+
+def test_burst_is_batched_and_evictions_counted():
+    """A burst queued with submit_many reaches the batch loop together (one
+    launch holds several small requests); a budget below the summed
+    footprints makes the workers evict idle instances and re-admit them."""
+    budget = 3 * 8 * (1 << 16) * 2       # two 16-qubit instances at a time
+    ex = MockExecutor(budget, dur=0.01)
+    srv = _server(ex, budget, n_workers=3)
+    for i, n in enumerate([12, 12, 12, 16, 16, 16, 16]):
+        srv.add_instance(i, n, None, None)
+    items = [(i, np.full(2, float(10 * i + k))) for k in range(3) for i in range(7)]
+    futs = srv.submit_many(items)
+    for (i, th), f in zip(items, futs):
+        assert f.result(timeout=20)[0] == 2 * th[0]
+    srv.close()
+    assert max(srv.batches) >= 2
+    assert srv.evictions >= 1
+    assert srv.peak_used <= budget and ex.resident == 0
