@@ -229,6 +229,31 @@ int vqe_hamiltonian_info(const vqe_hamiltonian* h, size_t* n_terms, size_t* n_gr
  * blocks are FP64 in a fixed order, so repeated calls give identical bits. */
 int vqe_expect_pauli(vqe_state* s, const vqe_hamiltonian* h, int mode, double* energy, double* norm);
 
+/* vqe_expect_pauli in VQE_EXPECT_GROUPED mode for callers that cannot
+ * allocate memory: code under HIP graph capture, serving loops and harnesses
+ * that forbid hipMalloc.  It allocates nothing (no hipMalloc, no pinned host
+ * memory) and does not synchronise: its kernels, the same as
+ * vqe_expect_pauli's grouped sweep, are enqueued on the state's stream, and
+ * the results are written to device memory of the caller:
+ *   d_out  device memory of the state's device, 2 doubles:
+ *          d_out[0] = <psi|H|psi> / <psi|psi>, d_out[1] = <psi|psi>;
+ *          bitwise equal to vqe_expect_pauli's energy and norm.
+ * The per-block partial sums and the reduced sums live in a library-owned
+ * device array of VQE_NOALLOC_SCRATCH_BYTES per device (held until the process
+ * ends), shared by every call on that device and left holding the last
+ * call's values: calls on one device that may overlap (other streams, no
+ * ordering between them) race and give undefined results.  Tracing
+ * (vqe_profile_enable) records nothing on a stream under capture.
+ * The Hamiltonian's device tables must already exist: any earlier
+ * evaluation with h (vqe_expect_pauli, vqe_apply_hamiltonian,
+ * vqe_energy_grad) uploads them.
+ * Errors: VQE_ERR_ARG (null, qubit counts differ, d_out not device memory of
+ * the state's device), VQE_ERR_STATE (tables not uploaded),
+ * VQE_ERR_UNSUPPORTED (a sweep needing more partial sums than the scratch
+ * holds), VQE_ERR_DEVICE. */
+#define VQE_NOALLOC_SCRATCH_BYTES 65792
+int vqe_expect_pauli_noalloc(vqe_state* s, const vqe_hamiltonian* h, double* d_out);
+
 /* lam <- H psi (out of place) and energy = Re<psi|lam>/<psi|psi>. */
 int vqe_apply_hamiltonian(vqe_state* psi, vqe_state* lam, const vqe_hamiltonian* h,
                           double* energy, double* norm);

@@ -24,6 +24,7 @@ SPECIALIZE_AUTO_MIN_QUBITS = 20
 MAX_WINDOW = 7
 KERNEL_WINDOW_FWD, KERNEL_WINDOW_REV, KERNEL_HPSI, KERNEL_EXPECT_HALF, KERNEL_PER_TERM, KERNEL_DENSE = range(6)
 KERNEL_KINDS = 6
+NOALLOC_SCRATCH_BYTES = 65792
 DENSE_K = 5
 
 
@@ -80,6 +81,7 @@ _SIGS = {
     "vqe_hamiltonian_free": (C.c_int, [_P]),
     "vqe_hamiltonian_info": (C.c_int, [_P, C.POINTER(_SZ), C.POINTER(_SZ), C.POINTER(C.c_double)]),
     "vqe_expect_pauli": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vqe_expect_pauli_noalloc": (C.c_int, [_P, _P, _P]),
     "vqe_apply_hamiltonian": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "vqe_energy_grad": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double), _SZ, _P, C.POINTER(vqe_grad_opts),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -249,6 +251,12 @@ def vqe_expect_pauli(s, h, mode=EXPECT_GROUPED):
     e, n = C.c_double(), C.c_double()
     check("vqe_expect_pauli", lib().vqe_expect_pauli(s, h, mode, C.byref(e), C.byref(n)))
     return e.value, n.value
+
+
+def vqe_expect_pauli_noalloc(s, h, d_out):
+    """Grouped energy into device memory d_out (2 doubles: energy, norm);
+    d_out is a device pointer (int).  Enqueued, not synchronised."""
+    return check("vqe_expect_pauli_noalloc", lib().vqe_expect_pauli_noalloc(s, h, C.c_void_p(d_out)))
 
 
 def vqe_apply_hamiltonian(psi, lam, h):

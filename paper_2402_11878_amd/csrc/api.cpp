@@ -870,9 +870,13 @@ double hpsi_bytes(const vqe_hamiltonian* h, const vqe_state* s, bool write) {
 
 // Grouped energy sums (Re<psi|H|psi>, <psi|psi>) reduced into sums[0..1]
 // on the device, with per-block partials in part (at most
-// kEnergyPartBlocks blocks of 2): m energy-only window passes (m S read;
+// energy_part_blocks() blocks of 2): m energy-only window passes (m S read;
 // per pass, its partials reduced and added in pass order) or one tile sweep
 // that visits each out-of-tile pair once ((1 + D/2) S read).
+uint32_t energy_part_blocks(const vqe_hamiltonian* h, int n) {
+    return h->hw_energy ? hwin_blocks(n) : hpsi_blocks(n, kEnergyPartBlocks);
+}
+
 template <typename T>
 int energy_grouped(vqe_state* s, const vqe_hamiltonian* h, double* part, double* sums) {
     uint32_t nb = 0;
@@ -1988,3 +1992,83 @@ int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* byt
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- grouped energy without allocation
+// Scratch memory of vqe_expect_pauli_noalloc: the per-block partial sums of
+// the energy sweep (kEnergyPartBlocks blocks x 2) and the two reduced sums,
+// in a fixed device array.  Each device that runs the call holds its own
+// copy until the process ends.  Host code never passes the array's name to a
+// kernel: it uses the address hipGetSymbolAddress returns on each device.
+namespace {
+constexpr size_t kScratchPart = 2 * (size_t)kEnergyPartBlocks;
+constexpr size_t kScratchDoubles = kScratchPart + 32;  // partials | sums[2] | pad
+static_assert(kScratchDoubles * sizeof(double) == VQE_NOALLOC_SCRATCH_BYTES, "scratch size and its public limit differ");
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+// Address of this device's scratch array, looked up once per device with that
+// device current.
+int scratch_of_device(int dev, double** out) {
+    if (dev < 0 || dev >= kScratchDevices) {
+        set_error("vqe_expect_pauli_noalloc: device index beyond the scratch table");
+        return VQE_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("vqe_expect_pauli_noalloc: hipGetSymbolAddress of the scratch array: ") +
+                      hipGetErrorString(e));
+            return VQE_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VQE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int vqe_expect_pauli_noalloc(vqe_state* s, const vqe_hamiltonian* h, double* d_out) {
+    VQE_GUARD_BEGIN
+    if (int rc = check_state(s, "vqe_expect_pauli_noalloc")) return rc;
+    if (!h || h->n != s->n || !d_out) {
+        set_error("vqe_expect_pauli_noalloc: Hamiltonian missing, of a different qubit count, or null d_out");
+        return VQE_ERR_ARG;
+    }
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, d_out) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != s->device) {
+        (void)hipGetLastError();
+        set_error("vqe_expect_pauli_noalloc: d_out is not device memory of the state's device");
+        return VQE_ERR_ARG;
+    }
+    if (!h->d_ready) {
+        set_error("vqe_expect_pauli_noalloc: the Hamiltonian's tables are not on the device yet (any evaluation "
+                  "with it, e.g. vqe_expect_pauli, uploads them)");
+        return VQE_ERR_STATE;
+    }
+    const uint32_t blocks = energy_part_blocks(h, s->n);
+    if ((size_t)blocks * 2 > kScratchPart) {
+        set_error("vqe_expect_pauli_noalloc: the sweep needs " + std::to_string(blocks) +
+                  " blocks of partial sums, more than the scratch holds (" + std::to_string(kEnergyPartBlocks) + ")");
+        return VQE_ERR_UNSUPPORTED;
+    }
+    VQE_HIP(hipSetDevice(s->device));
+    double* sc = nullptr;
+    if (int rc = scratch_of_device(s->device, &sc)) return rc;
+    double* sums = sc + kScratchPart;
+    int rc = s->dtype == VQE_C64 ? energy_grouped<float>(s, h, sc, sums) : energy_grouped<double>(s, h, sc, sums);
+    if (rc) return rc;
+    VQE_HIP(launch_energy_ratio(sums, d_out, s->stream));
+    return VQE_OK;
+    VQE_GUARD_END
+}
+
+}  // extern "C"

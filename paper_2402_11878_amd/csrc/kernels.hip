@@ -1163,6 +1163,15 @@ reduce_kernel(const double* __restrict__ part, uint32_t nblocks, uint32_t nslots
     }
 }
 
+// out[0] = sums[0] / sums[1] (the energy of eq. 7), out[1] = sums[1] (the norm).
+__global__ void energy_ratio_kernel(const double* __restrict__ sums, double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        const double e = sums[0], nrm = sums[1];
+        out[0] = e / nrm;
+        out[1] = nrm;
+    }
+}
+
 uint32_t grid_for(uint64_t items) {
     uint64_t b = (items + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
@@ -1362,6 +1371,14 @@ hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const
     return hipGetLastError();
 }
 
+uint32_t hpsi_blocks(int n, uint32_t max_blocks) {
+    const int tb = n < kTileBits ? n : kTileBits;
+    const uint64_t n_tiles = 1ull << (n - tb);
+    uint32_t tpb = 1;
+    while ((n_tiles + tpb - 1) / tpb > (uint64_t)max_blocks) tpb *= 2;
+    return (uint32_t)((n_tiles + tpb - 1) / tpb);
+}
+
 template <typename T>
 hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* groups, uint32_t n_groups,
                        const TermDesc<T>* terms, int mode, uint32_t max_blocks, double* part, uint32_t* nblocks,
@@ -1405,6 +1422,17 @@ hipError_t launch_expect_term(int n, const void* psi, uint64_t x, uint64_t z, do
     const T cre = (y == 0) ? T(1) : (y == 2 ? T(-1) : T(0));
     const T cim = (y == 1) ? T(-1) : (y == 3 ? T(1) : T(0));
     hipLaunchKernelGGL(expect_term_kernel<T>, dim3(g), dim3(kBlock), 0, st, n, cpt, (const V*)psi, x, z, hbit, cre, cim, part);
+    return hipGetLastError();
+}
+
+uint32_t hwin_blocks(int n) {
+    WinShape ws{};
+    grid_for_units(n >= kHwBits ? 1ull << (n - kHwBits) : 1, true, ws);
+    return ws.grid;
+}
+
+hipError_t launch_energy_ratio(const double* sums, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(energy_ratio_kernel, dim3(1), dim3(64), 0, st, sums, out);
     return hipGetLastError();
 }
 

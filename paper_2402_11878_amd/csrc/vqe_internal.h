@@ -290,9 +290,17 @@ template <typename T>
 hipError_t launch_hpsi(int n, const void* psi, void* lam, const GroupDesc* groups, uint32_t n_groups,
                        const TermDesc<T>* terms, int mode, uint32_t max_blocks, double* part, uint32_t* nblocks,
                        hipStream_t st);
-// Grouped energy-only sweeps launch at most this many blocks.
+// Blocks that launch_hpsi uses at n qubits under max_blocks, and that a
+// window pass of H psi (launch_hwin) uses at n qubits.
+uint32_t hpsi_blocks(int n, uint32_t max_blocks);
+uint32_t hwin_blocks(int n);
+// Grouped energy-only sweeps (vqe_expect_pauli and its no-allocation form)
+// launch at most this many blocks: one block count, hence one reduction
+// order, for both.
 constexpr uint32_t kEnergyPartBlocks = 4096;
 
+// out[0] = sums[0] / sums[1], out[1] = sums[1] (one thread; device memory).
+hipError_t launch_energy_ratio(const double* sums, double* out, hipStream_t st);
 
 // One term: partials of Re<psi|P(x,z)|psi> (pair-halved) and <psi|psi>.
 template <typename T>
