@@ -177,10 +177,11 @@ def cpu_baseline(wl_name):
                 sample_seconds=t, host_cpus=os.cpu_count())
 
 
-def serving_bench(args):
+def serving_bench(args, fracs=(0.5, 0.8, 0.95), baseline=True, emit=True):
     """Served stream of 32 optimiser instances (complex64, adjoint gradients,
     continuous batching) against one-at-a-time complex128 per-term energies
-    with parameter-shift gradients on the same GPU."""
+    with parameter-shift gradients on the same GPU.  Returns the result dict
+    (printed as one JSON line when emit)."""
     import torch
     import synth
     from paper_2402_11878_amd import _lib as L, hamiltonians as hm
@@ -202,11 +203,13 @@ def serving_bench(args):
         insts.append(dict(i=i, n=n, kind=kind, layers=layers, rng=rng, C=Circuit.layered(n, layers),
                           H=Hamiltonian(n, x, z, w)))
     log(f"[serving] {n_inst} instances built")
-    ex = GpuExecutor("c64", n_ckpt=0)
+    t_build = time.perf_counter()
+    ex = GpuExecutor("c64", n_ckpt=0, reserve_cus=args.reserve_cus, mid_n_max=args.mid_n_max)
     budget = int(args.budget_gib * (1 << 30))
 
     def new_server():
-        srv = Server(ex, budget, n_workers=args.workers)
+        srv = Server(ex, budget, n_workers=args.workers, mid_n_max=args.mid_n_max if args.mid_workers else None,
+                     mid_workers=args.mid_workers)
         for d in insts:
             srv.add_instance(d["i"], d["n"], d["C"], d["H"])
         return srv
@@ -218,6 +221,7 @@ def serving_bench(args):
     for f in [srv.submit(d["i"], draw(d)) for d in insts]:      # warm-up, makes instances resident
         f.result()
     torch.cuda.synchronize()
+    log(f"[serving] instances registered and warm ({time.perf_counter() - t_build:.1f} s)")
     # capacity: every instance submits `reps` requests at once
     reqs = [(d["i"], draw(d)) for _ in range(args.reps) for d in insts]
     t0 = time.perf_counter()
@@ -227,7 +231,7 @@ def serving_bench(args):
     log(f"[serving] capacity {cap:.2f} evals/s")
     srv.close()
     loads = {}
-    for frac in (0.5, 0.8, 0.95):
+    for frac in fracs:
         srv = new_server()
         for f in [srv.submit(d["i"], draw(d)) for d in insts]:
             f.result()
@@ -272,6 +276,20 @@ def serving_bench(args):
         log(f"[serving] load {frac}: {loads[str(frac)]}")
         srv.close()
     ex.close()
+    out = {
+        "metric": "served energy+gradient evals/s (32 optimiser instances) and p50/p99 latency",
+        "value": cap, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32 state, f64 reductions", "data": "synthetic",
+        "config": {"workload": f"{n_inst} instances: n in {{12,16,20,24,28}}, 1-D/2-D Hubbard and molecule-shaped "
+                               f"(slimmed at {args.slim}) Hamiltonians, 4-16 layers, seeds 10000+i",
+                   "workers": args.workers, "mid_workers": args.mid_workers, "mid_n_max": args.mid_n_max,
+                   "reserve_cus": args.reserve_cus, "budget_gib": args.budget_gib, "requests_per_load": args.requests},
+        "loads": loads,
+    }
+    if not baseline:
+        if emit:
+            print(json.dumps(out), flush=True)
+        return out
     # baseline: complex128, per-term energy, parameter shift, one request at a time
     base_t = []
     acc = []
@@ -301,20 +319,13 @@ def serving_bench(args):
         del bufs
     torch.cuda.empty_cache()
     base_rate = 1.0 / float(np.mean(base_t))
-    out = {
-        "metric": "served energy+gradient evals/s (32 optimiser instances) and p50/p99 latency",
-        "value": cap, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
-        "dtype": "f32 state, f64 reductions", "data": "synthetic",
-        "config": {"workload": f"{n_inst} instances: n in {{12,16,20,24,28}}, 1-D/2-D Hubbard and molecule-shaped "
-                               f"(slimmed at {args.slim}) Hamiltonians, 4-16 layers, seeds 10000+i",
-                   "workers": args.workers, "budget_gib": args.budget_gib},
-        "loads": loads,
-        "baseline_per_term_param_shift_f64": {"evals_per_s": base_rate,
-                                              "method": "one request at a time: (2P+1) x measured per-term energy time"},
-        "speedup_vs_baseline": cap / base_rate,
-        "accuracy_vs_baseline_small": acc,
-    }
-    print(json.dumps(out), flush=True)
+    out["baseline_per_term_param_shift_f64"] = {"evals_per_s": base_rate,
+                                                "method": "one request at a time: (2P+1) x measured per-term energy time"}
+    out["speedup_vs_baseline"] = cap / base_rate
+    out["accuracy_vs_baseline_small"] = acc
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def copy_calibration(args):
@@ -479,9 +490,15 @@ def main():
                     help="kernel form of the window passes (vqe_set_specialize): interpreted 5-qubit windows "
                          "(never), specialised 7-qubit windows from 20 qubits on (auto, the default), or always")
     ap.add_argument("--instances", type=int, default=32)
-    ap.add_argument("--requests", type=int, default=96)
+    ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--reps", type=int, default=2)
-    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=3, help="serving: workers for large requests")
+    ap.add_argument("--mid-workers", type=int, default=1,
+                    help="serving: workers of the mid-size lane (0: mid-size requests share the large workers)")
+    ap.add_argument("--mid-n-max", type=int, default=20, help="serving: largest qubit count of the mid-size lane")
+    ap.add_argument("--reserve-cus", type=int, default=32,
+                    help="serving: compute units reserved for the batched and mid-size lanes (0: none)")
+    ap.add_argument("--no-serving", action="store_true", help="step mode: skip the short serving leg")
     ap.add_argument("--budget-gib", type=float, default=160.0)
     ap.add_argument("--slim", type=float, default=1e-3)
     args = ap.parse_args()
@@ -583,6 +600,13 @@ def main():
     if not args.no_cpu_baseline and wl.kind != "molecule":
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.workload)
+    if not args.no_serving:
+        log("[bench] serving leg ...")
+        sv = serving_bench(args, fracs=(0.8,), baseline=False, emit=False)
+        ld = sv["loads"]["0.8"]
+        out["serving"] = {"capacity_evals_per_s": sv["value"], "load": 0.8, "offered": ld["offered"],
+                          "achieved_in_window": ld["achieved_in_window"], "p50_ms": ld["p50_ms"],
+                          "p99_ms": ld["p99_ms"], "requests": args.requests, "config": sv["config"]}
     print(json.dumps(out), flush=True)
 
 

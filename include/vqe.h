@@ -306,6 +306,21 @@ int vqe_batch_create(int dtype, void* hip_stream, vqe_batch** out);
 int vqe_batch_free(vqe_batch* b);
 int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* items);
 
+/* ------------------------------------------------------------------ streams
+ * A HIP stream of the current device for the work of states (vqe_state_alloc's
+ * hip_stream), optionally restricted to a subset of the compute units, so
+ * that the short kernels of latency-sensitive evaluations (small served
+ * requests) do not wait for compute units held by long-running passes of
+ * large ones.
+ *   cu_mask     bit i of word i / 32 selects compute unit i (hipExtStreamCreateWithCUMask);
+ *               NULL with mask_words = 0: an ordinary non-blocking stream
+ *   mask_words  32-bit words in cu_mask
+ *   stream      out: the hipStream_t; release with vqe_stream_destroy
+ * Default priority.  Errors: VQE_ERR_ARG (null, a mask selecting no compute
+ * unit of the device), VQE_ERR_DEVICE. */
+int vqe_stream_create(const uint32_t* cu_mask, size_t mask_words, void** stream);
+int vqe_stream_destroy(void* stream);
+
 /* ------------------------------------------------------------------ tracing
  * Per-kernel timing with HIP events.  While enabled (process-wide), every
  * launch of a state-sweeping kernel is bracketed by two events recorded on

@@ -91,6 +91,8 @@ _SIGS = {
     "vqe_set_specialize": (C.c_int, [C.c_int]),
     "vqe_hamiltonian_plan": (C.c_int, [_P, C.POINTER(_SZ), C.POINTER(C.c_uint64), _SZ]),
     "vqe_circuit_prepare": (C.c_int, [_P, C.c_int]),
+    "vqe_stream_create": (C.c_int, [C.POINTER(C.c_uint32), _SZ, C.POINTER(_P)]),
+    "vqe_stream_destroy": (C.c_int, [_P]),
     "vqe_profile_enable": (C.c_int, [C.c_int]),
     "vqe_profile_reset": (C.c_int, []),
     "vqe_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -299,6 +301,26 @@ def vqe_set_specialize(mode):
 def vqe_circuit_prepare(c, dtype):
     """Compiles/loads the specialised kernels an evaluation of dtype would use (no-op otherwise)."""
     check("vqe_circuit_prepare", lib().vqe_circuit_prepare(c, dtype))
+
+
+def vqe_stream_create(cus=None):
+    """A stream restricted to the compute units in `cus` (iterable of CU
+    indices; None: an ordinary non-blocking stream); returns the hipStream_t as int."""
+    out = C.c_void_p()
+    if cus is None:
+        check("vqe_stream_create", lib().vqe_stream_create(None, 0, C.byref(out)))
+    else:
+        cus = sorted(set(int(c) for c in cus))
+        words = (max(cus) // 32 + 1) if cus else 1
+        m = (C.c_uint32 * words)()
+        for c in cus:
+            m[c // 32] |= 1 << (c % 32)
+        check("vqe_stream_create", lib().vqe_stream_create(m, words, C.byref(out)))
+    return out.value
+
+
+def vqe_stream_destroy(stream):
+    check("vqe_stream_destroy", lib().vqe_stream_destroy(C.c_void_p(stream)))
 
 
 def vqe_profile_enable(on=True):

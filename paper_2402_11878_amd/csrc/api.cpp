@@ -1964,6 +1964,40 @@ int vqe_set_specialize(int mode) {
     return vqe::jit_set_mode(mode);
 }
 
+int vqe_stream_create(const uint32_t* cu_mask, size_t mask_words, void** stream) {
+    VQE_GUARD_BEGIN
+    if (!stream || (mask_words && !cu_mask)) {
+        set_error("vqe_stream_create: null argument");
+        return VQE_ERR_ARG;
+    }
+    hipStream_t st = nullptr;
+    if (mask_words == 0) {
+        VQE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    } else {
+        int dev = 0, ncu = 0;
+        VQE_HIP(hipGetDevice(&dev));
+        VQE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        size_t on = 0;
+        for (size_t i = 0; i < mask_words; ++i)
+            for (int b = 0; b < 32; ++b)
+                if (((cu_mask[i] >> b) & 1) && (int)(32 * i + b) < ncu) ++on;
+        if (on == 0) {
+            set_error("vqe_stream_create: the CU mask selects no compute unit of the device");
+            return VQE_ERR_ARG;
+        }
+        VQE_HIP(hipExtStreamCreateWithCUMask(&st, (uint32_t)mask_words, cu_mask));
+    }
+    *stream = st;
+    return VQE_OK;
+    VQE_GUARD_END
+}
+
+int vqe_stream_destroy(void* stream) {
+    if (!stream) return VQE_OK;
+    VQE_HIP(hipStreamDestroy((hipStream_t)stream));
+    return VQE_OK;
+}
+
 int vqe_profile_enable(int on) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof_on = on != 0;

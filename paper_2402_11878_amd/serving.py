@@ -11,6 +11,12 @@ node groups (Sec. II-C).  Here they share one GPU:
   * large requests run on worker threads, each instance on its own HIP stream
     with its state vectors (psi, lam, checkpoints) resident in HBM, so
     several instances' kernels overlap on the device;
+  * optionally, mid-size requests (up to `mid_n_max` qubits) form a lane of
+    their own with dedicated workers, so that they never queue behind large
+    ones on the host; the GPU executor can also reserve a few compute units
+    for the batched and mid-size lanes (streams with CU masks), so that their
+    short kernels do not wait for the compute units that the persistent
+    kernels of large requests hold;
   * an instance becomes resident only while the summed footprint of resident
     instances stays within the HBM budget; idle resident instances are
     evicted least-recently-used first;
@@ -71,8 +77,11 @@ def percentile(values, q):
 
 
 class Server:
-    def __init__(self, executor, budget_bytes, n_workers=4, max_batch=64, max_wait=2.0, clock=time.perf_counter):
+    def __init__(self, executor, budget_bytes, n_workers=4, max_batch=64, max_wait=2.0, clock=time.perf_counter,
+                 mid_n_max=None, mid_workers=1):
         self.ex = executor
+        # requests of more than the batch limit and at most mid_n_max qubits go to the mid lane
+        self.mid_n_max = mid_n_max if (mid_n_max is not None and mid_workers > 0) else None
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
         self.max_wait = max_wait
@@ -83,6 +92,7 @@ class Server:
         self._cv = threading.Condition()
         self._small = collections.deque()
         self._large = collections.deque()
+        self._mid = collections.deque()
         self._closing = False
         self.completed = []
         self.batches = []          # sizes of the launched batches
@@ -90,7 +100,11 @@ class Server:
         self.max_concurrent = 0
         self._running = 0
         self._threads = [threading.Thread(target=self._batch_loop, daemon=True)]
-        self._threads += [threading.Thread(target=self._worker_loop, daemon=True) for _ in range(n_workers)]
+        self._threads += [threading.Thread(target=self._worker_loop, args=(self._large,), daemon=True)
+                          for _ in range(n_workers)]
+        if self.mid_n_max is not None:
+            self._threads += [threading.Thread(target=self._worker_loop, args=(self._mid,), daemon=True)
+                              for _ in range(mid_workers)]
         for t in self._threads:
             t.start()
 
@@ -119,7 +133,7 @@ class Server:
             if self._closing:
                 raise RuntimeError("server is closed")
             for req in reqs:
-                (self._small if self.ex.is_small(req.inst) else self._large).append(req)
+                self._queue_of(req.inst).append(req)
             self._cv.notify_all()
         return [r.future for r in reqs]
 
@@ -133,6 +147,13 @@ class Server:
             if inst.resident:
                 self.ex.release(inst)
                 inst.resident = False
+
+    def _queue_of(self, inst):
+        if self.ex.is_small(inst):
+            return self._small
+        if self.mid_n_max is not None and inst.n <= self.mid_n_max:
+            return self._mid
+        return self._large
 
     def latencies(self):
         return [r.done_t - r.submit_t for r in self.completed]
@@ -196,26 +217,26 @@ class Server:
         self.peak_used = max(self.peak_used, self.used)
         return True
 
-    def _pick(self):
-        """Oldest runnable large request (caller holds the lock), or None."""
+    def _pick(self, queue):
+        """Oldest runnable request of `queue` (caller holds the lock), or None."""
         now = self.clock()
-        for k, req in enumerate(self._large):
+        for k, req in enumerate(queue):
             if req.inst.busy:
                 continue
             if self._admit(req.inst):
-                del self._large[k]
+                del queue[k]
                 return req
             if now - req.submit_t > self.max_wait:
                 return None          # the old request waits for memory: admit nobody younger
         return None
 
-    def _worker_loop(self):
+    def _worker_loop(self, queue):
         while True:
             with self._cv:
                 while True:
-                    if self._closing and not self._large:
+                    if self._closing and not queue:
                         return
-                    req = self._pick()
+                    req = self._pick(queue)
                     if req is not None:
                         break
                     self._cv.wait(timeout=0.05)
@@ -238,9 +259,14 @@ class Server:
 
 class GpuExecutor:
     """Runs requests with libvqe.so: batched LDS kernel for small states, the
-    fused-pass adjoint path on per-instance streams for large ones."""
+    fused-pass adjoint path on per-instance streams for large ones.
 
-    def __init__(self, dtype="c64", n_ckpt=0, small_n_max=None):
+    reserve_cus > 0 splits the compute units: the batched launches and the
+    instances of at most mid_n_max qubits run on one stream restricted to
+    the first reserve_cus compute units, larger instances on big_streams
+    streams restricted to the others (vqe_stream_create with a CU mask)."""
+
+    def __init__(self, dtype="c64", n_ckpt=0, small_n_max=None, reserve_cus=0, mid_n_max=20, big_streams=3):
         import torch
 
         from . import _lib
@@ -251,8 +277,32 @@ class GpuExecutor:
         self.n_ckpt = n_ckpt
         lim = _lib.BATCH_MAX_QUBITS[self.dtype]
         self.small_n_max = lim if small_n_max is None else min(small_n_max, lim)
-        self.batch_stream = torch.cuda.Stream()
+        self.mid_n_max = mid_n_max
+        self._own_streams = []
+        self._rr = 0
+        if reserve_cus > 0:
+            ncu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+            if not 0 < reserve_cus < ncu:
+                raise ValueError(f"reserve_cus must be in (0, {ncu})")
+            fast = _lib.vqe_stream_create(range(reserve_cus))
+            big = [_lib.vqe_stream_create(range(reserve_cus, ncu)) for _ in range(big_streams)]
+            self._own_streams = [fast] + big
+            self.batch_stream = torch.cuda.ExternalStream(fast)
+            self.fast_stream = self.batch_stream
+            self.big_streams = [torch.cuda.ExternalStream(b) for b in big]
+        else:
+            self.batch_stream = torch.cuda.Stream()
+            self.fast_stream = None
+            self.big_streams = []
         self.batch = _lib.vqe_batch_create(self.dtype, self.batch_stream.cuda_stream)
+
+    def _stream_for(self, inst):
+        if self.fast_stream is None:
+            return self.torch.cuda.Stream()
+        if inst.n <= self.mid_n_max:
+            return self.fast_stream
+        self._rr = (self._rr + 1) % len(self.big_streams)
+        return self.big_streams[self._rr]
 
     def is_small(self, inst):
         return inst.n <= self.small_n_max
@@ -267,7 +317,7 @@ class GpuExecutor:
 
     def make_resident(self, inst):
         torch, L = self.torch, self.L
-        st = torch.cuda.Stream()
+        st = self._stream_for(inst)
         bufs = [torch.empty(1 << inst.n, dtype=self.tdtype, device="cuda") for _ in range(2 + self.n_ckpt)]
         hs = [L.vqe_state_alloc(inst.n, self.dtype, b.data_ptr(), b.numel() * b.element_size(), st.cuda_stream)
               for b in bufs]
@@ -292,3 +342,8 @@ class GpuExecutor:
         if self.batch:
             self.L.vqe_batch_free(self.batch)
             self.batch = None
+        if self._own_streams:
+            self.torch.cuda.synchronize()
+            for st in self._own_streams:
+                self.L.vqe_stream_destroy(st)
+            self._own_streams = []

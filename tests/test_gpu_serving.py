@@ -117,3 +117,63 @@ def test_served_c64_without_checkpoints_at_20_qubits():
         E_ref, g_ref = ogr.adjoint(n, oracle_gates(C.gates), th, oham.from_masks(n, x, z, w))
         assert rel_err(E, E_ref) <= 1e-5
         assert np.max(np.abs(g - g_ref)) / max(np.max(np.abs(g_ref)), 1) <= 1e-4
+
+
+def test_cu_masked_stream_gives_the_same_bits():
+    """An evaluation on a stream restricted to 32 compute units (vqe_stream_create
+    with a CU mask) gives bitwise the result of the same evaluation on an
+    ordinary stream: the kernels and their reduction order do not depend on
+    where the blocks run."""
+    import torch
+    say("case cu-masked stream")
+    n = 16
+    x, z, w = _chain(n)
+    H = Hamiltonian(n, x, z, w)
+    C = Circuit.layered(n, 3)
+    th = synth.theta(77, C.n_params)
+    res = []
+    streams = [_lib.vqe_stream_create(range(32)), _lib.vqe_stream_create()]
+    try:
+        for st in streams:
+            bufs = [torch.empty(1 << n, dtype=torch.complex128, device="cuda") for _ in range(2)]
+            hs = [_lib.vqe_state_alloc(n, _lib.VQE_C128, b.data_ptr(), b.numel() * 16, st) for b in bufs]
+            try:
+                res.append(_lib.vqe_energy_grad(hs[0], hs[1], C.handle, th, H.handle))
+            finally:
+                for h in hs:
+                    _lib.vqe_state_free(h)
+    finally:
+        torch.cuda.synchronize()
+        for st in streams:
+            _lib.vqe_stream_destroy(st)
+    (E1, g1), (E2, g2) = res
+    assert E1 == E2 and np.array_equal(g1, g2)
+    E_ref, g_ref = ogr.adjoint(n, oracle_gates(C.gates), th, oham.from_masks(n, x, z, w))
+    assert rel_err(E1, E_ref) <= 1e-10
+
+
+def test_served_with_lanes_equals_alone():
+    """Serving with a mid-size lane and 32 compute units reserved for the
+    batched and mid-size lanes: every result equals the same request served
+    alone without lanes, bit for bit."""
+    from paper_2402_11878_amd.serving import GpuExecutor
+    say("case serving with lanes")
+    specs = [(10, 2), (12, 3), (16, 2), (18, 2), (20, 1), (22, 1)]
+    insts = []
+    for n, L in specs:
+        x, z, w = _chain(n)
+        insts.append((n, Circuit.layered(n, L), Hamiltonian(n, x, z, w), x, z, w))
+    reqs = [(i, synth.theta(900 + 10 * i + k, insts[i][1].n_params)) for k in range(2) for i in range(len(insts))]
+    ex0 = GpuExecutor("c64", n_ckpt=0)
+    alone = [_serve(ex0, 1 << 30, insts, [r], 1)[1][0] for r in reqs]
+    ex0.close()
+    ex = GpuExecutor("c64", n_ckpt=0, reserve_cus=32, mid_n_max=18, big_streams=2)
+    from paper_2402_11878_amd.serving import Server
+    srv = Server(ex, 1 << 30, n_workers=2, mid_n_max=18, mid_workers=1)
+    for i, (n, C, H, *_r) in enumerate(insts):
+        srv.add_instance(i, n, C, H)
+    mixed = [f.result(timeout=120) for f in srv.submit_many(reqs)]
+    srv.close()
+    ex.close()
+    for (E1, g1), (E2, g2) in zip(alone, mixed):
+        assert E1 == E2 and np.array_equal(g1, g2)

@@ -193,3 +193,19 @@ def test_burst_is_batched_and_evictions_counted():
     assert max(srv.batches) >= 2
     assert srv.evictions >= 1
     assert srv.peak_used <= budget and ex.resident == 0
+
+
+def test_mid_lane_is_not_blocked_by_large_requests():
+    """With a mid lane, mid-size requests are served by their own worker while
+    every large worker is busy with long requests."""
+    ex = MockExecutor(1 << 34, dur=0.2)
+    srv = _server(ex, 1 << 34, n_workers=1, mid_n_max=20, mid_workers=1)
+    srv.add_instance(0, 28, None, None)
+    srv.add_instance(1, 16, None, None)
+    fl = srv.submit(0, np.ones(1))
+    time.sleep(0.02)
+    fm = srv.submit(1, np.ones(1))
+    fm.result(timeout=10)
+    assert not fl.done()            # the mid request finished while the large one still ran
+    fl.result(timeout=10)
+    srv.close()
