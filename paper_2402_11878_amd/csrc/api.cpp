@@ -73,9 +73,6 @@ struct PassOps {
     // Per dtype (0: complex64, 1: complex128): lane-split bits of the forward
     // and reverse pass and, where S > 0, the ops lowered to physical slots.
     int S_f[2] = {0, 0}, S_r[2] = {0, 0};
-    // specialised passes whose window holds qubits 0 .. S-1 keep those bits in
-    // lane bits 0 .. S-1 (contiguous loads; see jit_source)
-    bool low_f[2] = {false, false}, low_r[2] = {false, false};
     SplitOps fwd_l[2], rev_l[2];
 };
 
@@ -236,7 +233,7 @@ int ensure_res(vqe_state* s, size_t count) {
 }
 
 int upload_plan(const Plan& cpl);
-bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps& out, bool low);
+bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps& out);
 
 // Device copies of a Hamiltonian's tables; the handle publishes them only
 // when every one was allocated and copied (d_ready), so a failed upload
@@ -661,12 +658,10 @@ int check_form(const vqe_circuit* c, const char* fn) {
 const Plan& plan_now(const vqe_circuit* c) { return c->plan[use_specialised(c) ? 1 : 0]; }
 
 // Physical ops, lane-split bits and slot positions of one specialised pass.
-const std::vector<KOp>& jit_ops(const Plan& pl, size_t pi, int d, bool reverse, int* S, JitArgs* a, int n,
-                                bool* low = nullptr) {
+const std::vector<KOp>& jit_ops(const Plan& pl, size_t pi, int d, bool reverse, int* S, JitArgs* a, int n) {
     const PlannedPass& p = pl.passes[pi];
     const PassOps& po = pl.ops[pi];
     *S = reverse ? po.S_r[d] : po.S_f[d];
-    if (low) *low = reverse ? po.low_r[d] : po.low_f[d];
     if (a) {
         std::memset(a, 0, sizeof(*a));
         a->n_cosets = 1ull << (n - p.K);
@@ -699,10 +694,9 @@ int ensure_jit(const vqe_circuit* c, const Plan& cpl, int d) {
     for (size_t pi = 0; pi < P; ++pi)
         for (int dir = 0; dir < 2; ++dir) {
             int S = 0;
-            bool low = false;
-            const auto& ops = jit_ops(pl, pi, d, dir == 1, &S, nullptr, c->n, &low);
+            const auto& ops = jit_ops(pl, pi, d, dir == 1, &S, nullptr, c->n);
             srcs[2 * pi + dir] = jit_source(d == 1, pl.passes[pi].K, S, dir == 1 ? 2 : 1, ops,
-                                            dir == 1 ? (uint32_t)pl.ops[pi].slot_param.size() : 0, low);
+                                            dir == 1 ? (uint32_t)pl.ops[pi].slot_param.size() : 0);
         }
     std::vector<void*> fns;
     std::string err;
@@ -1141,16 +1135,8 @@ int build_plan(vqe_circuit* c, const PlanLimits& lim, bool jit, Plan& pl) {
         for (int d = 0; d < 2; ++d) {
             po.S_f[d] = split_bits_for(jit, d == 1, p.K, false);
             po.S_r[d] = split_bits_for(jit, d == 1, p.K, true);
-            auto holds_low = [&](int S) {
-                if (!jit || S == 0 || S > p.K) return false;
-                for (int j = 0; j < S; ++j)
-                    if (p.pos[j] != j) return false;
-                return true;
-            };
-            po.low_f[d] = holds_low(po.S_f[d]);
-            po.low_r[d] = holds_low(po.S_r[d]);
-            if ((po.S_f[d] && !lower_split(po.fwd, p.K, po.S_f[d], cap, po.fwd_l[d], po.low_f[d])) ||
-                (po.S_r[d] && !lower_split(po.rev, p.K, po.S_r[d], cap, po.rev_l[d], po.low_r[d]))) {
+            if ((po.S_f[d] && !lower_split(po.fwd, p.K, po.S_f[d], cap, po.fwd_l[d])) ||
+                (po.S_r[d] && !lower_split(po.rev, p.K, po.S_r[d], cap, po.rev_l[d]))) {
                 set_error("vqe_circuit_create: too many ops in a pass after lane transposes (internal limit)");
                 return VQE_ERR_STATE;
             }
@@ -1186,7 +1172,7 @@ uint32_t reg_needs(const KOp& op) {
 // often start in the lanes; before an op that needs a lane-resident bit in
 // registers, a TPOSE swaps it with the register bit whose next use is
 // furthest away.  Returns false if the op capacity would be exceeded.
-bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps& out, bool low) {
+bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps& out) {
     const int KL = K - S;
     int cost[kMaxWindow] = {0};
     for (const auto& op : ops)
@@ -1194,11 +1180,7 @@ bool lower_split(const std::vector<KOp>& ops, int K, int S, size_t cap, SplitOps
             if (reg_needs(op) >> w & 1) cost[w]++;
     int order[kMaxWindow];
     for (int w = 0; w < K; ++w) order[w] = w;
-    // low: window bits 0 .. S-1 start in the lane slots (in order), so that
-    // consecutive lanes load consecutive amplitudes; otherwise the bits that
-    // registers need least often start there
-    if (!low)
-        std::sort(order, order + K, [&](int x, int y) { return cost[x] != cost[y] ? cost[x] < cost[y] : x > y; });
+    std::sort(order, order + K, [&](int x, int y) { return cost[x] != cost[y] ? cost[x] < cost[y] : x > y; });
     int bit_at[kMaxWindow], slot_of[kMaxWindow];
     std::vector<int> regs;
     for (int j = 0; j < S; ++j) bit_at[KL + j] = order[j];

@@ -59,16 +59,16 @@ std::string prelude(bool dbl) {
     // (a, b): a' = a on lanes with the bit clear, b(lane - m) on lanes with it
     // set; b' = a(lane + m) on lanes with the bit clear, b on lanes with it set.
     // Lane bits 5 and 4: one v_permlane{32,16}_swap per dword.  Lane bits 3
-    // to 0: DPP row_ror:8 (lane ^ 8) or row_shr:m / row_shl:m (lane - m /
-    // lane + m within a row of 16, m = 4, 2, 1) and a per-lane select.
+    // and 2: DPP row_ror:8 (lane ^ 8) or row_shr:4 / row_shl:4 (lane - 4 /
+    // lane + 4 within a row of 16) and a per-lane select.
     o << "template <int LB> __device__ __forceinline__ void tp32(u32& a, u32& b) {\n"
       << "  if constexpr (LB == 5) { const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false); a = r[0]; "
          "b = r[1]; }\n"
       << "  else if constexpr (LB == 4) { const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false); a = "
          "r[0]; b = r[1]; }\n"
       << "  else {\n"
-      << "    constexpr int DN = LB == 3 ? 0x128 : (LB == 2 ? 0x114 : (LB == 1 ? 0x112 : 0x111));\n"
-      << "    constexpr int UP = LB == 3 ? 0x128 : (LB == 2 ? 0x104 : (LB == 1 ? 0x102 : 0x101));\n"
+      << "    constexpr int DN = LB == 3 ? 0x128 : 0x114;\n"
+      << "    constexpr int UP = LB == 3 ? 0x128 : 0x104;\n"
       << "    const bool hb = (threadIdx.x >> LB) & 1;\n"
       << "    const u32 bd = (u32)__builtin_amdgcn_update_dpp(0, (int)b, DN, 0xF, 0xF, false);\n"
       << "    const u32 au = (u32)__builtin_amdgcn_update_dpp(0, (int)a, UP, 0xF, 0xF, false);\n"
@@ -92,17 +92,12 @@ std::string prelude(bool dbl) {
 // Straight-line body generator.  loc[p] = variable holding register entry p.
 struct Gen {
     int K, S, NV, KL, N;
-    // low: the S lane slots sit in lane bits 0 .. S-1 (consecutive lanes take
-    // consecutive window patterns) and the cosets in the lane bits above;
-    // otherwise the slots sit in lane bits 6-S .. 5 and consecutive lanes take
-    // consecutive cosets.
-    bool low = false;
     std::vector<int> loc;
     std::ostringstream o;
     std::string R(int v, int p) const { return "r" + std::to_string(v) + "_" + std::to_string(loc[p]); }
     std::string I(int v, int p) const { return "i" + std::to_string(v) + "_" + std::to_string(loc[p]); }
     std::string H(int lane_slot) const { return "h" + std::to_string(lane_slot); }
-    int lane_bit(int lane_slot) const { return low ? lane_slot : 6 - S + lane_slot; }
+    int lane_bit(int lane_slot) const { return 6 - S + lane_slot; }
 
     void mats(int s, bool all) {
         o << "  { const T* m = mats[" << s << "].v;\n";
@@ -322,11 +317,10 @@ int jit_mode() { return g_mode.load(); }
 
 int jit_set_mode(int mode) { return g_mode.exchange(mode); }
 
-std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& ops, uint32_t n_gslots, bool low) {
+std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& ops, uint32_t n_gslots) {
     Gen g;
     g.K = K;
     g.S = S;
-    g.low = low && S > 0;
     g.NV = NV;
     g.KL = K - S;
     g.N = 1 << g.KL;
@@ -340,8 +334,7 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
          "const V* __restrict__ in0, V* __restrict__ out0, const V* __restrict__ in1, V* __restrict__ out1, "
          "double* __restrict__ gpart) {\n"
       << "  const int tid = threadIdx.x;\n  const int lane = tid & 63;\n"
-      << "  const int sub = (tid >> 6) * " << CPW << " + "
-      << (g.low ? "(lane >> " + std::to_string(S) + ")" : "(lane & " + std::to_string(CPW - 1) + ")") << ";\n"
+      << "  const int sub = (tid >> 6) * " << CPW << " + (lane & " << (CPW - 1) << ");\n"
       << "  u64 bitval[" << K << "], bv_in[" << K << "], bv_out[" << K << "];\n"
       << "#pragma unroll\n  for (int j = 0; j < " << K
       << "; ++j) { bitval[j] = 1ull << a.pos[j]; bv_in[j] = 1ull << a.pos_in[j]; bv_out[j] = 1ull << a.pos_out[j]; }\n"

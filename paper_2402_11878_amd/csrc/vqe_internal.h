@@ -201,9 +201,7 @@ int jit_set_mode(int mode);
 const char* jit_kernel_name(int NV, bool dbl);
 // HIP source of the specialised kernel of one pass: K window bits, S lane-split
 // bits, NV = 1 (forward) or 2 (reverse, psi and lam), ops on physical slots.
-// low: the lane slots sit in lane bits 0 .. S-1 (for windows holding qubits
-// 0 .. S-1, so that consecutive lanes read consecutive amplitudes).
-std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& ops, uint32_t n_gslots, bool low);
+std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& ops, uint32_t n_gslots);
 // Compiles (in parallel) and loads on the current device every source not yet
 // cached; fns[i] = kernel of srcs[i] (nullptr for an empty source).
 int jit_prepare(const std::vector<std::string>& srcs, std::vector<void*>& fns, std::string& err);
