@@ -234,8 +234,9 @@ def serving_bench(args, fracs=(0.5, 0.8, 0.95), baseline=True, emit=True):
     budget = int(args.budget_gib * (1 << 30))
 
     def new_server():
-        srv = Server(ex, budget, n_workers=args.workers, mid_n_max=args.mid_n_max if args.mid_workers else None,
-                     mid_workers=args.mid_workers)
+        srv = Server(ex, budget, n_workers=args.workers,
+                     mid_n_max=args.mid_n_max if (args.mid_workers or args.mid_batch) else None,
+                     mid_workers=args.mid_workers, mid_batch=bool(args.mid_batch))
         for d in insts:
             srv.add_instance(d["i"], d["n"], d["C"], d["H"])
         return srv
@@ -298,6 +299,8 @@ def serving_bench(args, fracs=(0.5, 0.8, 0.95), baseline=True, emit=True):
                                                         service_max_ms=max(svc_n[k]) * 1e3)
                                            for k, v in sorted(by_n.items())},
                                 batches=len(srv.batches), mean_batch=float(np.mean(srv.batches)) if srv.batches else 0,
+                                mid_batches=len(srv.mid_batches),
+                                mean_mid_batch=float(np.mean(srv.mid_batches)) if srv.mid_batches else 0,
                                 max_concurrent=srv.max_concurrent, evictions=srv.evictions)
         log(f"[serving] load {frac}: {loads[str(frac)]}")
         srv.close()
@@ -309,6 +312,7 @@ def serving_bench(args, fracs=(0.5, 0.8, 0.95), baseline=True, emit=True):
         "config": {"workload": f"{n_inst} instances: n in {{12,16,20,24,28}}, 1-D/2-D Hubbard and molecule-shaped "
                                f"(slimmed at {args.slim}) Hamiltonians, 4-16 layers, seeds 10000+i",
                    "workers": args.workers, "mid_workers": args.mid_workers, "mid_n_max": args.mid_n_max,
+                   "mid_batch": bool(args.mid_batch),
                    "reserve_cus": args.reserve_cus, "budget_gib": args.budget_gib, "requests_per_load": args.requests},
         "loads": loads,
     }
@@ -493,6 +497,91 @@ def dense_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_bench(args):
+    """Mid-size requests batched (vqe_batch_energy_grad: tile passes, one
+    launch per pass index for every item) against the same requests one at a
+    time on the per-request path (vqe_energy_grad, fused window passes),
+    complex64, for 14-24 qubits and batches of 1-16 items.  Items mix layer
+    counts (4-16) and Hamiltonians (Hubbard chains and molecule-shaped,
+    slimmed at --slim) as the served stream does.  Optionally restricted to
+    the first --reserve-cus compute units (the serving lane's stream)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2402_11878_amd import _lib as L, ansatz, hamiltonians as hm
+
+    sizes = [int(v) for v in args.batch_sizes.split(",")]
+    qubits = [int(v) for v in args.batch_qubits.split(",")]
+    if args.reserve_cus > 0 and args.batch_masked:
+        raw = L.vqe_stream_create(range(args.reserve_cus))
+        stream = torch.cuda.ExternalStream(raw)
+    else:
+        raw, stream = None, torch.cuda.current_stream()
+    out = {"mode": "batch", "dtype": "c64", "reps": args.reps,
+           "cus": args.reserve_cus if raw else torch.cuda.get_device_properties(0).multi_processor_count,
+           "note": "evals/s = items x reps / wall time of reps calls; per_request: the same items one at a time "
+                   "(vqe_energy_grad, psi and lam resident, no checkpoints)"}
+    with torch.cuda.stream(stream):
+        for n in qubits:
+            items = []
+            for i in range(max(sizes)):
+                layers = 4 + (3 * i) % 13
+                if i % 2 == 0:
+                    lat = synth.Lattice(n // 2, tuple(synth.chain_bonds(n // 2)), 1.0, 4.0)
+                    x, z, w = hm.from_lattice(lat)
+                else:
+                    h, g = synth.molecule_integrals(n // 2, 500 + i)
+                    x, z, w = hm.molecule(h, g)
+                    keep, _, _ = L.vqe_slim_hamiltonian(x, z, w, L.SLIM_THRESHOLD, args.slim)
+                    k = keep.astype(bool)
+                    x, z, w = x[k], z[k], w[k]
+                c = L.vqe_circuit_create(n, ansatz.layered(n, layers))
+                hh = L.vqe_hamiltonian_create(n, x, z, w)
+                th = np.random.default_rng(700 + i).uniform(-np.pi, np.pi, 2 * n * layers)
+                items.append((c, hh, th))
+            res = {}
+            b = L.vqe_batch_create(L.VQE_C64, stream.cuda_stream)
+            try:
+                for B in sizes:
+                    L.vqe_batch_energy_grad(b, items[:B])           # warm-up: buffers, table uploads
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(args.reps):
+                        L.vqe_batch_energy_grad(b, items[:B])
+                    dt = time.perf_counter() - t0
+                    res[str(B)] = {"evals_per_s": B * args.reps / dt, "ms_per_call": dt / args.reps * 1e3}
+            finally:
+                L.vqe_batch_free(b)
+            tdt = torch.complex64
+            bufs = [torch.empty(1 << n, dtype=tdt, device="cuda") for _ in range(2)]
+            hs = [L.vqe_state_alloc(n, L.VQE_C64, t.data_ptr(), t.numel() * 8, stream.cuda_stream) for t in bufs]
+            try:
+                B = max(sizes)
+                for c, hh, th in items[:B]:
+                    L.vqe_circuit_prepare(c, L.VQE_C64)
+                    L.vqe_energy_grad(hs[0], hs[1], c, th, hh)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.reps):
+                    for c, hh, th in items[:B]:
+                        L.vqe_energy_grad(hs[0], hs[1], c, th, hh)
+                dt = time.perf_counter() - t0
+                res["per_request"] = {"evals_per_s": B * args.reps / dt, "ms_per_eval": dt / (B * args.reps) * 1e3}
+            finally:
+                for h_ in hs:
+                    L.vqe_state_free(h_)
+                del bufs
+            for c, hh, _ in items:
+                L.vqe_circuit_free(c)
+                L.vqe_hamiltonian_free(hh)
+            out[str(n)] = res
+            log(f"[batch] n={n}: {res}")
+    if raw:
+        torch.cuda.synchronize()
+        L.vqe_stream_destroy(raw)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -506,11 +595,12 @@ def main():
     ap.add_argument("--skip-c64", action="store_true")
     ap.add_argument("--skip-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "serving", "copy", "dense", "energy"],
+    ap.add_argument("--mode", default="step", choices=["step", "serving", "copy", "dense", "energy", "batch"],
                     help="step: the 32-qubit energy+gradient step (default); serving: the served stream; "
                          "copy: a plain 8 GiB device copy (counter calibration); dense: a 5-qubit window "
                          "as a dense unitary on the matrix cores against the gate-by-gate window pass; "
-                         "energy: the grouped energy-only sweep of the workload")
+                         "energy: the grouped energy-only sweep of the workload; batch: mid-size requests "
+                         "batched against one at a time")
     ap.add_argument("--per-term", action="store_true", help="energy mode: also time the per-term form once")
     ap.add_argument("--specialize", default="auto", choices=["never", "auto", "always"],
                     help="kernel form of the window passes (vqe_set_specialize): interpreted 5-qubit windows "
@@ -524,6 +614,12 @@ def main():
     ap.add_argument("--mid-n-max", type=int, default=20, help="serving: largest qubit count of the mid-size lane")
     ap.add_argument("--reserve-cus", type=int, default=32,
                     help="serving: compute units reserved for the batched and mid-size lanes (0: none)")
+    ap.add_argument("--mid-batch", type=int, default=0,
+                    help="serving: 1 = the mid-size lane launches its queued requests together (tile passes)")
+    ap.add_argument("--batch-sizes", default="1,4,16", help="batch mode: items per call")
+    ap.add_argument("--batch-qubits", default="14,16,20,24", help="batch mode: qubit counts")
+    ap.add_argument("--batch-masked", type=int, default=0,
+                    help="batch mode: 1 = run on a stream restricted to the first --reserve-cus compute units")
     ap.add_argument("--no-serving", action="store_true", help="step mode: skip the short serving leg")
     ap.add_argument("--budget-gib", type=float, default=160.0)
     ap.add_argument("--slim", type=float, default=1e-3)
@@ -556,6 +652,9 @@ def main():
         return
     if args.mode == "dense":
         dense_bench(args)
+        return
+    if args.mode == "batch":
+        batch_bench(args)
         return
     if args.mode == "energy":
         energy_bench(args)

@@ -279,20 +279,32 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,
                     const double* params, size_t n_params, const vqe_hamiltonian* h,
                     const vqe_grad_opts* opts, double* energy, double* grad);
 
-/* ------------------------------------------------------------------ batched small states
+/* ------------------------------------------------------------------ batched states
  * Many independent energy + gradient evaluations (the independent circuit
- * runs of Sec. II-C, here from many optimiser instances) in one launch: one
- * workgroup per item holds psi and lam = H psi of the item in LDS and runs
- * the forward gates, the energy (eq. 7) and the adjoint reverse sweep.
- * Items may mix circuits, Hamiltonians and qubit counts; every item needs
- * n <= VQE_BATCH_MAX_QUBITS_C64 (complex64) or VQE_BATCH_MAX_QUBITS_C128
- * (complex128).  Each item's result depends only on that item (fixed
- * per-item work and reduction order), so it is bitwise the same alone or in
- * any batch.  A batch handle owns device and pinned staging buffers, grown on
- * demand, and runs on its stream; vqe_batch_energy_grad returns after the
- * results are on the host. */
+ * runs of Sec. II-C, here from many optimiser instances) in few launches.
+ * Items may mix circuits, Hamiltonians and qubit counts (n <=
+ * VQE_BATCH_MAX_QUBITS_MID).
+ *   Small items, n <= VQE_BATCH_MAX_QUBITS_C64 (complex64) or
+ *   VQE_BATCH_MAX_QUBITS_C128 (complex128): one launch, one workgroup per
+ *   item holding psi and lam = H psi in LDS, running the forward gates, the
+ *   energy (eq. 7) and the adjoint reverse sweep.
+ *   Mid-size items, above that up to VQE_BATCH_MAX_QUBITS_MID: psi and lam
+ *   in device memory owned by the batch handle (2 x 2^n amplitudes per
+ *   item); the gates are fused into passes over 10-qubit windows, and one
+ *   launch applies pass k of every item that has one, a workgroup staging
+ *   one 2^10-amplitude tile of a window in LDS at a time; then one launch
+ *   for lam = H psi and the energy of every item, the reverse passes
+ *   likewise, and one launch reducing per-block partial sums.
+ * Each item's result depends only on that item (fixed per-item work and
+ * reduction order), so it is bitwise the same alone or in any batch.  A
+ * batch handle owns device and pinned staging buffers, grown on demand to
+ * the largest call and held until vqe_batch_free, and runs on its stream;
+ * vqe_batch_energy_grad returns after the results are on the host.
+ * Errors: VQE_ERR_ARG (a null field, n above the limit, a Hamiltonian of
+ * another size, too few parameters), VQE_ERR_OOM (buffers). */
 #define VQE_BATCH_MAX_QUBITS_C64  13
 #define VQE_BATCH_MAX_QUBITS_C128 12
+#define VQE_BATCH_MAX_QUBITS_MID  24
 typedef struct vqe_batch vqe_batch;
 typedef struct vqe_batch_item {
     const vqe_circuit* circuit;

@@ -92,6 +92,15 @@ struct Plan {
     int jit_dev[2] = {-1, -1};      // device they are loaded on
 };
 
+// One pass of the mid-size batched form: a window of kMidWin qubits and its
+// gates (window-local qubits) in mid_gates[gate_off, gate_off + n_gates);
+// its parameterised gates, last first, own gradient slots
+// [slot_off, slot_off + n_slots) of mid_slot_pidx.
+struct MidPlanPass {
+    uint32_t pos[kMidWin];
+    uint32_t gate_off, n_gates, slot_off, n_slots;
+};
+
 struct vqe_circuit {
     int n = 0;
     std::vector<Gate> gates;
@@ -100,6 +109,10 @@ struct vqe_circuit {
     uint32_t n_mats = 0;            // matrices per evaluation (gates with a 2x2 matrix)
     Plan plan[2];  // [0]: interpreted (not built for circuits with excitation gates), [1]: specialised
     bool has_excitation = false;
+    // batched mid-size form (kMidWin < n <= kMidMaxQubits)
+    std::vector<MidPlanPass> mid;
+    std::vector<BatchGate> mid_gates;
+    std::vector<int32_t> mid_slot_pidx;
 };
 
 struct vqe_hamiltonian {
@@ -141,6 +154,11 @@ struct vqe_batch {
     size_t d_cap = 0;
     void* h_buf = nullptr;   // pinned staging of the same layout
     size_t h_cap = 0;
+    // mid-size items: tables | out | partial sums | states (device), tables | out (pinned)
+    void* md_buf = nullptr;
+    size_t md_cap = 0;
+    void* mh_buf = nullptr;
+    size_t mh_cap = 0;
 };
 
 namespace {
@@ -1082,6 +1100,53 @@ void free_circuit(vqe_circuit* c) {
     delete c;
 }
 
+// Tile passes of the batched mid-size form: the planner's windows of at most
+// kMidWin qubits, each padded to kMidWin with the lowest qubits outside it,
+// and the pass's gates rewritten to window-local qubits and patterns.
+int build_mid_plan(vqe_circuit* c) {
+    if (c->n <= kMidWin || c->n > kMidMaxQubits) return VQE_OK;
+    std::vector<PlannedPass> passes;
+    std::string msg;
+    if (!plan_passes(c->n, c->gates, kMidLimits, passes, msg)) {
+        set_error("vqe_circuit_create: " + msg);
+        return VQE_ERR_STATE;
+    }
+    if (passes.empty()) passes.emplace_back();  // no gates: one pass that only prepares |0...0>
+    for (const PlannedPass& p : passes) {
+        uint64_t w = 0;
+        for (int j = 0; j < p.K; ++j) w |= 1ull << p.pos[j];
+        for (int q = 0; __builtin_popcountll(w) < kMidWin; ++q) w |= 1ull << q;
+        MidPlanPass mp{};
+        int local[64] = {0};
+        int k = 0;
+        for (int q = 0; q < c->n; ++q)
+            if ((w >> q) & 1) {
+                local[q] = k;
+                mp.pos[k++] = (uint32_t)q;
+            }
+        mp.gate_off = (uint32_t)c->mid_gates.size();
+        mp.n_gates = (uint32_t)p.gates.size();
+        mp.slot_off = (uint32_t)c->mid_slot_pidx.size();
+        for (int gi : p.gates) {
+            const Gate& g = c->gates[gi];
+            BatchGate bg = c->bgates[gi];
+            bg.q0 = (uint8_t)local[g.q0];
+            bg.q1 = (uint8_t)local[g.q1];
+            if (is_excitation(g.kind)) {
+                const bool dbl = g.kind == VQE_GATE_DEXC;
+                bg.pa = (uint16_t)(dbl ? (1u << local[g.q0]) | (1u << local[g.q1]) : (1u << local[g.q0]));
+                bg.pb = (uint16_t)(dbl ? (1u << local[g.q2]) | (1u << local[g.q3]) : (1u << local[g.q1]));
+            }
+            c->mid_gates.push_back(bg);
+        }
+        for (size_t j = p.gates.size(); j-- > 0;)
+            if (c->gates[p.gates[j]].pidx >= 0) c->mid_slot_pidx.push_back(c->gates[p.gates[j]].pidx);
+        mp.n_slots = (uint32_t)c->mid_slot_pidx.size() - mp.slot_off;
+        c->mid.push_back(mp);
+    }
+    return VQE_OK;
+}
+
 // Plans fused passes within the given limits and lowers them to kernel op
 // lists (forward, and reverse with gradient ops), per dtype also to the
 // lane-split layout.
@@ -1342,6 +1407,184 @@ int batch_impl(vqe_batch* b, size_t n_items, const vqe_batch_item* items) {
     }
     return VQE_OK;
 }
+// Bytes of one state of n qubits in the mid-size buffer (256-byte aligned).
+size_t st_bytes_half(int n, size_t amp) { return align_up(((size_t)1 << n) * amp, 256); }
+
+// Grows a batch's mid-size buffers to at least dev / host bytes.
+int mid_reserve(vqe_batch* b, size_t dev, size_t host) {
+    if (dev <= b->md_cap && host <= b->mh_cap) return VQE_OK;
+    VQE_HIP(hipStreamSynchronize(b->stream));
+    if (dev > b->md_cap) {
+        if (b->md_buf) VQE_HIP(hipFree(b->md_buf));
+        b->md_buf = nullptr;
+        b->md_cap = 0;
+        const size_t cap = dev + dev / 4;
+        if (hipMalloc(&b->md_buf, cap) != hipSuccess) {
+            b->md_buf = nullptr;
+            set_error("vqe_batch_energy_grad: device allocation of " + std::to_string(cap) +
+                      " bytes for mid-size items failed");
+            return VQE_ERR_OOM;
+        }
+        b->md_cap = cap;
+    }
+    if (host > b->mh_cap) {
+        if (b->mh_buf) VQE_HIP(hipHostFree(b->mh_buf));
+        b->mh_buf = nullptr;
+        b->mh_cap = 0;
+        const size_t cap = std::max(host + host / 4, (size_t)1 << 20);
+        if (hipHostMalloc(&b->mh_buf, cap, hipHostMallocDefault) != hipSuccess) {
+            b->mh_buf = nullptr;
+            set_error("vqe_batch_energy_grad: pinned staging allocation failed");
+            return VQE_ERR_OOM;
+        }
+        b->mh_cap = cap;
+    }
+    return VQE_OK;
+}
+
+// Mid-size items (LDS limit < n <= kMidMaxQubits): forward tile passes, one
+// launch per pass index over every item that has that pass; lam = H psi over
+// tiles; reverse tile passes likewise; one reduction launch; results to the
+// host.  Per item: psi and lam in the batch's device buffer, n_blk =
+// min(2^(n - kMidWin), kMidMaxBlocks) blocks per launch.
+template <typename T>
+int mid_impl(vqe_batch* b, const vqe_batch_item* items, const std::vector<size_t>& idx) {
+    const size_t m = idx.size();
+    const size_t amp = 2 * sizeof(T);
+    std::vector<uint32_t> nblk(m);
+    std::vector<uint64_t> ncos(m), part_base(m), red_base(m), st_off(m), m_off(m);
+    size_t n_gates = 0, n_mats = 1, n_fwd = 0, n_part = 0, n_red = 0, st_bytes = 0;
+    size_t pmax = 0;
+    for (size_t k = 0; k < m; ++k) {
+        const vqe_circuit* c = items[idx[k]].circuit;
+        ncos[k] = 1ull << (c->n - kMidWin);
+        nblk[k] = (uint32_t)std::min<uint64_t>(ncos[k], kMidMaxBlocks);
+        part_base[k] = n_part;
+        n_part += (2 + c->mid_slot_pidx.size()) * (size_t)nblk[k];
+        red_base[k] = n_red;
+        n_red += 2 + c->mid_slot_pidx.size();
+        st_off[k] = st_bytes;
+        st_bytes += 2 * align_up(((size_t)1 << c->n) * amp, 256);
+        m_off[k] = n_mats;
+        n_gates += c->mid_gates.size();
+        n_mats += c->n_mats;
+        n_fwd += c->mid.size();
+        pmax = std::max(pmax, c->mid.size());
+        if (int rc = upload_hamiltonian(items[idx[k]].hamiltonian)) return rc;
+    }
+    // host-written tables | out, then (device only) partial sums | states
+    const size_t o_fwd = 0;
+    const size_t o_rev = align_up(o_fwd + n_fwd * sizeof(MidPass), 256);
+    const size_t o_ham = align_up(o_rev + n_fwd * sizeof(MidPass), 256);
+    const size_t o_red = align_up(o_ham + m * sizeof(MidHam), 256);
+    const size_t o_gates = align_up(o_red + n_red * sizeof(MidRed), 256);
+    const size_t o_mats = align_up(o_gates + std::max<size_t>(n_gates, 1) * sizeof(BatchGate), 256);
+    const size_t o_out = align_up(o_mats + (n_mats + 1) * sizeof(Mat2<T>), 256);  // + a zero matrix at the end
+    const size_t o_part = align_up(o_out + n_red * sizeof(double), 256);
+    const size_t o_st = align_up(o_part + n_part * sizeof(double), 256);
+    if (int rc = mid_reserve(b, o_st + st_bytes, o_part)) return rc;
+    char* h = (char*)b->mh_buf;
+    char* d = (char*)b->md_buf;
+    auto* hf = (MidPass*)(h + o_fwd);
+    auto* hr = (MidPass*)(h + o_rev);
+    auto* hh = (MidHam*)(h + o_ham);
+    auto* hred = (MidRed*)(h + o_red);
+    auto* hg = (BatchGate*)(h + o_gates);
+    auto* hm = (Mat2<T>*)(h + o_mats);
+    std::memset(&hm[0], 0, sizeof(Mat2<T>));
+    std::memset(&hm[n_mats], 0, sizeof(Mat2<T>));
+    double* part = (double*)(d + o_part);
+    // gates, matrices, H psi and reduction descriptors per item
+    size_t g_off = 0;
+    uint32_t hblk = 0;
+    for (size_t k = 0; k < m; ++k) {
+        const vqe_batch_item& it = items[idx[k]];
+        const vqe_circuit* c = it.circuit;
+        std::copy(c->mid_gates.begin(), c->mid_gates.end(), hg + g_off);
+        for (size_t i = 0; i < c->gates.size(); ++i)
+            if (c->bgates[i].type == OP_U2 || c->bgates[i].type == OP_PAIR2)
+                fill_matrix(hm[m_off[k] + c->bgates[i].mat], c->gates[i], angle_of(c->gates[i], it.params), false);
+        MidHam mh{};
+        mh.psi = d + o_st + st_off[k];
+        mh.lam = d + o_st + st_off[k] + st_bytes_half(c->n, amp);
+        mh.groups = it.hamiltonian->d_groups;
+        mh.terms = terms_of<T>(it.hamiltonian);
+        mh.n_tiles = ncos[k];
+        mh.part_off = part_base[k];
+        mh.n_groups = (uint32_t)it.hamiltonian->groups.size();
+        mh.blk_begin = hblk;
+        mh.n_blk = nblk[k];
+        hh[k] = mh;
+        hblk += nblk[k];
+        const uint64_t nb = nblk[k];
+        hred[red_base[k]] = MidRed{part_base[k], nblk[k], 0};
+        hred[red_base[k] + 1] = MidRed{part_base[k] + nb, nblk[k], 0};
+        for (size_t sl = 0; sl < c->mid_slot_pidx.size(); ++sl)
+            hred[red_base[k] + 2 + sl] = MidRed{part_base[k] + (2 + sl) * nb, nblk[k], 0};
+        g_off += c->mid_gates.size();
+    }
+    // pass descriptors, grouped by launch
+    std::vector<size_t> l_off(pmax), l_cnt(pmax);
+    std::vector<uint32_t> l_grid(pmax);
+    size_t e = 0;
+    for (size_t p = 0; p < pmax; ++p) {
+        l_off[p] = e;
+        uint32_t blk = 0;
+        size_t gbase = 0;
+        for (size_t k = 0; k < m; ++k) {
+            const vqe_circuit* c = items[idx[k]].circuit;
+            const size_t P = c->mid.size();
+            if (p < P) {
+                for (int dir = 0; dir < 2; ++dir) {
+                    const MidPlanPass& mp = c->mid[dir ? P - 1 - p : p];
+                    MidPass x{};
+                    x.psi = d + o_st + st_off[k];
+                    x.lam = d + o_st + st_off[k] + st_bytes_half(c->n, amp);
+                    x.n_cosets = ncos[k];
+                    x.part_off = part_base[k] + (2 + (uint64_t)mp.slot_off) * nblk[k];
+                    for (int j = 0; j < kMidWin; ++j) x.pos[j] = mp.pos[j];
+                    x.gate_off = (uint32_t)(gbase + mp.gate_off);
+                    x.n_gates = mp.n_gates;
+                    x.mat_off = (uint32_t)m_off[k];
+                    x.n_slots = mp.n_slots;
+                    x.blk_begin = blk;
+                    x.n_blk = nblk[k];
+                    x.first = (dir == 0 && p == 0) ? 1u : 0u;
+                    (dir ? hr : hf)[e] = x;
+                }
+                blk += nblk[k];
+                ++e;
+            }
+            gbase += c->mid_gates.size();
+        }
+        l_cnt[p] = e - l_off[p];
+        l_grid[p] = blk;
+    }
+    VQE_HIP(hipMemcpyAsync(d, h, o_out, hipMemcpyHostToDevice, b->stream));
+    const auto* dg = (const BatchGate*)(d + o_gates);
+    const auto* dm = (const Mat2<T>*)(d + o_mats);
+    for (size_t p = 0; p < pmax; ++p)
+        VQE_HIP(launch_mid_pass<T>((const MidPass*)(d + o_fwd) + l_off[p], (uint32_t)l_cnt[p], l_grid[p], false, dg,
+                                   dm, part, b->stream));
+    VQE_HIP(launch_mid_hpsi<T>((const MidHam*)(d + o_ham), (uint32_t)m, hblk, part, b->stream));
+    for (size_t p = 0; p < pmax; ++p)
+        VQE_HIP(launch_mid_pass<T>((const MidPass*)(d + o_rev) + l_off[p], (uint32_t)l_cnt[p], l_grid[p], true, dg,
+                                   dm, part, b->stream));
+    VQE_HIP(launch_mid_reduce((const MidRed*)(d + o_red), (uint32_t)n_red, part, (double*)(d + o_out), b->stream));
+    VQE_HIP(hipMemcpyAsync(h + o_out, d + o_out, n_red * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    VQE_HIP(hipStreamSynchronize(b->stream));
+    const double* r = (const double*)(h + o_out);
+    for (size_t k = 0; k < m; ++k) {
+        const vqe_batch_item& it = items[idx[k]];
+        const vqe_circuit* c = it.circuit;
+        const double* o = r + red_base[k];
+        const double nrm = o[1];
+        *it.energy = o[0] / nrm;
+        for (size_t q = 0; q < c->n_params; ++q) it.grad[q] = 0.0;
+        for (size_t sl = 0; sl < c->mid_slot_pidx.size(); ++sl) it.grad[c->mid_slot_pidx[sl]] += o[2 + sl] / nrm;
+    }
+    return VQE_OK;
+}
 }  // namespace
 
 // ================================================================ exported
@@ -1577,6 +1820,10 @@ int vqe_circuit_create(int n_qubits, const vqe_gate* gates, size_t n_gates, vqe_
             free_circuit(c);
             return rc;
         }
+    }
+    if (int rc = build_mid_plan(c)) {
+        free_circuit(c);
+        return rc;
     }
     *out = c;
     return VQE_OK;
@@ -1923,6 +2170,8 @@ int vqe_batch_free(vqe_batch* b) {
     (void)hipStreamSynchronize(b->stream);
     if (b->d_buf) (void)hipFree(b->d_buf);
     if (b->h_buf) (void)hipHostFree(b->h_buf);
+    if (b->md_buf) (void)hipFree(b->md_buf);
+    if (b->mh_buf) (void)hipHostFree(b->mh_buf);
     delete b;
     return VQE_OK;
 }
@@ -1939,7 +2188,34 @@ int vqe_batch_energy_grad(vqe_batch* b, size_t n_items, const vqe_batch_item* it
         return VQE_ERR_ARG;
     }
     VQE_HIP(hipSetDevice(b->device));
-    return b->dtype == VQE_C64 ? batch_impl<float>(b, n_items, items) : batch_impl<double>(b, n_items, items);
+    // Items up to the LDS limit go to the small-state kernel, larger ones up
+    // to kMidMaxQubits to the tile passes; every item is checked first.
+    const int max_small = b->dtype == VQE_C64 ? kBatchMaxQubitsC64 : kBatchMaxQubitsC128;
+    std::vector<vqe_batch_item> small;
+    std::vector<size_t> mid;
+    for (size_t i = 0; i < n_items; ++i) {
+        const vqe_batch_item& it = items[i];
+        if (!it.circuit || !it.hamiltonian || !it.energy || (it.n_params && (!it.params || !it.grad))) {
+            set_error("vqe_batch_energy_grad: item " + std::to_string(i) + " has a null field");
+            return VQE_ERR_ARG;
+        }
+        const int n = it.circuit->n;
+        if (n > kMidMaxQubits || it.hamiltonian->n != n) {
+            set_error("vqe_batch_energy_grad: item " + std::to_string(i) + " has " + std::to_string(n) +
+                      " qubits (limit " + std::to_string(kMidMaxQubits) + ") or a Hamiltonian of another size");
+            return VQE_ERR_ARG;
+        }
+        if (int rc = check_params(it.circuit, it.params, it.n_params, "vqe_batch_energy_grad")) return rc;
+        if (n <= max_small) small.push_back(it);
+        else mid.push_back(i);
+    }
+    if (!small.empty()) {
+        const int rc = b->dtype == VQE_C64 ? batch_impl<float>(b, small.size(), small.data())
+                                           : batch_impl<double>(b, small.size(), small.data());
+        if (rc) return rc;
+    }
+    if (!mid.empty()) return b->dtype == VQE_C64 ? mid_impl<float>(b, items, mid) : mid_impl<double>(b, items, mid);
+    return VQE_OK;
     VQE_GUARD_END
 }
 

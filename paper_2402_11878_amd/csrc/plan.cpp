@@ -90,7 +90,7 @@ int popcount64(uint64_t v) { return __builtin_popcountll(v); }
 bool plan_passes(int n, const std::vector<Gate>& gates, const PlanLimits& lim, std::vector<PlannedPass>& out,
                  std::string& msg) {
     out.clear();
-    const int K = std::min(n, std::min(lim.kmax, kMaxWindow));
+    const int K = std::min(n, std::min(lim.kmax, kMaxPlanWindow));
     PlanState ps;
     ps.n = n;
     ps.lim = &lim;

@@ -25,6 +25,7 @@ constexpr int kBlock = 256;       // threads per block of every streaming kernel
 constexpr int kMaxBlocks = 2048;  // grid-stride kernels use at most this many blocks
 constexpr int kMaxPartBlocks = 1 << 17;  // blocks writing per-block partial sums
 constexpr int kTileBits = 10;     // amplitudes per Hamiltonian tile = 2^kTileBits
+constexpr int kMaxPlanWindow = 10;  // largest window the planner forms (mid-size tile passes)
 
 // Per-pass limits of the fusion planner.
 struct PlanLimits {
@@ -168,6 +169,64 @@ template <typename T>
 hipError_t launch_batch(const BatchDesc<T>* items, uint32_t n_items, const BatchGate* gates, const Mat2<T>* mats,
                         double* out, int max_n, hipStream_t st);
 hipError_t batch_set_lds_limit();
+
+// ---------------------------------------------------------------- batched mid-size states (batch.hip)
+// Items above the LDS limit, up to kMidMaxQubits: psi and lam stay in device
+// memory (up to 256 MiB per state in complex64, held in the last-level cache
+// between passes at the small end), and one launch applies one fused pass of
+// every item of the batch.  A pass is a window of kMidWin qubits (padded
+// with the lowest qubits outside it, so a tile's loads run over consecutive
+// amplitudes); a block stages a coset of 2^kMidWin amplitudes in LDS, applies
+// the pass's gates there one at a time and writes it back.
+constexpr int kMidWin = 10;
+constexpr int kMidMaxQubits = 24;
+constexpr int kMidMaxSlots = 64;          // parameterised gates per pass
+constexpr uint32_t kMidMaxBlocks = 1024;  // blocks per item and launch
+constexpr PlanLimits kMidLimits = {kMidWin, 1024, 1024, kMidMaxSlots};
+static_assert(kMidWin <= kMaxPlanWindow, "planner window");
+static_assert(kMidMaxQubits == VQE_BATCH_MAX_QUBITS_MID, "public and internal mid-size limits differ");
+
+// One item's pass in one launch.  Blocks [blk_begin, blk_begin + n_blk) of
+// the launch take cosets blk, blk + n_blk, ...; in a reverse pass block blk
+// writes gradient slot s (the pass's parameterised gates, last gate first)
+// to part[part_off + s n_blk + blk].
+struct MidPass {
+    void* psi;
+    void* lam;
+    uint64_t n_cosets;
+    uint64_t part_off;
+    uint32_t pos[kMidWin];  // window qubits, ascending
+    uint32_t gate_off, n_gates, mat_off, n_slots;
+    uint32_t blk_begin, n_blk;
+    uint32_t first;         // forward pass 0: stage |0...0> instead of reading psi
+    uint32_t pad;
+};
+
+// lam = H psi of one item over tiles of 2^kMidWin amplitudes; block blk
+// writes its energy and norm partials to part[part_off + blk] and
+// part[part_off + n_blk + blk].
+struct MidHam {
+    const void* psi;
+    void* lam;
+    const GroupDesc* groups;
+    const void* terms;      // TermDesc<T>
+    uint64_t n_tiles;
+    uint64_t part_off;
+    uint32_t n_groups, blk_begin, n_blk, pad;
+};
+
+// out[k] = sum of part[part_off .. part_off + count) in a fixed order.
+struct MidRed {
+    uint64_t part_off;
+    uint32_t count, pad;
+};
+
+template <typename T>
+hipError_t launch_mid_pass(const MidPass* d, uint32_t n_desc, uint32_t grid, bool rev, const BatchGate* gates,
+                           const Mat2<T>* mats, double* part, hipStream_t st);
+template <typename T>
+hipError_t launch_mid_hpsi(const MidHam* d, uint32_t n_desc, uint32_t grid, double* part, hipStream_t st);
+hipError_t launch_mid_reduce(const MidRed* r, uint32_t n, const double* part, double* out, hipStream_t st);
 
 // ---------------------------------------------------------------- launchers (kernels.hip)
 hipError_t launch_set_basis(int dtype, void* psi, uint64_t dim, uint64_t b, hipStream_t st);
@@ -339,12 +398,12 @@ inline int gate_qubits(const Gate& g, int q[4]) {
 
 struct PlannedPass {
     int K = 0;
-    int pos[kMaxWindow] = {0};
+    int pos[kMaxPlanWindow] = {0};
     std::vector<int> gates;      // indices into the circuit's gate list, execution order
 };
 
 // Partition gates into fused passes.  Returns false (with msg) on failure.
-// lim.kmax = largest window (<= kMaxWindow).
+// lim.kmax = largest window (<= kMaxPlanWindow).
 bool plan_passes(int n, const std::vector<Gate>& gates, const PlanLimits& lim, std::vector<PlannedPass>& out,
                  std::string& msg);
 

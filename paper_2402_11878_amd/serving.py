@@ -12,11 +12,14 @@ node groups (Sec. II-C).  Here they share one GPU:
     with its state vectors (psi, lam, checkpoints) resident in HBM, so
     several instances' kernels overlap on the device;
   * optionally, mid-size requests (up to `mid_n_max` qubits) form a lane of
-    their own with dedicated workers, so that they never queue behind large
-    ones on the host; the GPU executor can also reserve a few compute units
-    for the batched and mid-size lanes (streams with CU masks), so that their
-    short kernels do not wait for the compute units that the persistent
-    kernels of large requests hold;
+    their own, so that they never queue behind large ones on the host:
+    either dedicated workers running them one at a time, or (`mid_batch`) a
+    second batch loop that launches every queued mid-size request together
+    (the tile passes of vqe_batch_energy_grad, one launch per pass index);
+    the GPU executor can also reserve a few compute units for the batched
+    and mid-size lanes (streams with CU masks), so that their short kernels
+    do not wait for the compute units that the persistent kernels of large
+    requests hold;
   * an instance becomes resident only while the summed footprint of resident
     instances stays within the HBM budget; idle resident instances are
     evicted least-recently-used first;
@@ -78,10 +81,11 @@ def percentile(values, q):
 
 class Server:
     def __init__(self, executor, budget_bytes, n_workers=4, max_batch=64, max_wait=2.0, clock=time.perf_counter,
-                 mid_n_max=None, mid_workers=1):
+                 mid_n_max=None, mid_workers=1, mid_batch=False):
         self.ex = executor
         # requests of more than the batch limit and at most mid_n_max qubits go to the mid lane
-        self.mid_n_max = mid_n_max if (mid_n_max is not None and mid_workers > 0) else None
+        self.mid_n_max = mid_n_max if (mid_n_max is not None and (mid_workers > 0 or mid_batch)) else None
+        self.mid_batch = bool(mid_batch) and self.mid_n_max is not None
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
         self.max_wait = max_wait
@@ -95,14 +99,19 @@ class Server:
         self._mid = collections.deque()
         self._closing = False
         self.completed = []
-        self.batches = []          # sizes of the launched batches
+        self.batches = []          # sizes of the launched batches of small requests
+        self.mid_batches = []      # ... of mid-size requests (mid_batch)
         self.evictions = 0         # resident instances released to admit others
         self.max_concurrent = 0
         self._running = 0
-        self._threads = [threading.Thread(target=self._batch_loop, daemon=True)]
+        self._threads = [threading.Thread(target=self._batch_loop, args=(self._small, self.ex.run_batch,
+                                                                         self.batches), daemon=True)]
         self._threads += [threading.Thread(target=self._worker_loop, args=(self._large,), daemon=True)
                           for _ in range(n_workers)]
-        if self.mid_n_max is not None:
+        if self.mid_batch:
+            self._threads.append(threading.Thread(target=self._batch_loop, args=(self._mid, self.ex.run_mid_batch,
+                                                                                self.mid_batches), daemon=True))
+        elif self.mid_n_max is not None:
             self._threads += [threading.Thread(target=self._worker_loop, args=(self._mid,), daemon=True)
                               for _ in range(mid_workers)]
         for t in self._threads:
@@ -111,11 +120,11 @@ class Server:
     # ------------------------------------------------------------ client side
     def add_instance(self, iid, n, circuit, hamiltonian):
         inst = Instance(iid, n, circuit, hamiltonian)
-        inst.footprint = self.ex.footprint(inst)
-        if not self.ex.is_small(inst) and inst.footprint > self.budget:
+        inst.footprint = 0 if self._batched(inst) else self.ex.footprint(inst)
+        if not self._batched(inst) and inst.footprint > self.budget:
             raise ValueError(f"instance {iid} needs {inst.footprint} bytes, more than the budget {self.budget}")
         prepare = getattr(self.ex, "prepare", None)
-        if prepare is not None:
+        if prepare is not None and not self._batched(inst):
             prepare(inst)  # kernel compilation stays out of the instance's first request
         with self._cv:
             self.instances[iid] = inst
@@ -155,6 +164,10 @@ class Server:
             return self._mid
         return self._large
 
+    def _batched(self, inst):
+        """Served by a batch launch (no resident state of its own)."""
+        return self.ex.is_small(inst) or (self.mid_batch and inst.n <= self.mid_n_max)
+
     def latencies(self):
         return [r.done_t - r.submit_t for r in self.completed]
 
@@ -168,22 +181,24 @@ class Server:
         else:
             req.future.set_result(result)
 
-    def _batch_loop(self):
+    def _batch_loop(self, queue, run, sizes):
+        """Launches everything queued (up to max_batch) as one batch, again and
+        again; requests queued meanwhile form the next batch."""
         while True:
             with self._cv:
-                while not self._small and not self._closing:
+                while not queue and not self._closing:
                     self._cv.wait()
-                if not self._small and self._closing:
+                if not queue and self._closing:
                     return
-                batch = [self._small.popleft() for _ in range(min(self.max_batch, len(self._small)))]
+                batch = [queue.popleft() for _ in range(min(self.max_batch, len(queue)))]
                 t_start = self.clock()
                 for r in batch:
                     r.start_t = t_start
                 self._running += 1
                 self.max_concurrent = max(self.max_concurrent, self._running)
-            self.batches.append(len(batch))
+            sizes.append(len(batch))
             try:
-                results = self.ex.run_batch([(r.inst, r.theta) for r in batch])
+                results = run([(r.inst, r.theta) for r in batch])
             except Exception as e:  # the whole launch failed: fail its requests, keep serving
                 results = [e] * len(batch)
             with self._cv:
@@ -262,9 +277,11 @@ class GpuExecutor:
     fused-pass adjoint path on per-instance streams for large ones.
 
     reserve_cus > 0 splits the compute units: the batched launches and the
-    instances of at most mid_n_max qubits run on one stream restricted to
-    the first reserve_cus compute units, larger instances on big_streams
-    streams restricted to the others (vqe_stream_create with a CU mask)."""
+    instances of at most mid_n_max qubits run on streams restricted to the
+    first reserve_cus compute units, larger instances on big_streams
+    streams restricted to the others (vqe_stream_create with a CU mask).
+    Batched mid-size requests (run_mid_batch) have a batch handle and stream
+    of their own."""
 
     def __init__(self, dtype="c64", n_ckpt=0, small_n_max=None, reserve_cus=0, mid_n_max=20, big_streams=3):
         import torch
@@ -285,16 +302,20 @@ class GpuExecutor:
             if not 0 < reserve_cus < ncu:
                 raise ValueError(f"reserve_cus must be in (0, {ncu})")
             fast = _lib.vqe_stream_create(range(reserve_cus))
+            fast2 = _lib.vqe_stream_create(range(reserve_cus))
             big = [_lib.vqe_stream_create(range(reserve_cus, ncu)) for _ in range(big_streams)]
-            self._own_streams = [fast] + big
+            self._own_streams = [fast, fast2] + big
             self.batch_stream = torch.cuda.ExternalStream(fast)
             self.fast_stream = self.batch_stream
+            self.mid_stream = torch.cuda.ExternalStream(fast2)
             self.big_streams = [torch.cuda.ExternalStream(b) for b in big]
         else:
             self.batch_stream = torch.cuda.Stream()
+            self.mid_stream = torch.cuda.Stream()
             self.fast_stream = None
             self.big_streams = []
         self.batch = _lib.vqe_batch_create(self.dtype, self.batch_stream.cuda_stream)
+        self.mid_batch = _lib.vqe_batch_create(self.dtype, self.mid_stream.cuda_stream)
 
     def _stream_for(self, inst):
         if self.fast_stream is None:
@@ -338,10 +359,17 @@ class GpuExecutor:
         return self.L.vqe_batch_energy_grad(
             self.batch, [(inst.circuit.handle, inst.hamiltonian.handle, th) for inst, th in items])
 
+    def run_mid_batch(self, items):
+        return self.L.vqe_batch_energy_grad(
+            self.mid_batch, [(inst.circuit.handle, inst.hamiltonian.handle, th) for inst, th in items])
+
     def close(self):
         if self.batch:
             self.L.vqe_batch_free(self.batch)
             self.batch = None
+        if self.mid_batch:
+            self.L.vqe_batch_free(self.mid_batch)
+            self.mid_batch = None
         if self._own_streams:
             self.torch.cuda.synchronize()
             for st in self._own_streams:

@@ -73,9 +73,9 @@ def test_batch_matches_oracle_and_is_order_independent(handles, dt):
         _lib.vqe_batch_free(b)
 
 
-def test_batch_rejects_large_states():
+def test_batch_rejects_states_above_the_mid_size_limit():
     import torch
-    n = 14
+    n = _lib.BATCH_MAX_QUBITS_MID + 1
     c = _lib.vqe_circuit_create(n, ansatz.layered(n, 1))
     h = _lib.vqe_hamiltonian_create(n, np.array([0], np.uint64), np.array([1], np.uint64), np.array([1.0]))
     b = _lib.vqe_batch_create(_lib.VQE_C64, torch.cuda.current_stream().cuda_stream)

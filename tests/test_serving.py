@@ -64,6 +64,13 @@ class MockExecutor:
                 out.append(e)
         return out
 
+    def run_mid_batch(self, items):
+        for inst, _ in items:
+            assert inst.state is None and not self.is_small(inst)  # batched: no resident buffers
+        with self.lock:
+            self.mid_sizes = getattr(self, "mid_sizes", []) + [len(items)]
+        return self.run_batch(items)
+
 
 def _server(ex, budget, **kw):
     return Server(ex, budget, **kw)
@@ -209,3 +216,24 @@ def test_mid_lane_is_not_blocked_by_large_requests():
     assert not fl.done()            # the mid request finished while the large one still ran
     fl.result(timeout=10)
     srv.close()
+
+
+def test_mid_batch_lane_batches_queued_mid_requests():
+    """With mid_batch, queued mid-size requests are launched together by a
+    batch loop of their own: no resident state, no footprint, one launch
+    for a burst; small and large requests keep their own paths."""
+    budget = 3 * 8 * (1 << 24)            # one 24-qubit instance
+    ex = MockExecutor(budget, dur=0.05)
+    srv = _server(ex, budget, n_workers=1, mid_n_max=20, mid_batch=True)
+    sizes = [12, 16, 16, 18, 20, 20, 24]
+    for i, n in enumerate(sizes):
+        srv.add_instance(i, n, None, None)
+    items = [(i, np.full(2, float(10 * i + k))) for k in range(2) for i in range(len(sizes))]
+    futs = srv.submit_many(items)
+    for (i, th), f in zip(items, futs):
+        assert f.result(timeout=20)[0] == 2 * th[0]
+    srv.close()
+    assert sum(srv.mid_batches) == 2 * 5 and max(srv.mid_batches) >= 2
+    assert ex.mid_sizes == srv.mid_batches
+    assert all(srv.instances[i].footprint == 0 for i in range(5))
+    assert srv.instances[6].footprint > 0 and srv.peak_used <= budget and ex.resident == 0
