@@ -230,13 +230,15 @@ def serving_bench(args, fracs=(0.5, 0.8, 0.95), baseline=True, emit=True):
                           H=Hamiltonian(n, x, z, w)))
     log(f"[serving] {n_inst} instances built")
     t_build = time.perf_counter()
-    ex = GpuExecutor("c64", n_ckpt=0, reserve_cus=args.reserve_cus, mid_n_max=args.mid_n_max)
+    ex = GpuExecutor("c64", n_ckpt=0, reserve_cus=args.reserve_cus, mid_n_max=args.mid_n_max,
+                     chunk_passes=args.chunk_passes)
     budget = int(args.budget_gib * (1 << 30))
 
     def new_server():
         srv = Server(ex, budget, n_workers=args.workers,
                      mid_n_max=args.mid_n_max if (args.mid_workers or args.mid_batch) else None,
-                     mid_workers=args.mid_workers, mid_batch=bool(args.mid_batch))
+                     mid_workers=args.mid_workers, mid_batch=bool(args.mid_batch),
+                     mid_batch_n_max=args.mid_batch_n_max or None)
         for d in insts:
             srv.add_instance(d["i"], d["n"], d["C"], d["H"])
         return srv
@@ -312,7 +314,8 @@ def serving_bench(args, fracs=(0.5, 0.8, 0.95), baseline=True, emit=True):
         "config": {"workload": f"{n_inst} instances: n in {{12,16,20,24,28}}, 1-D/2-D Hubbard and molecule-shaped "
                                f"(slimmed at {args.slim}) Hamiltonians, 4-16 layers, seeds 10000+i",
                    "workers": args.workers, "mid_workers": args.mid_workers, "mid_n_max": args.mid_n_max,
-                   "mid_batch": bool(args.mid_batch),
+                   "mid_batch": bool(args.mid_batch), "mid_batch_n_max": args.mid_batch_n_max or None,
+                   "chunk_passes": args.chunk_passes,
                    "reserve_cus": args.reserve_cus, "budget_gib": args.budget_gib, "requests_per_load": args.requests},
         "loads": loads,
     }
@@ -612,10 +615,15 @@ def main():
     ap.add_argument("--mid-workers", type=int, default=1,
                     help="serving: workers of the mid-size lane (0: mid-size requests share the large workers)")
     ap.add_argument("--mid-n-max", type=int, default=20, help="serving: largest qubit count of the mid-size lane")
-    ap.add_argument("--reserve-cus", type=int, default=32,
+    ap.add_argument("--reserve-cus", type=int, default=0,
                     help="serving: compute units reserved for the batched and mid-size lanes (0: none)")
-    ap.add_argument("--mid-batch", type=int, default=0,
+    ap.add_argument("--mid-batch", type=int, default=1,
                     help="serving: 1 = the mid-size lane launches its queued requests together (tile passes)")
+    ap.add_argument("--mid-batch-n-max", type=int, default=16,
+                    help="serving with --mid-batch 1: largest qubit count batched (larger mid-size requests go "
+                         "to the mid-size workers; 0: all of them batched)")
+    ap.add_argument("--chunk-passes", type=int, default=3,
+                    help="serving: submit large evaluations in chunks of this many window passes (0: at once)")
     ap.add_argument("--batch-sizes", default="1,4,16", help="batch mode: items per call")
     ap.add_argument("--batch-qubits", default="14,16,20,24", help="batch mode: qubit counts")
     ap.add_argument("--batch-masked", type=int, default=0,

@@ -120,7 +120,13 @@ typedef struct vqe_grad_opts {
     int32_t method;        /* VQE_GRAD_ADJOINT or VQE_GRAD_PARAM_SHIFT */
     int32_t expect_mode;   /* energy evaluation used by PARAM_SHIFT: VQE_EXPECT_* */
     int32_t n_ckpt;        /* number of checkpoint states in ckpt (ADJOINT only; may be 0) */
-    int32_t reserved;
+    int32_t chunk_passes;  /* ADJOINT: > 0 waits for the state's stream after every chunk_passes
+                              window passes of the forward and reverse sweeps (one ansatz layer
+                              is about passes / layers), so that at most that many passes of
+                              this evaluation are queued on the device at a time and work that
+                              other threads submit on other streams starts within one chunk;
+                              0 queues the whole evaluation at once; < 0 is VQE_ERR_ARG.
+                              Results do not depend on it. */
     vqe_state* const* ckpt;/* n_ckpt states of the same n and dtype as psi; their
                               contents are overwritten */
 } vqe_grad_opts;

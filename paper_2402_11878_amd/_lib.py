@@ -42,7 +42,7 @@ class vqe_gate(C.Structure):
 
 class vqe_grad_opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("expect_mode", C.c_int32), ("n_ckpt", C.c_int32),
-                ("reserved", C.c_int32), ("ckpt", C.POINTER(C.c_void_p))]
+                ("chunk_passes", C.c_int32), ("ckpt", C.POINTER(C.c_void_p))]
 
 
 class vqe_batch_item(C.Structure):
@@ -268,11 +268,11 @@ def vqe_apply_hamiltonian(psi, lam, h):
     return e.value, n.value
 
 
-def vqe_energy_grad(psi, lam, c, params, h, method=GRAD_ADJOINT, expect_mode=EXPECT_GROUPED, ckpt=()):
+def vqe_energy_grad(psi, lam, c, params, h, method=GRAD_ADJOINT, expect_mode=EXPECT_GROUPED, ckpt=(), chunk_passes=0):
     p, pp = _arr(params, np.float64, C.c_double)
     g = np.zeros(len(p), dtype=np.float64)
     arr = (C.c_void_p * max(len(ckpt), 1))(*ckpt)
-    opts = vqe_grad_opts(method, expect_mode, len(ckpt), 0, C.cast(arr, C.POINTER(C.c_void_p)))
+    opts = vqe_grad_opts(method, expect_mode, len(ckpt), int(chunk_passes), C.cast(arr, C.POINTER(C.c_void_p)))
     e = C.c_double()
     check("vqe_energy_grad", lib().vqe_energy_grad(psi, lam, c, pp, len(p), h, C.byref(opts), C.byref(e),
                                                    g.ctypes.data_as(C.POINTER(C.c_double))))

@@ -478,7 +478,9 @@ void plan_hwin(vqe_hamiltonian* h) {
     const size_t m = passes.size();
     h->hw_lam = 3 * m - 1 < D + 2;
     h->hw_energy = 2 * m < 2 + D;
-    if (!h->hw_lam && !h->hw_energy) return;
+    // batched mid-size states use the window passes whenever a cover exists
+    // (their states stay in cache, so arithmetic, not bytes, decides)
+    if (!h->hw_lam && !h->hw_energy && n > kMidMaxQubits) return;
     h->hw_wins.swap(passes);
     h->hw_groups.swap(hgroups);
     h->hw_classes.swap(hclasses);
@@ -800,7 +802,7 @@ int apply_dense(vqe_state* s, const DenseArgs& a, const double* u) {
 // ckpt_ptr[k] receives the state at boundary bounds[k] (pass index + 1).
 template <typename T>
 int forward(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* params,
-            const std::vector<size_t>& bounds, const std::vector<void*>& ckpt_ptr) {
+            const std::vector<size_t>& bounds, const std::vector<void*>& ckpt_ptr, int chunk = 0) {
     void* cur = s->data;
     const int d = sizeof(T) == 8 ? 1 : 0;
     const Mat2<T>* mats = nullptr;
@@ -827,6 +829,8 @@ int forward(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* pa
         }
         ps.end();
         cur = out;
+        if (chunk > 0 && (pi + 1) % (size_t)chunk == 0 && pi + 1 < pl.passes.size())
+            VQE_HIP(hipStreamSynchronize(s->stream));
     }
     return VQE_OK;
 }
@@ -988,8 +992,9 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
     double* d_e = psi->d_res;
     double* d_g = psi->d_res + 2;
     hipStream_t st = psi->stream;
+    const int chunk = o && o->chunk_passes > 0 ? o->chunk_passes : 0;
     VQE_HIP(launch_set_basis(psi->dtype, psi->data, 1ull << psi->n, 0, st));
-    rc = forward<T>(psi, c, pl, params, bounds, ck);
+    rc = forward<T>(psi, c, pl, params, bounds, ck, chunk);
     if (rc) return rc;
     rc = apply_h<T>(psi, lam->data, h, d_e);
     if (rc) return rc;
@@ -1017,6 +1022,7 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
         ps.end();
         if (n_gslots)
             VQE_HIP(launch_reduce(psi->d_part, gb, n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, 1, st));
+        if (chunk > 0 && (P - pi) % (size_t)chunk == 0 && pi > 0) VQE_HIP(hipStreamSynchronize(st));
     }
     VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, (2 + c->n_params) * sizeof(double), hipMemcpyDeviceToHost, st));
     VQE_HIP(hipStreamSynchronize(st));
@@ -1451,16 +1457,30 @@ template <typename T>
 int mid_impl(vqe_batch* b, const vqe_batch_item* items, const std::vector<size_t>& idx) {
     const size_t m = idx.size();
     const size_t amp = 2 * sizeof(T);
-    std::vector<uint32_t> nblk(m);
-    std::vector<uint64_t> ncos(m), part_base(m), red_base(m), st_off(m), m_off(m);
-    size_t n_gates = 0, n_mats = 1, n_fwd = 0, n_part = 0, n_red = 0, st_bytes = 0;
-    size_t pmax = 0;
+    // lam = H psi: window passes (hwin_batch_kernel, one launch per pass index
+    // and coefficient form) where the Hamiltonian has a window cover, else the
+    // tile kernel (mid_hpsi_kernel)
+    std::vector<uint32_t> nblk(m), nblk_e(m);
+    std::vector<uint64_t> ncos(m), part_base(m), part_s(m), red_base(m), st_off(m), m_off(m);
+    std::vector<char> use_hw(m);
+    size_t n_gates = 0, n_mats = 1, n_fwd = 0, n_part = 0, n_red = 0, st_bytes = 0, n_hw = 0, n_tile = 0;
+    size_t pmax = 0, hmax = 0;
     for (size_t k = 0; k < m; ++k) {
         const vqe_circuit* c = items[idx[k]].circuit;
+        const vqe_hamiltonian* hh = items[idx[k]].hamiltonian;
         ncos[k] = 1ull << (c->n - kMidWin);
         nblk[k] = (uint32_t)std::min<uint64_t>(ncos[k], kMidMaxBlocks);
+        use_hw[k] = !hh->hw_wins.empty();
+        nblk_e[k] = use_hw[k] ? (uint32_t)std::min<uint64_t>(1ull << (c->n - kHwBits), kMidMaxBlocks) : nblk[k];
+        if (use_hw[k]) {
+            n_hw += hh->hw_wins.size();
+            hmax = std::max(hmax, hh->hw_wins.size());
+        } else {
+            ++n_tile;
+        }
         part_base[k] = n_part;
-        n_part += (2 + c->mid_slot_pidx.size()) * (size_t)nblk[k];
+        part_s[k] = n_part + 2 * (size_t)nblk_e[k];
+        n_part += 2 * (size_t)nblk_e[k] + c->mid_slot_pidx.size() * (size_t)nblk[k];
         red_base[k] = n_red;
         n_red += 2 + c->mid_slot_pidx.size();
         st_off[k] = st_bytes;
@@ -1476,7 +1496,8 @@ int mid_impl(vqe_batch* b, const vqe_batch_item* items, const std::vector<size_t
     const size_t o_fwd = 0;
     const size_t o_rev = align_up(o_fwd + n_fwd * sizeof(MidPass), 256);
     const size_t o_ham = align_up(o_rev + n_fwd * sizeof(MidPass), 256);
-    const size_t o_red = align_up(o_ham + m * sizeof(MidHam), 256);
+    const size_t o_hw = align_up(o_ham + std::max<size_t>(n_tile, 1) * sizeof(MidHam), 256);
+    const size_t o_red = align_up(o_hw + std::max<size_t>(n_hw, 1) * sizeof(HwItem), 256);
     const size_t o_gates = align_up(o_red + n_red * sizeof(MidRed), 256);
     const size_t o_mats = align_up(o_gates + std::max<size_t>(n_gates, 1) * sizeof(BatchGate), 256);
     const size_t o_out = align_up(o_mats + (n_mats + 1) * sizeof(Mat2<T>), 256);  // + a zero matrix at the end
@@ -1494,8 +1515,9 @@ int mid_impl(vqe_batch* b, const vqe_batch_item* items, const std::vector<size_t
     std::memset(&hm[0], 0, sizeof(Mat2<T>));
     std::memset(&hm[n_mats], 0, sizeof(Mat2<T>));
     double* part = (double*)(d + o_part);
-    // gates, matrices, H psi and reduction descriptors per item
-    size_t g_off = 0;
+    // gates, matrices, tile-form H psi and reduction descriptors per item
+    auto* hw = (HwItem*)(h + o_hw);
+    size_t g_off = 0, n_th = 0;
     uint32_t hblk = 0;
     for (size_t k = 0; k < m; ++k) {
         const vqe_batch_item& it = items[idx[k]];
@@ -1504,24 +1526,62 @@ int mid_impl(vqe_batch* b, const vqe_batch_item* items, const std::vector<size_t
         for (size_t i = 0; i < c->gates.size(); ++i)
             if (c->bgates[i].type == OP_U2 || c->bgates[i].type == OP_PAIR2)
                 fill_matrix(hm[m_off[k] + c->bgates[i].mat], c->gates[i], angle_of(c->gates[i], it.params), false);
-        MidHam mh{};
-        mh.psi = d + o_st + st_off[k];
-        mh.lam = d + o_st + st_off[k] + st_bytes_half(c->n, amp);
-        mh.groups = it.hamiltonian->d_groups;
-        mh.terms = terms_of<T>(it.hamiltonian);
-        mh.n_tiles = ncos[k];
-        mh.part_off = part_base[k];
-        mh.n_groups = (uint32_t)it.hamiltonian->groups.size();
-        mh.blk_begin = hblk;
-        mh.n_blk = nblk[k];
-        hh[k] = mh;
-        hblk += nblk[k];
-        const uint64_t nb = nblk[k];
-        hred[red_base[k]] = MidRed{part_base[k], nblk[k], 0};
-        hred[red_base[k] + 1] = MidRed{part_base[k] + nb, nblk[k], 0};
+        if (!use_hw[k]) {
+            MidHam mh{};
+            mh.psi = d + o_st + st_off[k];
+            mh.lam = d + o_st + st_off[k] + st_bytes_half(c->n, amp);
+            mh.groups = it.hamiltonian->d_groups;
+            mh.terms = terms_of<T>(it.hamiltonian);
+            mh.n_tiles = ncos[k];
+            mh.part_off = part_base[k];
+            mh.n_groups = (uint32_t)it.hamiltonian->groups.size();
+            mh.blk_begin = hblk;
+            mh.n_blk = nblk[k];
+            hh[n_th++] = mh;
+            hblk += nblk[k];
+        }
+        hred[red_base[k]] = MidRed{part_base[k], nblk_e[k], 0};
+        hred[red_base[k] + 1] = MidRed{part_base[k] + nblk_e[k], nblk_e[k], 0};
         for (size_t sl = 0; sl < c->mid_slot_pidx.size(); ++sl)
-            hred[red_base[k] + 2 + sl] = MidRed{part_base[k] + (2 + sl) * nb, nblk[k], 0};
+            hred[red_base[k] + 2 + sl] = MidRed{part_s[k] + sl * (uint64_t)nblk[k], nblk[k], 0};
         g_off += c->mid_gates.size();
+    }
+    // window-form H psi descriptors, grouped by launch: pass index, then real
+    // coefficients or not
+    struct HwLaunch {
+        size_t off, cnt;
+        uint32_t grid;
+        bool real;
+    };
+    std::vector<HwLaunch> hw_launch;
+    {
+        size_t e = 0;
+        for (size_t p = 0; p < hmax; ++p)
+            for (int real = 1; real >= 0; --real) {
+                HwLaunch L{e, 0, 0, real == 1};
+                for (size_t k = 0; k < m; ++k) {
+                    const vqe_hamiltonian* H = items[idx[k]].hamiltonian;
+                    if (!use_hw[k] || p >= H->hw_wins.size() || H->real_coeffs != (real == 1)) continue;
+                    const vqe_circuit* c = items[idx[k]].circuit;
+                    HwItem x{};
+                    x.w = H->hw_wins[p];
+                    x.psi = d + o_st + st_off[k];
+                    x.lam = d + o_st + st_off[k] + st_bytes_half(c->n, amp);
+                    x.groups = H->d_hw_groups;
+                    x.classes = H->d_hw_classes;
+                    x.terms = hw_terms_of<T>(H);
+                    x.n_cosets = 1ull << (c->n - kHwBits);
+                    x.part_off = part_base[k];
+                    x.blk_begin = L.grid;
+                    x.n_blk = nblk_e[k];
+                    x.first = p == 0 ? 1u : 0u;
+                    x.last = p + 1 == H->hw_wins.size() ? 1u : 0u;
+                    hw[e++] = x;
+                    L.grid += nblk_e[k];
+                    ++L.cnt;
+                }
+                if (L.cnt) hw_launch.push_back(L);
+            }
     }
     // pass descriptors, grouped by launch
     std::vector<size_t> l_off(pmax), l_cnt(pmax);
@@ -1541,7 +1601,7 @@ int mid_impl(vqe_batch* b, const vqe_batch_item* items, const std::vector<size_t
                     x.psi = d + o_st + st_off[k];
                     x.lam = d + o_st + st_off[k] + st_bytes_half(c->n, amp);
                     x.n_cosets = ncos[k];
-                    x.part_off = part_base[k] + (2 + (uint64_t)mp.slot_off) * nblk[k];
+                    x.part_off = part_s[k] + (uint64_t)mp.slot_off * nblk[k];
                     for (int j = 0; j < kMidWin; ++j) x.pos[j] = mp.pos[j];
                     x.gate_off = (uint32_t)(gbase + mp.gate_off);
                     x.n_gates = mp.n_gates;
@@ -1566,7 +1626,10 @@ int mid_impl(vqe_batch* b, const vqe_batch_item* items, const std::vector<size_t
     for (size_t p = 0; p < pmax; ++p)
         VQE_HIP(launch_mid_pass<T>((const MidPass*)(d + o_fwd) + l_off[p], (uint32_t)l_cnt[p], l_grid[p], false, dg,
                                    dm, part, b->stream));
-    VQE_HIP(launch_mid_hpsi<T>((const MidHam*)(d + o_ham), (uint32_t)m, hblk, part, b->stream));
+    if (n_th) VQE_HIP(launch_mid_hpsi<T>((const MidHam*)(d + o_ham), (uint32_t)n_th, hblk, part, b->stream));
+    for (const HwLaunch& L : hw_launch)
+        VQE_HIP(launch_hwin_batch<T>((const HwItem*)(d + o_hw) + L.off, (uint32_t)L.cnt, L.grid, L.real, part,
+                                     b->stream));
     for (size_t p = 0; p < pmax; ++p)
         VQE_HIP(launch_mid_pass<T>((const MidPass*)(d + o_rev) + l_off[p], (uint32_t)l_cnt[p], l_grid[p], true, dg,
                                    dm, part, b->stream));
@@ -2104,6 +2167,10 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const 
     if (int rc = check_state(lam, "vqe_energy_grad")) return rc;
     if (lam == psi || lam->data == psi->data || lam->n != psi->n || lam->dtype != psi->dtype) {
         set_error("vqe_energy_grad: lam must be a distinct state of the same n and dtype as psi");
+        return VQE_ERR_ARG;
+    }
+    if (opts && opts->chunk_passes < 0) {
+        set_error("vqe_energy_grad: chunk_passes must be >= 0");
         return VQE_ERR_ARG;
     }
     if (opts && opts->n_ckpt > 0) {

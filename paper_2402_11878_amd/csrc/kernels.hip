@@ -848,14 +848,13 @@ __device__ __forceinline__ void parity_sign(uint32_t cnt, float& s) { s = __uint
 // bucket sums E_u over the classes (A and zt staged in LDS at local index
 // j - cbase), D_r = sum_{u in M} (-1)^{popcount(u & r)} E_u (a transform over
 // the register bits in M only: buckets outside M are empty, so D_r = D_{r & M}),
-// then lam_r += D_r psi[(t + kHwThreads r) ^ xl].
+// returned in dr (and di); hw_apply then adds D_r psi[(t + kHwThreads r) ^ xl].
 // REAL: every folded coefficient is real (a real symmetric H: each term holds
 // an even number of Y, so w (-i)^popcount(x&z) = +-w); D is then real and the
 // imaginary halves of the class sums, the transform and the update vanish.
 template <typename T, int M, bool REAL>
 __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint32_t t,
-                                         const typename VecOf<T>::type* A, const uint32_t* zt,
-                                         const typename VecOf<T>::type* sp, T* lr, T* li) {
+                                         const typename VecOf<T>::type* A, const uint32_t* zt, T* dr, T* di) {
     using V = typename VecOf<T>::type;
     constexpr int R = 1 << kHwRegBits;
     T er[R], ei[R];
@@ -911,6 +910,20 @@ __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint3
                 }
             }
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        dr[r] = er[r & M];
+        if (!REAL) di[r] = ei[r & M];
+    }
+}
+
+// lam_r += D_r psi[(t + kHwThreads r) ^ xl] for the R patterns of thread t
+// (one code path for every register-bit subset of the group's classes).
+template <typename T, bool REAL>
+__device__ __forceinline__ void hw_apply(const HwGroup& G, uint32_t t, const typename VecOf<T>::type* sp,
+                                         const T* dr, const T* di, T* lr, T* li) {
+    using V = typename VecOf<T>::type;
+    constexpr int R = 1 << kHwRegBits;
     // partner of pattern t + kHwThreads r: byte offset a0 + (r ^ xr) kHwThreads sizeof(V)
     const uint32_t a0 = (t ^ (G.xl & (kHwThreads - 1))) * (uint32_t)sizeof(V);
     const uint32_t xr = G.xl >> kHwThreadBits;
@@ -918,13 +931,11 @@ __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint3
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const V pv = *reinterpret_cast<const V*>(spb + a0 + (r ^ xr) * (uint32_t)(kHwThreads * sizeof(V)));
-        const T dr = er[r & M];
-        lr[r] = fma(dr, pv.x, lr[r]);
-        li[r] = fma(dr, pv.y, li[r]);
+        lr[r] = fma(dr[r], pv.x, lr[r]);
+        li[r] = fma(dr[r], pv.y, li[r]);
         if (!REAL) {
-            const T di = ei[r & M];
-            lr[r] = fma(-di, pv.y, lr[r]);
-            li[r] = fma(di, pv.x, li[r]);
+            lr[r] = fma(-di[r], pv.y, lr[r]);
+            li[r] = fma(di[r], pv.x, li[r]);
         }
     }
 }
@@ -932,12 +943,16 @@ __device__ __forceinline__ void hw_group(const HwGroup& G, uint32_t cbase, uint3
 // EONLY: the energy-only form of the grouped expectation (eq. 7).  No lam is
 // read or written: each pass adds Re sum_b conj(psi_b) (H_w psi)_b over its
 // own groups H_w to per-block partials, the first pass also <psi|psi>.
-template <typename T, bool EONLY, bool REAL>
-__global__ void __launch_bounds__(kHwThreads)
-hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
-            const typename VecOf<T>::type* __restrict__ psi, typename VecOf<T>::type* __restrict__ lam,
-            const HwGroup* __restrict__ groups, const HwClass* __restrict__ classes,
-            const HwTerm<T>* __restrict__ terms, int first, int last, double* __restrict__ part) {
+// The pass for one block: cosets unit(0), ..., unit(count - 1) while below n_cosets;
+// after the last pass (or every energy-only pass) the block's energy and
+// norm partials go to *e_out and *n_out.
+template <typename T, bool EONLY, bool REAL, typename Unit>
+__device__ __forceinline__ void hwin_body(const HwDesc& w, uint64_t n_cosets, uint32_t count, Unit unit,
+                                          const typename VecOf<T>::type* __restrict__ psi,
+                                          typename VecOf<T>::type* __restrict__ lam,
+                                          const HwGroup* __restrict__ groups, const HwClass* __restrict__ classes,
+                                          const HwTerm<T>* __restrict__ terms, int first, int last,
+                                          double* e_out, double* n_out) {
     using V = typename VecOf<T>::type;
     constexpr int R = 1 << kHwRegBits;
     constexpr int TB = kHwThreadBits;
@@ -965,8 +980,8 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
     for (int k = 0; k < TB; ++k)
         if ((t >> k) & 1) off_t += bitval[k];
     double e_acc = 0.0, n_acc = 0.0;
-    for (uint32_t it = 0; it < cpt; ++it) {
-        const uint64_t c = xcd_unit(blockIdx.x, it, cpt, mlog);
+    for (uint32_t it = 0; it < count; ++it) {
+        const uint64_t c = unit(it);
         if (c >= n_cosets) break;
         uint64_t base = c;
 #pragma unroll
@@ -1022,16 +1037,18 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
         for (uint32_t g = w.g_begin; g < w.g_end; ++g) {
             const HwGroup& G = groups[g];
             static_assert(kHwRegBits == 3, "one case per register-bit subset");
+            T dr[R], di[R];
             switch (G.zrm) {
-                case 0: hw_group<T, 0, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 1: hw_group<T, 1, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 2: hw_group<T, 2, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 3: hw_group<T, 3, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 4: hw_group<T, 4, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 5: hw_group<T, 5, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                case 6: hw_group<T, 6, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
-                default: hw_group<T, 7, REAL>(G, w.c_begin, t, A, zt, sp, lr, li); break;
+                case 0: hw_group<T, 0, REAL>(G, w.c_begin, t, A, zt, dr, di); break;
+                case 1: hw_group<T, 1, REAL>(G, w.c_begin, t, A, zt, dr, di); break;
+                case 2: hw_group<T, 2, REAL>(G, w.c_begin, t, A, zt, dr, di); break;
+                case 3: hw_group<T, 3, REAL>(G, w.c_begin, t, A, zt, dr, di); break;
+                case 4: hw_group<T, 4, REAL>(G, w.c_begin, t, A, zt, dr, di); break;
+                case 5: hw_group<T, 5, REAL>(G, w.c_begin, t, A, zt, dr, di); break;
+                case 6: hw_group<T, 6, REAL>(G, w.c_begin, t, A, zt, dr, di); break;
+                default: hw_group<T, 7, REAL>(G, w.c_begin, t, A, zt, dr, di); break;
             }
+            hw_apply<T, REAL>(G, t, sp, dr, di, lr, li);
         }
         T e_t = 0, n_t = 0;
 #pragma unroll
@@ -1062,9 +1079,44 @@ hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
         __syncthreads();
     }
     if (t == 0) {
-        part[2 * blockIdx.x + 0] = red[0];
-        part[2 * blockIdx.x + 1] = red[kHwThreads];
+        *e_out = red[0];
+        *n_out = red[kHwThreads];
     }
+}
+
+template <typename T, bool EONLY, bool REAL>
+__global__ void __launch_bounds__(kHwThreads)
+hwin_kernel(const HwDesc w, uint64_t n_cosets, uint32_t cpt, uint32_t mlog,
+            const typename VecOf<T>::type* __restrict__ psi, typename VecOf<T>::type* __restrict__ lam,
+            const HwGroup* __restrict__ groups, const HwClass* __restrict__ classes,
+            const HwTerm<T>* __restrict__ terms, int first, int last, double* __restrict__ part) {
+    const uint64_t b = blockIdx.x;
+    hwin_body<T, EONLY, REAL>(
+        w, n_cosets, cpt, [=](uint32_t it) { return xcd_unit(b, it, cpt, mlog); }, psi, lam, groups, classes, terms,
+        first, last, part + 2 * b, part + 2 * b + 1);
+}
+
+// One window pass of lam = H psi for every item of a batch: descriptor i
+// owns blocks [blk_begin, blk_begin + n_blk), block blk takes cosets blk,
+// blk + n_blk, ... of its item.
+template <typename T, bool REAL>
+__global__ void __launch_bounds__(kHwThreads)
+hwin_batch_kernel(const HwItem* __restrict__ d, uint32_t n_desc, double* __restrict__ part) {
+    using V = typename VecOf<T>::type;
+    uint32_t lo = 0, hi = n_desc;
+    while (hi - lo > 1) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (d[m].blk_begin <= blockIdx.x) lo = m;
+        else hi = m;
+    }
+    const HwItem& x = d[lo];
+    const uint64_t blk = blockIdx.x - x.blk_begin, nb = x.n_blk;
+    const uint32_t count = (uint32_t)((x.n_cosets - blk + nb - 1) / nb);
+    hwin_body<T, false, REAL>(
+        x.w, x.n_cosets, count, [=](uint32_t it) { return blk + (uint64_t)it * nb; }, (const V*)x.psi, (V*)x.lam,
+        x.groups,
+        x.classes, (const HwTerm<T>*)x.terms, (int)x.first, (int)x.last, part + x.part_off + blk,
+        part + x.part_off + nb + blk);
 }
 
 // ---------------------------------------------------------------- one term
@@ -1371,6 +1423,16 @@ hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_hwin_batch(const HwItem* d, uint32_t n_desc, uint32_t grid, bool real, double* part,
+                             hipStream_t st) {
+    if (real)
+        hipLaunchKernelGGL((hwin_batch_kernel<T, true>), dim3(grid), dim3(kHwThreads), 0, st, d, n_desc, part);
+    else
+        hipLaunchKernelGGL((hwin_batch_kernel<T, false>), dim3(grid), dim3(kHwThreads), 0, st, d, n_desc, part);
+    return hipGetLastError();
+}
+
 uint32_t hpsi_blocks(int n, uint32_t max_blocks) {
     const int tb = n < kTileBits ? n : kTileBits;
     const uint64_t n_tiles = 1ull << (n - tb);
@@ -1451,6 +1513,8 @@ template hipError_t launch_hwin<float>(int, const HwDesc&, const void*, void*, c
                                        const HwTerm<float>*, bool, bool, bool, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hwin<double>(int, const HwDesc&, const void*, void*, const HwGroup*, const HwClass*,
                                         const HwTerm<double>*, bool, bool, bool, double*, uint32_t*, hipStream_t);
+template hipError_t launch_hwin_batch<float>(const HwItem*, uint32_t, uint32_t, bool, double*, hipStream_t);
+template hipError_t launch_hwin_batch<double>(const HwItem*, uint32_t, uint32_t, bool, double*, hipStream_t);
 template hipError_t launch_hpsi<float>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<float>*, int, uint32_t, double*, uint32_t*, hipStream_t);
 template hipError_t launch_hpsi<double>(int, const void*, void*, const GroupDesc*, uint32_t, const TermDesc<double>*, int, uint32_t, double*, uint32_t*, hipStream_t);
 template hipError_t launch_expect_term<float>(int, const void*, uint64_t, uint64_t, double*, uint32_t*, hipStream_t);

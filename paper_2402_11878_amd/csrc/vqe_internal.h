@@ -325,6 +325,25 @@ hipError_t launch_hwin(int n, const HwDesc& w, const void* psi, void* lam, const
                        const HwClass* classes, const HwTerm<T>* terms, bool real, bool first, bool last,
                        double* part, uint32_t* nblocks, hipStream_t st);
 
+// One window pass of lam = H psi for one item of a batch of mid-size
+// states (one launch covers the pass of every item): blocks [blk_begin,
+// blk_begin + n_blk) of the launch; after the item's last pass block blk
+// writes its energy and norm partials to part[part_off + blk] and
+// part[part_off + n_blk + blk].
+struct HwItem {
+    HwDesc w;
+    const void* psi;
+    void* lam;
+    const HwGroup* groups;
+    const HwClass* classes;
+    const void* terms;  // HwTerm<T>
+    uint64_t n_cosets, part_off;
+    uint32_t blk_begin, n_blk, first, last;
+};
+template <typename T>
+hipError_t launch_hwin_batch(const HwItem* d, uint32_t n_desc, uint32_t grid, bool real, double* part,
+                             hipStream_t st);
+
 // ---------------------------------------------------------------- dense window by MFMA
 // psi' = U psi on kDenseK qubits, all >= 4 (16 consecutive cosets are 16
 // consecutive amplitudes), U given to the kernel as the real 2^(k+1) square

@@ -81,11 +81,17 @@ def percentile(values, q):
 
 class Server:
     def __init__(self, executor, budget_bytes, n_workers=4, max_batch=64, max_wait=2.0, clock=time.perf_counter,
-                 mid_n_max=None, mid_workers=1, mid_batch=False):
+                 mid_n_max=None, mid_workers=1, mid_batch=False, mid_batch_n_max=None):
         self.ex = executor
-        # requests of more than the batch limit and at most mid_n_max qubits go to the mid lane
+        # requests of more than the batch limit and at most mid_n_max qubits go to the mid lane: with
+        # mid_batch, those of at most mid_batch_n_max qubits (default: all of them) to its batch loop,
+        # the others to its workers
         self.mid_n_max = mid_n_max if (mid_n_max is not None and (mid_workers > 0 or mid_batch)) else None
         self.mid_batch = bool(mid_batch) and self.mid_n_max is not None
+        self.mid_batch_n_max = (min(mid_batch_n_max, self.mid_n_max) if mid_batch_n_max is not None
+                                else self.mid_n_max) if self.mid_batch else None
+        if self.mid_batch and self.mid_batch_n_max < self.mid_n_max and mid_workers < 1:
+            raise ValueError("mid_batch_n_max below mid_n_max needs mid_workers >= 1")
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
         self.max_wait = max_wait
@@ -97,6 +103,7 @@ class Server:
         self._small = collections.deque()
         self._large = collections.deque()
         self._mid = collections.deque()
+        self._midb = collections.deque()
         self._closing = False
         self.completed = []
         self.batches = []          # sizes of the launched batches of small requests
@@ -109,9 +116,9 @@ class Server:
         self._threads += [threading.Thread(target=self._worker_loop, args=(self._large,), daemon=True)
                           for _ in range(n_workers)]
         if self.mid_batch:
-            self._threads.append(threading.Thread(target=self._batch_loop, args=(self._mid, self.ex.run_mid_batch,
+            self._threads.append(threading.Thread(target=self._batch_loop, args=(self._midb, self.ex.run_mid_batch,
                                                                                 self.mid_batches), daemon=True))
-        elif self.mid_n_max is not None:
+        if self.mid_n_max is not None and (not self.mid_batch or self.mid_batch_n_max < self.mid_n_max):
             self._threads += [threading.Thread(target=self._worker_loop, args=(self._mid,), daemon=True)
                               for _ in range(mid_workers)]
         for t in self._threads:
@@ -160,13 +167,15 @@ class Server:
     def _queue_of(self, inst):
         if self.ex.is_small(inst):
             return self._small
+        if self.mid_batch and inst.n <= self.mid_batch_n_max:
+            return self._midb
         if self.mid_n_max is not None and inst.n <= self.mid_n_max:
             return self._mid
         return self._large
 
     def _batched(self, inst):
         """Served by a batch launch (no resident state of its own)."""
-        return self.ex.is_small(inst) or (self.mid_batch and inst.n <= self.mid_n_max)
+        return self.ex.is_small(inst) or (self.mid_batch and inst.n <= self.mid_batch_n_max)
 
     def latencies(self):
         return [r.done_t - r.submit_t for r in self.completed]
@@ -281,9 +290,13 @@ class GpuExecutor:
     first reserve_cus compute units, larger instances on big_streams
     streams restricted to the others (vqe_stream_create with a CU mask).
     Batched mid-size requests (run_mid_batch) have a batch handle and stream
-    of their own."""
+    of their own.  chunk_passes > 0 submits the evaluations of instances
+    above mid_n_max qubits in chunks of that many window passes (about one
+    ansatz layer at 3), waiting for each chunk before queueing the next, so
+    that kernels of other lanes start between chunks."""
 
-    def __init__(self, dtype="c64", n_ckpt=0, small_n_max=None, reserve_cus=0, mid_n_max=20, big_streams=3):
+    def __init__(self, dtype="c64", n_ckpt=0, small_n_max=None, reserve_cus=0, mid_n_max=20, big_streams=3,
+                 chunk_passes=0):
         import torch
 
         from . import _lib
@@ -295,6 +308,7 @@ class GpuExecutor:
         lim = _lib.BATCH_MAX_QUBITS[self.dtype]
         self.small_n_max = lim if small_n_max is None else min(small_n_max, lim)
         self.mid_n_max = mid_n_max
+        self.chunk_passes = int(chunk_passes)
         self._own_streams = []
         self._rr = 0
         if reserve_cus > 0:
@@ -352,8 +366,9 @@ class GpuExecutor:
 
     def run_one(self, inst, theta):
         st, bufs, hs = inst.state
+        chunk = self.chunk_passes if inst.n > self.mid_n_max else 0
         return self.L.vqe_energy_grad(hs[0], hs[1], inst.circuit.handle, theta, inst.hamiltonian.handle,
-                                      ckpt=hs[2:])
+                                      ckpt=hs[2:], chunk_passes=chunk)
 
     def run_batch(self, items):
         return self.L.vqe_batch_energy_grad(

@@ -208,6 +208,38 @@ def test_checkpoints_and_determinism(dt):
         _lib.vqe_hamiltonian_free(h)
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_chunked_submission_gives_the_same_bits(dt):
+    """chunk_passes only changes when the host waits for the stream: every
+    chunk size, with and without checkpoints, gives the bits of the
+    unchunked sweep; a negative chunk size is an argument error."""
+    dtype = DT[dt]
+    n, L = 14, 5
+    say(f"case chunk n={n} {dt}")
+    lat = synth.Lattice(7, tuple(synth.chain_bonds(7)), 1.0, 4.0)
+    x, z, w = lham.from_lattice(lat)
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    c = _lib.vqe_circuit_create(n, ansatz.layered(n, L))
+    th = synth.theta(9, 2 * n * L)
+    s, l, ck = Dev(n, dtype), Dev(n, dtype), Dev(n, dtype)
+    try:
+        E0, g0 = _lib.vqe_energy_grad(s.h, l.h, c, th, h)
+        _, n_passes = _lib.vqe_circuit_info(c)
+        for chunk in (1, 2, 3, n_passes, n_passes + 5):
+            E1, g1 = _lib.vqe_energy_grad(s.h, l.h, c, th, h, chunk_passes=chunk)
+            assert E1 == E0 and np.array_equal(g1, g0), chunk
+        Ec, gc = _lib.vqe_energy_grad(s.h, l.h, c, th, h, ckpt=[ck.h])
+        Ecc, gcc = _lib.vqe_energy_grad(s.h, l.h, c, th, h, ckpt=[ck.h], chunk_passes=2)
+        assert Ecc == Ec and np.array_equal(gcc, gc)
+        with pytest.raises(_lib.VqeError):
+            _lib.vqe_energy_grad(s.h, l.h, c, th, h, chunk_passes=-1)
+    finally:
+        for d in (s, l, ck):
+            d.free()
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
+
+
 def test_library_owned_state_and_errors():
     """A state whose memory the library allocates; argument errors on device calls."""
     n = 6

@@ -237,3 +237,20 @@ def test_mid_batch_lane_batches_queued_mid_requests():
     assert ex.mid_sizes == srv.mid_batches
     assert all(srv.instances[i].footprint == 0 for i in range(5))
     assert srv.instances[6].footprint > 0 and srv.peak_used <= budget and ex.resident == 0
+
+
+def test_mid_batch_split_by_size():
+    """mid_batch_n_max splits the mid lane: requests up to it are batched,
+    larger mid-size ones go to the mid workers (resident state)."""
+    ex = MockExecutor(1 << 34, dur=0.02)
+    srv = _server(ex, 1 << 34, n_workers=1, mid_n_max=20, mid_workers=1, mid_batch=True, mid_batch_n_max=16)
+    for i, n in enumerate([14, 16, 18, 20, 24]):
+        srv.add_instance(i, n, None, None)
+    items = [(i, np.full(2, float(10 * i + k))) for k in range(3) for i in range(5)]
+    for (i, th), f in zip(items, srv.submit_many(items)):
+        assert f.result(timeout=20)[0] == 2 * th[0]
+    srv.close()
+    assert sum(srv.mid_batches) == 6
+    assert [srv.instances[i].footprint == 0 for i in range(5)] == [True, True, False, False, False]
+    with pytest.raises(ValueError):
+        _server(ex, 1 << 34, mid_n_max=20, mid_workers=0, mid_batch=True, mid_batch_n_max=16)
