@@ -177,3 +177,48 @@ def test_served_with_lanes_equals_alone():
     ex.close()
     for (E1, g1), (E2, g2) in zip(alone, mixed):
         assert E1 == E2 and np.array_equal(g1, g2)
+
+
+def test_served_with_mid_batches_and_chunks():
+    """The served stream's default form: mid-size requests up to 16 qubits
+    batched (tile passes), 18-20 qubits on the mid worker, larger ones
+    submitted in chunks of 3 passes.  Batched results equal the same items
+    batched alone (the batch path's own bits) and match the oracle within the
+    complex64 tolerance; worker results equal the request served alone."""
+    from paper_2402_11878_amd.serving import GpuExecutor, Server
+    import torch
+    say("case serving with mid batches and chunks")
+    specs = [(10, 2), (14, 2), (16, 3), (16, 2), (18, 2), (22, 1)]
+    insts = []
+    for n, L in specs:
+        x, z, w = _chain(n)
+        insts.append((n, Circuit.layered(n, L), Hamiltonian(n, x, z, w), x, z, w))
+    reqs = [(i, synth.theta(1300 + 10 * i + k, insts[i][1].n_params)) for k in range(2) for i in range(len(insts))]
+    ex0 = GpuExecutor("c64", n_ckpt=0)
+    alone = [_serve(ex0, 1 << 30, insts, [r], 1)[1][0] for r in reqs]
+    ex0.close()
+    ex = GpuExecutor("c64", n_ckpt=0, mid_n_max=20, chunk_passes=3)
+    srv = Server(ex, 1 << 30, n_workers=2, mid_n_max=20, mid_workers=1, mid_batch=True, mid_batch_n_max=16)
+    for i, (n, C, H, *_r) in enumerate(insts):
+        srv.add_instance(i, n, C, H)
+    mixed = [f.result(timeout=120) for f in srv.submit_many(reqs)]
+    srv.close()
+    b = _lib.vqe_batch_create(_lib.VQE_C64, torch.cuda.current_stream().cuda_stream)
+    try:
+        for (i, th), (E1, g1), (E2, g2) in zip(reqs, alone, mixed):
+            n, C, H, x, z, w = insts[i]
+            if 13 < n <= 16:
+                (Eb, gb), = _lib.vqe_batch_energy_grad(b, [(C.handle, H.handle, th)])
+                assert E2 == Eb and np.array_equal(g2, gb)
+                assert rel_err(E2, E1) <= 1e-5
+            else:
+                assert E1 == E2 and np.array_equal(g1, g2)
+    finally:
+        _lib.vqe_batch_free(b)
+        ex.close()
+    assert sum(srv.mid_batches) == 6
+    for (i, th), (E, g) in list(zip(reqs, mixed))[:len(insts)]:
+        n, C, H, x, z, w = insts[i]
+        E_ref, g_ref = ogr.adjoint(n, oracle_gates(C.gates), th, oham.from_masks(n, x, z, w))
+        assert rel_err(E, E_ref) <= 1e-5
+        assert np.max(np.abs(g - g_ref)) / max(np.max(np.abs(g_ref)), 1) <= 1e-4
