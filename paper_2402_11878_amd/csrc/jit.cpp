@@ -329,7 +329,10 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
     const int CPW = 64 >> S, PER_BLOCK = kBlock >> S;
     std::ostringstream& o = g.o;
     o << prelude(dbl);
-    o << "extern \"C\" __global__ void __launch_bounds__(" << kBlock << ")\n"
+    // Reverse kernels ask for two blocks per CU: unconstrained they take 256 VGPRs plus a few
+    // AGPRs, one wave per SIMD; at two waves the compiler spills a few dwords (complex64
+    // reverse pass 37.9 -> 36.4 ms at 32 qubits, complex128 unchanged).
+    o << "extern \"C\" __global__ void __launch_bounds__(" << kBlock << (NV == 2 ? ", 2" : "") << ")\n"
       << jit_kernel_name(NV, dbl) << "(const JitArgs a, const Mat2* __restrict__ mats, u32 cpt, u32 mlog, "
          "const V* __restrict__ in0, V* __restrict__ out0, const V* __restrict__ in1, V* __restrict__ out1, "
          "double* __restrict__ gpart) {\n"
