@@ -185,3 +185,64 @@ def test_mid_batch_limits():
             _lib.vqe_circuit_free(c)
             _lib.vqe_hamiltonian_free(h)
             _lib.vqe_hamiltonian_free(h2)
+
+
+def _pauli_sum_masks(n, n_terms, seed, max_flip, long_x=False):
+    """Random Pauli sum as (x, z, w) masks: each term flips (X or Y) at most
+    max_flip qubits, with Z on some others, so Y counts are odd and even
+    (complex and real folded coefficients); long_x adds X on every qubit,
+    which no 12-qubit window holds."""
+    rng = np.random.default_rng(seed)
+    x, z, w = [], [], []
+    for _ in range(n_terms):
+        flips = rng.choice(n, size=int(rng.integers(0, max_flip + 1)), replace=False)
+        xm = 0
+        zm = int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n))
+        for q in flips:
+            xm |= 1 << int(q)
+            if rng.random() < 0.5:
+                zm |= 1 << int(q)     # Y on q
+            else:
+                zm &= ~(1 << int(q))  # X on q
+        x.append(xm), z.append(zm), w.append(float(rng.normal()))
+    if long_x:
+        x.append((1 << n) - 1), z.append(0), w.append(0.7)
+    return np.array(x, np.uint64), np.array(z, np.uint64), np.array(w)
+
+
+@pytest.mark.parametrize("dt", [_lib.VQE_C128, _lib.VQE_C64])
+def test_mid_batch_complex_and_uncovered_hamiltonians(dt):
+    """lam = H psi of mid-size items in both forms: window passes with
+    complex folded coefficients (terms with odd Y counts), and the tile
+    kernel for a Hamiltonian with an X mask no window can hold; against the
+    oracle, and bitwise the same alone and together."""
+    import torch
+    n = 14
+    arr, P = ansatz.layered(n, 2), 4 * n
+    probs = [_pauli_sum_masks(n, 60, 21, 4), _pauli_sum_masks(n, 40, 22, 3, long_x=True)]
+    assert any(bin(int(a) & int(b)).count("1") % 2 for a, b in zip(probs[0][0], probs[0][1]))  # odd Y
+    items, refs, hs = [], [], []
+    c = _lib.vqe_circuit_create(n, arr)
+    try:
+        for k, (x, z, w) in enumerate(probs):
+            h = _lib.vqe_hamiltonian_create(n, x, z, w)
+            hs.append(h)
+            th = synth.theta(60 + k, P)
+            items.append((c, h, th))
+            refs.append(ogr.adjoint(n, oracle_gates(arr), th, oham.from_masks(n, x, z, w)))
+        say(f"case mid complex/uncovered dtype={dt}")
+        b = _lib.vqe_batch_create(dt, torch.cuda.current_stream().cuda_stream)
+        try:
+            both = _lib.vqe_batch_energy_grad(b, items)
+            alone = [_lib.vqe_batch_energy_grad(b, [it])[0] for it in items]
+        finally:
+            _lib.vqe_batch_free(b)
+        te, tg = TOL[dt]
+        for (E, g), (E1, g1), (E_ref, g_ref) in zip(both, alone, refs):
+            assert E == E1 and np.array_equal(g, g1)
+            assert rel_err(E, E_ref) <= te, (dt, E, E_ref)
+            assert _grad_err(g, g_ref) <= tg, (dt, _grad_err(g, g_ref))
+    finally:
+        for h in hs:
+            _lib.vqe_hamiltonian_free(h)
+        _lib.vqe_circuit_free(c)
