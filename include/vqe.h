@@ -298,9 +298,11 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,
  *   in device memory owned by the batch handle (2 x 2^n amplitudes per
  *   item); the gates are fused into passes over 10-qubit windows, and one
  *   launch applies pass k of every item that has one, a workgroup staging
- *   one 2^10-amplitude tile of a window in LDS at a time; then one launch
- *   for lam = H psi and the energy of every item, the reverse passes
- *   likewise, and one launch reducing per-block partial sums.
+ *   one 2^10-amplitude tile of a window in LDS at a time; then lam = H psi
+ *   and the energy (the 12-qubit window passes of each Hamiltonian, one
+ *   launch per pass index, or one tile launch for Hamiltonians without a
+ *   window cover), the reverse passes likewise, and one launch reducing
+ *   per-block partial sums.
  * Each item's result depends only on that item (fixed per-item work and
  * reduction order), so it is bitwise the same alone or in any batch.  A
  * batch handle owns device and pinned staging buffers, grown on demand to
