@@ -231,8 +231,9 @@ struct Gen {
                 for (int p = 0; p < N; ++p) {
                     if ((p & (int)mask) != (int)PA) continue;
                     const int q = p ^ (int)PA ^ (int)PB;
-                    o << "    acc += (" << R(1, q) << " * " << R(0, p) << " + " << I(1, q) << " * " << I(0, p) << ") - ("
-                      << R(1, p) << " * " << R(0, q) << " + " << I(1, p) << " * " << I(0, q) << ");\n";
+                    o << "    acc += " << R(1, q) << " * " << R(0, p) << "; acc += " << I(1, q) << " * " << I(0, p)
+                      << "; acc -= " << R(1, p) << " * " << R(0, q) << "; acc -= " << I(1, p) << " * " << I(0, q)
+                      << ";\n";
                 }
                 o << "    g" << (int)k.slot << " += (double)acc; }\n";
                 break;
@@ -244,7 +245,7 @@ struct Gen {
                 o << "  { T acc = 0;\n";
                 if (k.type == OP_GZ && la) {
                     for (int p = 0; p < N; ++p)
-                        o << "    acc += " << R(1, p) << " * " << I(0, p) << " - " << I(1, p) << " * " << R(0, p)
+                        o << "    acc += " << R(1, p) << " * " << I(0, p) << "; acc -= " << I(1, p) << " * " << R(0, p)
                           << ";\n";
                     o << "    g" << (int)k.slot << " += (double)(" << H(A - KL) << " ? -acc : acc); }\n";
                     break;
@@ -254,15 +255,17 @@ struct Gen {
                     const int q = p | (1 << A);
                     const std::string p0r = R(0, p), p0i = I(0, p), p1r = R(0, q), p1i = I(0, q);
                     const std::string l0r = R(1, p), l0i = I(1, p), l1r = R(1, q), l1i = I(1, q);
+                    // one fused multiply-add per product (the sum of the pair's four
+                    // products, accumulated term by term)
                     if (k.type == OP_GZ)
-                        o << "    acc += (" << l0r << " * " << p0i << " - " << l0i << " * " << p0r << ") - (" << l1r
-                          << " * " << p1i << " - " << l1i << " * " << p1r << ");\n";
+                        o << "    acc += " << l0r << " * " << p0i << "; acc -= " << l0i << " * " << p0r << "; acc -= "
+                          << l1r << " * " << p1i << "; acc += " << l1i << " * " << p1r << ";\n";
                     else if (k.type == OP_GY)
-                        o << "    acc += (" << l1r << " * " << p0r << " + " << l1i << " * " << p0i << ") - (" << l0r
-                          << " * " << p1r << " + " << l0i << " * " << p1i << ");\n";
+                        o << "    acc += " << l1r << " * " << p0r << "; acc += " << l1i << " * " << p0i << "; acc -= "
+                          << l0r << " * " << p1r << "; acc -= " << l0i << " * " << p1i << ";\n";
                     else
-                        o << "    acc += (" << l0r << " * " << p1i << " - " << l0i << " * " << p1r << ") + (" << l1r
-                          << " * " << p0i << " - " << l1i << " * " << p0r << ");\n";
+                        o << "    acc += " << l0r << " * " << p1i << "; acc -= " << l0i << " * " << p1r << "; acc += "
+                          << l1r << " * " << p0i << "; acc -= " << l1i << " * " << p0r << ";\n";
                 }
                 o << "    g" << (int)k.slot << " += (double)acc; }\n";
                 break;
