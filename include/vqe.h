@@ -307,7 +307,9 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,
  * reduction order), so it is bitwise the same alone or in any batch.  A
  * batch handle owns device and pinned staging buffers, grown on demand to
  * the largest call and held until vqe_batch_free, and runs on its stream;
- * vqe_batch_energy_grad returns after the results are on the host.
+ * vqe_batch_energy_grad returns after the results are on the host.  Calls on
+ * one handle must not overlap (one handle per thread); handles are
+ * independent of each other.
  * Errors: VQE_ERR_ARG (a null field, n above the limit, a Hamiltonian of
  * another size, too few parameters), VQE_ERR_OOM (buffers). */
 #define VQE_BATCH_MAX_QUBITS_C64  13
