@@ -280,7 +280,10 @@ int vqe_apply_hamiltonian(vqe_state* psi, vqe_state* lam, const vqe_hamiltonian*
  *     et al. 2021).  Exact when each parameter drives one gate.  lam is unused
  *     (may be NULL).
  * psi is overwritten; on return it holds U(theta)|0> for PARAM_SHIFT and the
- * reference |0...0> (up to rounding) for ADJOINT. */
+ * reference |0...0> (up to rounding) for ADJOINT, possibly with the sign -1:
+ * the specialised reverse kernels un-apply rotations by angles beyond a
+ * quarter turn as a half turn (a sign on psi and lam together, which the
+ * gradient does not see) and three shears. */
 int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,
                     const double* params, size_t n_params, const vqe_hamiltonian* h,
                     const vqe_grad_opts* opts, double* energy, double* grad);

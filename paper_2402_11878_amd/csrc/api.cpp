@@ -56,6 +56,9 @@ struct vqe_state {
     double* h_res = nullptr;   // pinned host mirror of d_res
     void* d_mats = nullptr;    // matrix table of the specialised kernels, filled per evaluation
     void* h_mats = nullptr;    // pinned staging of d_mats
+    // per pass, whether the shear forms of its reverse rotations flip the sign
+    // of psi and lam an odd number of times (filled with the matrix table)
+    std::vector<int8_t> rev_flip;
     size_t mats_cap = 0;
     hipEvent_t mats_ev = nullptr;  // completion of the last upload from h_mats
 };
@@ -591,6 +594,10 @@ void emit_gate(const Gate& g, int gi, const PlannedPass& p, std::vector<KOp>& op
             op.type = mat_op(g.kind);
             op.slot = (uint8_t)mat_gate.size();
             mat_gate.push_back(gi);
+            // RY and RZ are plane rotations (of the amplitude pair, of each
+            // amplitude's real and imaginary parts): the specialised reverse
+            // kernels un-apply them as three shears (shear_coefficients)
+            if (g.kind == VQE_GATE_RY || g.kind == VQE_GATE_RZ) op.c = 1;
             break;
     }
     ops.push_back(op);
@@ -757,18 +764,50 @@ int stage_mats(vqe_state* s, size_t bytes) {
     return VQE_OK;
 }
 
+// A plane rotation by a (x' = x cos a - y sin a, y' = x sin a + y cos a) as
+// three shears x += k1 y, y += k2 x, x += k1 y with k1 = -tan(a/2) and
+// k2 = sin a (Paeth's decomposition; three fused multiply-adds per plane
+// instead of two products and two FMAs).  a is first brought into
+// [-pi/2, pi/2] by a half turn, R(a) = -R(a -+ pi), so |k1|, |k2| <= 1;
+// returns whether that flipped the sign.
+template <typename T>
+bool shear_coefficients(double a, Mat2<T>& m) {
+    bool flip = false;
+    if (a > M_PI / 2) {
+        a -= M_PI;
+        flip = true;
+    } else if (a < -M_PI / 2) {
+        a += M_PI;
+        flip = true;
+    }
+    std::memset(&m, 0, sizeof(m));
+    m.v[0] = (T)-std::tan(a / 2);
+    m.v[1] = (T)std::sin(a);
+    return flip;
+}
+
 template <typename T>
 int upload_mats(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double* params, const Mat2<T>** out) {
     const size_t bytes = std::max<size_t>(pl.mat_total, 1) * sizeof(Mat2<T>);
     if (int rc = stage_mats(s, bytes)) return rc;
     Mat2<T>* h = (Mat2<T>*)s->h_mats;
+    s->rev_flip.assign(pl.passes.size(), 0);
     for (size_t pi = 0; pi < pl.passes.size(); ++pi)
         for (int dir = 0; dir < 2; ++dir) {
             const auto& mg = dir ? pl.ops[pi].rev_mat_gate : pl.ops[pi].fwd_mat_gate;
             Mat2<T>* m = h + pl.mat_off[2 * pi + dir];
             for (size_t i = 0; i < mg.size(); ++i) {
                 const Gate& g = c->gates[mg[i]];
-                fill_matrix(m[i], g, angle_of(g, params), dir == 1);
+                if (dir == 1 && (g.kind == VQE_GATE_RY || g.kind == VQE_GATE_RZ)) {
+                    // the inverse as a rotation: RY^-1 turns (a_0, a_1), RZ^-1 turns
+                    // (Re, Im) of an amplitude with bit 0 (bit 1 by the opposite angle)
+                    Mat2<double> u;
+                    fill_matrix(u, g, angle_of(g, params), true);
+                    const double a = g.kind == VQE_GATE_RY ? std::atan2(u.v[4], u.v[0]) : std::atan2(u.v[1], u.v[0]);
+                    s->rev_flip[pi] ^= (int8_t)shear_coefficients(a, m[i]);
+                } else {
+                    fill_matrix(m[i], g, angle_of(g, params), dir == 1);
+                }
             }
         }
     VQE_HIP(hipMemcpyAsync(s->d_mats, s->h_mats, bytes, hipMemcpyHostToDevice, s->stream));
@@ -1003,10 +1042,15 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
     const Mat2<T>* mats = (const Mat2<T>*)psi->d_mats;  // uploaded by forward()
     PassArgs<T> a;
     JitArgs ja;
+    // Half turns of the sheared rotations flip psi and lam together, so the
+    // gradient terms (bilinear in them) keep their sign until psi is restored
+    // from a checkpoint; from there on they carry the flips made before it.
+    bool flipped = false, grad_neg = false;
     for (size_t pi = P; pi-- > 0;) {
         const void* pin = psi->data;
         for (size_t k = 0; k < bounds.size(); ++k)
             if (bounds[k] == pi + 1) pin = ck[k];
+        if (pl.jit && pin != psi->data) grad_neg = flipped;
         uint32_t gb = 0;
         const uint32_t n_gslots = (uint32_t)pl.ops[pi].slot_param.size();
         ProfScope ps(VQE_KERNEL_WINDOW_REV, 4.0 * (double)psi->bytes, st);
@@ -1021,7 +1065,9 @@ int adjoint_impl(vqe_state* psi, vqe_state* lam, const vqe_circuit* c, const dou
         }
         ps.end();
         if (n_gslots)
-            VQE_HIP(launch_reduce(psi->d_part, gb, n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, 1, st));
+            VQE_HIP(launch_reduce(psi->d_part, gb, n_gslots, pl.d_slotmap + pl.slot_off[pi], d_g, grad_neg ? -1 : 1,
+                                  st));
+        if (pl.jit && psi->rev_flip[pi]) flipped = !flipped;
         if (chunk > 0 && (P - pi) % (size_t)chunk == 0 && pi > 0) VQE_HIP(hipStreamSynchronize(st));
     }
     VQE_HIP(hipMemcpyAsync(psi->h_res, psi->d_res, (2 + c->n_params) * sizeof(double), hipMemcpyDeviceToHost, st));

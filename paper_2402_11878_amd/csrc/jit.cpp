@@ -128,6 +128,24 @@ struct Gen {
                 break;
             case OP_R2:
                 mats(k.slot, false);
+                if (NV == 2 && k.c == 1) {
+                    // un-applied rotation as three shears of each (a_p, a_q) plane,
+                    // coefficients k1 = m[0], k2 = m[1] (shear_coefficients)
+                    o << "    const T k1 = m[0], k2 = m[1];\n";
+                    for (int p = 0; p < N; ++p) {
+                        if (p & (1 << A)) continue;
+                        const int q = p | (1 << A);
+                        for (int v = 0; v < NV; ++v)
+                            o << "    { T xr = " << R(v, p) << ", yr = " << R(v, q) << ", xi = " << I(v, p)
+                              << ", yi = " << I(v, q) << ";\n"
+                              << "      xr += k1 * yr; xi += k1 * yi; yr += k2 * xr; yi += k2 * xi; xr += k1 * yr; "
+                                 "xi += k1 * yi;\n"
+                              << "      " << R(v, p) << " = xr; " << I(v, p) << " = xi; " << R(v, q) << " = yr; "
+                              << I(v, q) << " = yi; }\n";
+                    }
+                    o << "  }\n";
+                    break;
+                }
                 o << "    const T ca = m[0], cb = m[2], cc = m[4], cd = m[6];\n";
                 for (int p = 0; p < N; ++p) {
                     if (p & (1 << A)) continue;
@@ -143,6 +161,25 @@ struct Gen {
                 break;
             case OP_DIAG:
                 mats(k.slot, false);
+                if (NV == 2 && k.c == 1) {
+                    // un-applied phase rotation of (Re, Im) as three shears: k1 = m[0],
+                    // k2 = m[1] for bit 0, the opposite angle (-k1, -k2) for bit 1
+                    if (la)
+                        o << "    const T k1 = " << H(A - KL) << " ? -m[0] : m[0], k2 = " << H(A - KL)
+                          << " ? -m[1] : m[1];\n";
+                    else
+                        o << "    const T k1 = m[0], k2 = m[1], n1 = -m[0], n2 = -m[1];\n";
+                    for (int p = 0; p < N; ++p) {
+                        const char* s1 = (!la && (p & (1 << A))) ? "n1" : "k1";
+                        const char* s2 = (!la && (p & (1 << A))) ? "n2" : "k2";
+                        for (int v = 0; v < NV; ++v)
+                            o << "    { T xr = " << R(v, p) << ", xi = " << I(v, p) << "; xr += " << s1
+                              << " * xi; xi += " << s2 << " * xr; xr += " << s1 << " * xi; " << R(v, p) << " = xr; "
+                              << I(v, p) << " = xi; }\n";
+                    }
+                    o << "  }\n";
+                    break;
+                }
                 if (la)
                     o << "    const T p0r = " << H(A - KL) << " ? m[6] : m[0], p0i = " << H(A - KL)
                       << " ? m[7] : m[1];\n";

@@ -1211,7 +1211,7 @@ reduce_kernel(const double* __restrict__ part, uint32_t nblocks, uint32_t nslots
     }
     if (tid == 0) {
         const int idx = map ? map[s] : (int)s;
-        out[idx] = accumulate ? out[idx] + red[0] : red[0];
+        out[idx] = accumulate > 0 ? out[idx] + red[0] : accumulate < 0 ? out[idx] - red[0] : red[0];
     }
 }
 

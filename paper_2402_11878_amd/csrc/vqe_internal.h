@@ -385,7 +385,8 @@ template <typename T>
 hipError_t launch_expect_term(int n, const void* psi, uint64_t x, uint64_t z, double* part,
                               uint32_t* nblocks, hipStream_t st);
 
-// out[map ? map[s] : s] (+)= sum over blocks of part[block][s], fixed order, FP64.
+// out[map ? map[s] : s] = (accumulate 0), += (1) or -= (-1) the sum over blocks
+// of part[block][s], fixed order, FP64.
 hipError_t launch_reduce(const double* part, uint32_t nblocks, uint32_t nslots,
                          const int32_t* map, double* out, int accumulate, hipStream_t st);
 

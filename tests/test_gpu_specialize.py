@@ -172,3 +172,48 @@ def test_prepare_then_evaluate(dt):
         _lib.vqe_circuit_free(c1)
         _lib.vqe_circuit_free(c2)
         _lib.vqe_hamiltonian_free(h)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_sheared_rotations_at_any_angle_with_checkpoints(dt):
+    """The specialised reverse kernels un-apply RY and RZ as three shears
+    after a half turn for |angle| > pi, which flips the sign of psi and lam
+    together; after a checkpoint restore only lam carries the flips and the
+    host corrects the gradient sign.  Angles in (-4 pi, 4 pi) (most rotations
+    take the half turn) and multiples of pi / 2 (the range edges), with 0, 1
+    and 3 checkpoints: every gradient against the oracle, and the checkpoint
+    counts against each other."""
+    dtype = DT[dt]
+    n = 12
+    arr, P = ansatz.layered(n, 4), 8 * n
+    rnd, P2 = random_circuit(n, 40, 91)
+    rnd["param_index"][rnd["param_index"] >= 0] += P
+    arr = np.concatenate([arr, rnd])
+    P += P2
+    rng = np.random.default_rng(92)
+    th = rng.uniform(-4 * np.pi, 4 * np.pi, P)
+    th[::5] = (np.pi / 2) * rng.integers(-8, 9, size=len(th[::5]))
+    H = _random_pauli_sum(n, 30, 93)
+    x, z, w = oham.to_masks(H)
+    E_ref, g_ref = ogr.adjoint(n, oracle_gates(arr), th, H)
+    gscale = max(np.max(np.abs(g_ref)), 1.0)
+    h = _lib.vqe_hamiltonian_create(n, x, z, w)
+    c = _lib.vqe_circuit_create(n, arr)
+    s, l = Dev(n, dtype), Dev(n, dtype)
+    cks = [Dev(n, dtype) for _ in range(3)]
+    say(f"case sheared rotations n={n} {dt}")
+    try:
+        _lib.vqe_set_specialize(_lib.SPECIALIZE_ALWAYS)
+        res = []
+        for k in (0, 1, 3):
+            E, g = _lib.vqe_energy_grad(s.h, l.h, c, th, h, ckpt=[d.h for d in cks[:k]])
+            assert rel_err(E, E_ref) <= tol_energy(dtype), (k, E, E_ref)
+            assert np.max(np.abs(g - g_ref)) / gscale <= GRAD_TOL[dtype], (k, np.max(np.abs(g - g_ref)) / gscale)
+            res.append(g)
+        for g in res[1:]:
+            assert np.max(np.abs(g - res[0])) / gscale <= (1e-12 if dtype == _lib.VQE_C128 else 2e-5)
+    finally:
+        for d in [s, l] + cks:
+            d.free()
+        _lib.vqe_circuit_free(c)
+        _lib.vqe_hamiltonian_free(h)
