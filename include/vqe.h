@@ -226,7 +226,7 @@ int vqe_hamiltonian_info(const vqe_hamiltonian* h, size_t* n_terms, size_t* n_gr
 
 /* energy = <psi|H|psi> / <psi|psi>  (eq. 7); norm (nullable) = <psi|psi>.
  * mode VQE_EXPECT_GROUPED serves every Z pattern of an X-mask group from one
- * read of the partner amplitudes: either m passes over 12-qubit windows (the
+ * read of the partner amplitudes: either m passes over 13-qubit windows (the
  * window form of vqe_hamiltonian_plan, reading psi once per pass, m S in
  * all), when that reads less than the tile form, or one sweep over tiles of
  * 1024 amplitudes that reads each distinct out-of-tile partner tile once per
@@ -302,7 +302,7 @@ int vqe_energy_grad(vqe_state* psi, vqe_state* lam, const vqe_circuit* c,
  *   item); the gates are fused into passes over 10-qubit windows, and one
  *   launch applies pass k of every item that has one, a workgroup staging
  *   one 2^10-amplitude tile of a window in LDS at a time; then lam = H psi
- *   and the energy (the 12-qubit window passes of each Hamiltonian, one
+ *   and the energy (the 13-qubit window passes of each Hamiltonian, one
  *   launch per pass index, or one tile launch for Hamiltonians without a
  *   window cover), the reverse passes likewise, and one launch reducing
  *   per-block partial sums.
@@ -372,15 +372,17 @@ int vqe_profile_read(int kind, uint64_t* launches, double* total_ms, double* byt
  *   Tile form (*n_windows = 0): one sweep over tiles of 1024 amplitudes that
  *     reads the partner tile of every distinct out-of-tile x: (1 + D) S read,
  *     S written (D = distinct non-zero x >> 10, S = state bytes).
- *   Window form (*n_windows = m > 0): m passes over 12-qubit windows that
+ *   Window form (*n_windows = m > 0): m passes over 13-qubit windows that
  *     all contain qubits 0..2, every X group inside one window; a pass reads
  *     psi and writes lam (the first) or reads and writes it (the others):
- *     (3 m - 1) S.  Chosen when it moves fewer bytes; n >= 12 only.  Terms
+ *     (3 m - 1) S.  Chosen when it moves fewer bytes; n >= VQE_HPSI_WINDOW_QUBITS
+ *     only.  Terms
  *     of a group with equal z bits inside the window share one coefficient
  *     per coset (a class); a window with more than 512 classes takes several
  *     passes over the same qubits.
  * window_masks (capacity entries, may be NULL) receives each pass's qubit
  * mask in pass order. */
+#define VQE_HPSI_WINDOW_QUBITS 13
 int vqe_hamiltonian_plan(const vqe_hamiltonian* h, size_t* n_windows, uint64_t* window_masks, size_t capacity);
 
 /* ------------------------------------------------------------------ kernel form

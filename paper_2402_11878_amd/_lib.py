@@ -52,6 +52,7 @@ class vqe_batch_item(C.Structure):
 
 BATCH_MAX_QUBITS = {1: 13, 2: 12}  # whole state in LDS (complex64, complex128)
 BATCH_MAX_QUBITS_MID = 24          # larger items run as tile passes, up to this size
+HPSI_WINDOW_QUBITS = 13            # qubits per window pass of H psi
 
 GATE_DTYPE = np.dtype([("kind", "u1"), ("q0", "u1"), ("q1", "u1"), ("q2", "u1"), ("q3", "u1"),
                        ("reserved", "u1", (3,)), ("param_index", "<i4"), ("reserved2", "<i4"),

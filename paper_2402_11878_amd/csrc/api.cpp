@@ -798,13 +798,15 @@ int upload_mats(vqe_state* s, const vqe_circuit* c, const Plan& pl, const double
             Mat2<T>* m = h + pl.mat_off[2 * pi + dir];
             for (size_t i = 0; i < mg.size(); ++i) {
                 const Gate& g = c->gates[mg[i]];
-                if (dir == 1 && (g.kind == VQE_GATE_RY || g.kind == VQE_GATE_RZ || is_excitation(g.kind))) {
-                    // the inverse as a rotation: RY^-1 turns (a_0, a_1) and an excitation's
-                    // inverse each (A, B) pattern pair, RZ^-1 turns (Re, Im) of an amplitude
-                    // with bit 0 (bit 1 by the opposite angle)
+                if (dir == 1 && (g.kind == VQE_GATE_RY || g.kind == VQE_GATE_RZ)) {
+                    // the inverse as a rotation: RY^-1 turns (a_0, a_1), RZ^-1 turns
+                    // (Re, Im) of an amplitude with bit 0 (bit 1 by the opposite angle).
+                    // Every amplitude takes part, so a half turn is a sign on the whole
+                    // state; an excitation turns only its (A, B) patterns, where a half
+                    // turn would not be, so excitations keep the matrix form.
                     Mat2<double> u;
                     fill_matrix(u, g, angle_of(g, params), true);
-                    const double a = g.kind == VQE_GATE_RZ ? std::atan2(u.v[1], u.v[0]) : std::atan2(u.v[4], u.v[0]);
+                    const double a = g.kind == VQE_GATE_RY ? std::atan2(u.v[4], u.v[0]) : std::atan2(u.v[1], u.v[0]);
                     s->rev_flip[pi] ^= (int8_t)shear_coefficients(a, m[i]);
                 } else {
                     fill_matrix(m[i], g, angle_of(g, params), dir == 1);

@@ -245,24 +245,6 @@ struct Gen {
                 uint32_t mask, PA, PB;
                 pair_patterns(k, mask, PA, PB);
                 mats(k.slot, false);
-                if (NV == 2) {
-                    // un-applied excitation: a rotation of each (A, B) pattern pair, as
-                    // three shears (k1 = m[0], k2 = m[1]; shear_coefficients)
-                    o << "    const T k1 = m[0], k2 = m[1];\n";
-                    for (int p = 0; p < N; ++p) {
-                        if ((p & (int)mask) != (int)PA) continue;
-                        const int q = p ^ (int)PA ^ (int)PB;
-                        for (int v = 0; v < NV; ++v)
-                            o << "    { T xr = " << R(v, p) << ", yr = " << R(v, q) << ", xi = " << I(v, p)
-                              << ", yi = " << I(v, q) << ";\n"
-                              << "      xr += k1 * yr; xi += k1 * yi; yr += k2 * xr; yi += k2 * xi; xr += k1 * yr; "
-                                 "xi += k1 * yi;\n"
-                              << "      " << R(v, p) << " = xr; " << I(v, p) << " = xi; " << R(v, q) << " = yr; "
-                              << I(v, q) << " = yi; }\n";
-                    }
-                    o << "  }\n";
-                    break;
-                }
                 o << "    const T ca = m[0], cb = m[2], cc = m[4], cd = m[6];\n";
                 for (int p = 0; p < N; ++p) {
                     if ((p & (int)mask) != (int)PA) continue;

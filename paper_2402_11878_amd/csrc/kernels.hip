@@ -835,7 +835,7 @@ hpsi_kernel(int n, int tb, uint32_t tpb, const typename VecOf<T>::type* __restri
 // thread then sums its classes' A, signed by the thread part of their z
 // bits, into one bucket per register part, and a Walsh-Hadamard transform of
 // the R bucket sums gives D_x for its R patterns.
-constexpr int kHwThreads = 1 << kHwThreadBits;  // 16 waves per CU at two blocks
+constexpr int kHwThreads = 1 << kHwThreadBits;  // 16 waves per CU at one block
 
 // (-1)^cnt as a floating-point factor: the sign bit set from the low bit of
 // cnt on the bit pattern of 1.0.

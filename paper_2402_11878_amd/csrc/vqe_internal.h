@@ -284,9 +284,13 @@ size_t jit_cached();
 // register part, and the classes of a group are sorted into buckets by the
 // register part, whose 2^(kHwBits - kHwThreadBits) bucket sums give D for
 // every r through one Walsh-Hadamard transform.
-constexpr int kHwBits = 12;
+// 13-qubit windows measured faster than 12 on both 32-qubit workloads (Hubbard
+// 4 passes instead of 5, molecule-shaped 21 instead of 26) at the same 16 waves
+// per CU (one 1024-thread block with a 128 KiB complex128 coset in LDS).
+constexpr int kHwBits = 13;
+static_assert(kHwBits == VQE_HPSI_WINDOW_QUBITS, "public and internal window sizes differ");
 constexpr int kHwLow = 3;
-constexpr int kHwThreadBits = 9;        // 512 threads per block
+constexpr int kHwThreadBits = 10;       // 1024 threads per block
 constexpr int kHwRegBits = kHwBits - kHwThreadBits;
 constexpr int kHwMaxClasses = 512;      // classes per pass (their coefficients are staged in LDS)
 

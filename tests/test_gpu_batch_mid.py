@@ -191,7 +191,7 @@ def _pauli_sum_masks(n, n_terms, seed, max_flip, long_x=False):
     """Random Pauli sum as (x, z, w) masks: each term flips (X or Y) at most
     max_flip qubits, with Z on some others, so Y counts are odd and even
     (complex and real folded coefficients); long_x adds X on every qubit,
-    which no 12-qubit window holds."""
+    which no window holds."""
     rng = np.random.default_rng(seed)
     x, z, w = [], [], []
     for _ in range(n_terms):

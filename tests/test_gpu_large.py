@@ -156,7 +156,7 @@ def test_bench_configuration_32q_clifford():
     h = _lib.vqe_hamiltonian_create(n, x, z, w)
     c = _lib.vqe_circuit_create(n, arr)
     try:
-        assert len(_lib.vqe_hamiltonian_plan(h)) == 5
+        assert len(_lib.vqe_hamiltonian_plan(h)) == 4
         for dt, n_ck, te, tg in ((_lib.VQE_C128, 1, 1e-10, 1e-9), (_lib.VQE_C64, 4, 1e-5, 1e-4)):
             say(f"case bench configuration 32q dtype={dt} checkpoints={n_ck}")
             bufs = [Dev(n, dt) for _ in range(2 + n_ck)]

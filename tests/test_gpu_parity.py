@@ -279,27 +279,31 @@ def _split_window_masks(n=14, seed=11):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("case", ["chain8", "ladder2x4", "molecule7", "split", "chain6_12q", "chain6_13q"])
+@pytest.mark.parametrize("case", ["chain8", "ladder2x4", "molecule7", "split", "chain6_13q", "chain7_14q"])
 def test_apply_hamiltonian_window_form(case, dt):
-    """lam = H psi and the energy by window passes (12-qubit windows over the
+    """lam = H psi and the energy by window passes (13-qubit windows over the
     X groups) against the oracle's term-by-term H psi, element by element;
     "split" takes two passes over one window (more classes than a pass holds);
-    at 12 qubits one pass holds one coset (a one-block grid), at 13 qubits two
-    passes hold two cosets each.  The grouped energy-only sweep (eq. 7) runs
-    over the same windows without lam and must match the oracle's energy."""
+    at 13 qubits one pass holds one coset (a one-block grid), at 14 qubits
+    with an X mask on every qubit two passes hold two cosets each.  The
+    grouped energy-only sweep (eq. 7) runs over the same windows without lam
+    and must match the oracle's energy."""
     dtype = DT[dt]
     if case == "split":
         n = 14
         H = oham.from_masks(n, *_split_window_masks(n))
-    elif case == "chain6_12q":
-        n, H = 12, oham.hubbard(6, synth.chain_bonds(6), 1.0, 4.0)
     elif case == "chain6_13q":
         n = 13
         x, z, w = oham.to_masks(oham.hubbard(6, synth.chain_bonds(6), 1.0, 4.0))
-        x = np.concatenate([x, np.array([(1 << 10) | 1, (1 << 11) | 2, (1 << 12) | 1, (3 << 10) | 4, (5 << 10) | 8],
-                                        np.uint64)])
-        z = np.concatenate([z, np.array([0, 1 << 12, 0b101, 1 << 11, 3], np.uint64)])
-        w = np.concatenate([w, [0.3, -0.2, 0.15, 0.1, -0.25]])
+        H = oham.from_masks(n, x, z, w)
+    elif case == "chain7_14q":
+        n = 14
+        x, z, w = oham.to_masks(oham.hubbard(7, synth.chain_bonds(7), 1.0, 4.0))
+        # X on every qubit 3..13 (paired with qubit 0): no single 13-qubit window
+        # (all but one qubit) holds them all
+        x = np.concatenate([x, np.array([(1 << q) | 1 for q in range(3, 14)], np.uint64)])
+        z = np.concatenate([z, np.array([(1 << (q - 1)) for q in range(3, 14)], np.uint64)])
+        w = np.concatenate([w, 0.1 * np.arange(1, 12) * (-1.0) ** np.arange(11)])
         H = oham.from_masks(n, x, z, w)
     elif case == "chain8":
         n, H = 16, oham.hubbard(8, synth.chain_bonds(8), 1.0, 4.0)
@@ -322,9 +326,9 @@ def test_apply_hamiltonian_window_form(case, dt):
     assert len(plan) >= 1
     if case == "split":
         assert len(plan) == 2 and plan[0] == plan[1]
-    if case == "chain6_12q":
-        assert plan == [(1 << 12) - 1]
     if case == "chain6_13q":
+        assert plan == [(1 << 13) - 1]
+    if case == "chain7_14q":
         assert len(plan) == 2
     c = _lib.vqe_circuit_create(n, arr)
     s, l = Dev(n, dtype), Dev(n, dtype)

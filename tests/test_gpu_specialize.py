@@ -179,7 +179,8 @@ def test_sheared_rotations_at_any_angle_with_checkpoints(dt):
     """The specialised reverse kernels un-apply RY and RZ as three shears
     after a half turn for |angle| > pi, which flips the sign of psi and lam
     together; after a checkpoint restore only lam carries the flips and the
-    host corrects the gradient sign.  Angles in (-4 pi, 4 pi) (most rotations
+    host corrects the gradient sign.  Excitation gates at the same angles
+    (matrix form) share the passes.  Angles in (-4 pi, 4 pi) (most rotations
     take the half turn) and multiples of pi / 2 (the range edges), with 0, 1
     and 3 checkpoints: every gradient against the oracle, and the checkpoint
     counts against each other."""
@@ -188,8 +189,10 @@ def test_sheared_rotations_at_any_angle_with_checkpoints(dt):
     arr, P = ansatz.layered(n, 4), 8 * n
     rnd, P2 = random_circuit(n, 40, 91)
     rnd["param_index"][rnd["param_index"] >= 0] += P
-    arr = np.concatenate([arr, rnd])
-    P += P2
+    exc, P3 = ansatz.excitations(n, 4)  # excitations keep the matrix form: no half turns there
+    exc["param_index"][exc["param_index"] >= 0] += P + P2
+    arr = np.concatenate([arr, rnd, exc])
+    P += P2 + P3
     rng = np.random.default_rng(92)
     th = rng.uniform(-4 * np.pi, 4 * np.pi, P)
     th[::5] = (np.pi / 2) * rng.integers(-8, 9, size=len(th[::5]))

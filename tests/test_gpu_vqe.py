@@ -106,12 +106,12 @@ def test_cutoff_ratio_on_device():
         _lib.vqe_circuit_free(c)
 
 
-def test_vqe_window_form_12_qubits():
+def test_vqe_12_qubits():
     """12 qubits (6-site Hubbard chain, 2 electrons, one S/D layer from
-    Hartree-Fock), where lam = H psi runs as one window pass: BFGS with the
-    device gradient; at its final angles the oracle's energy and adjoint
-    gradient agree with the device's, and the energy lies between the sector's
-    lowest eigenvalue and the Hartree-Fock energy."""
+    Hartree-Fock), below the window size, so lam = H psi runs in the tile
+    form: BFGS with the device gradient; at its final angles the oracle's
+    energy and adjoint gradient agree with the device's, and the energy lies
+    between the sector's lowest eigenvalue and the Hartree-Fock energy."""
     from gpu_util import Dev
     n, ne = 12, 2
     wl = synth.WORKLOADS["hubbard1d_6"]
@@ -124,9 +124,9 @@ def test_vqe_window_form_12_qubits():
     c = _lib.vqe_circuit_create(n, arr)
     h = _lib.vqe_hamiltonian_create(n, x, z, w)
     s, l = Dev(n, _lib.VQE_C128), Dev(n, _lib.VQE_C128)
-    say("case vqe n=12 window form")
+    say("case vqe n=12 tile form")
     try:
-        assert _lib.vqe_hamiltonian_plan(h) == [(1 << 12) - 1]
+        assert _lib.vqe_hamiltonian_plan(h) == []
         r = vqe.minimize(n, c, h, np.full(P, 0.05), method="BFGS")
         assert E0 - 1e-10 <= r["energy"] < E_hf - 1e-3, (E0, r["energy"], E_hf)
         E_d, g_d = _lib.vqe_energy_grad(s.h, l.h, c, r["theta"], h)

@@ -421,8 +421,9 @@ def test_cutoff_ratio_rule():
 @pytest.mark.parametrize("name,th", [("hubbard4x4", None), ("hubbard2x7", None), ("molecule_10", 1e-3),
                                      ("molecule_10", 0.0)])
 def test_hamiltonian_window_plan_valid(name, th):
-    """Window form of H psi: 12-qubit windows holding qubits 0..2, every X mask
-    inside some window, chosen only when (3 m - 1) S < (D + 2) S."""
+    """Window form of H psi: windows of HPSI_WINDOW_QUBITS qubits holding qubits
+    0..2, every X mask inside some window, chosen only when (3 m - 1) S <
+    (D + 2) S."""
     wl = synth.WORKLOADS[name]
     if wl.kind == "molecule":
         h, g = synth.molecule_integrals(wl.n_orb, wl.integral_seed)
@@ -440,7 +441,7 @@ def test_hamiltonian_window_plan_valid(name, th):
     assert wins, "expected the window form for this Hamiltonian"
     assert 3 * len(wins) - 1 < D + 2
     for W in wins:
-        assert bin(W).count("1") == 12 and W & 0b111 == 0b111 and W < (1 << wl.n_qubits)
+        assert bin(W).count("1") == _lib.HPSI_WINDOW_QUBITS and W & 0b111 == 0b111 and W < (1 << wl.n_qubits)
     for xm in np.unique(x).tolist():
         assert any(int(xm) & ~W == 0 for W in wins)
 
@@ -461,17 +462,21 @@ def test_hamiltonian_window_plan_splits_classes():
         _lib.vqe_hamiltonian_free(h)
     assert len(plan) == 2 and plan[0] == plan[1]
     high = 0b1111 << 10  # every x lies in qubits 0 and 10..13
-    assert plan[0] & (high | 0b111) == high | 0b111 and bin(plan[0]).count("1") == 12
+    assert plan[0] & (high | 0b111) == high | 0b111 and bin(plan[0]).count("1") == _lib.HPSI_WINDOW_QUBITS
     assert 512 < len({int(zi) & plan[0] for zi in z[:700]}) <= 1024
 
 
 def test_hamiltonian_window_plan_small_n():
-    """At 12 qubits one window holds every qubit (one pass, 2 S); below 12
-    qubits H psi keeps the tile form."""
+    """At the window size (13 qubits) one window holds every qubit (one pass,
+    2 S); below it H psi keeps the tile form."""
+    k = _lib.HPSI_WINDOW_QUBITS
     wl = synth.WORKLOADS["hubbard1d_6"]
     x, z, w = lham.from_lattice(wl.lattice)
-    h = _lib.vqe_hamiltonian_create(wl.n_qubits, x, z, w)
-    assert _lib.vqe_hamiltonian_plan(h) == [(1 << 12) - 1]
+    h = _lib.vqe_hamiltonian_create(k, x, z, w)  # the 12-qubit chain on k qubits (the top ones idle)
+    assert _lib.vqe_hamiltonian_plan(h) == [(1 << k) - 1]
+    _lib.vqe_hamiltonian_free(h)
+    h = _lib.vqe_hamiltonian_create(k - 1, x, z, w)
+    assert _lib.vqe_hamiltonian_plan(h) == []
     _lib.vqe_hamiltonian_free(h)
     h = _lib.vqe_hamiltonian_create(10, np.array([1, 3], np.uint64), np.array([0, 2], np.uint64), np.array([1.0, 0.5]))
     assert _lib.vqe_hamiltonian_plan(h) == []
@@ -481,9 +486,9 @@ def test_hamiltonian_window_plan_small_n():
 def test_hamiltonian_window_plan_deterministic_and_compact():
     """The window cover is a deterministic function of the Hamiltonian (its
     restarts use a fixed seeded stream) and keeps the pass counts reached by
-    the multi-start greedy: 5 for the 32-qubit Hubbard step, 4 at 28 qubits,
-    at most 26 for the 32-qubit molecule-shaped Hamiltonian slimmed at 1e-3."""
-    cases = [("hubbard4x4", None, 5), ("hubbard2x7", None, 4), ("molecule_16", 1e-3, 26)]
+    the multi-start greedy: 4 for the 32-qubit Hubbard step, 4 at 28 qubits,
+    at most 21 for the 32-qubit molecule-shaped Hamiltonian slimmed at 1e-3."""
+    cases = [("hubbard4x4", None, 4), ("hubbard2x7", None, 4), ("molecule_16", 1e-3, 21)]
     for name, th, most in cases:
         wl = synth.WORKLOADS[name]
         if wl.kind == "molecule":
