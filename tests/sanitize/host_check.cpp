@@ -128,7 +128,7 @@ static void check_hamiltonian(int n, const std::vector<uint64_t>& x, const std::
     EXPECT(vqe_hamiltonian_plan(h, &nw, nullptr, 0) == VQE_OK);
     std::vector<uint64_t> masks(nw + 1);
     EXPECT(vqe_hamiltonian_plan(h, &nw, masks.data(), masks.size()) == VQE_OK);
-    for (size_t i = 0; i < nw; ++i) EXPECT(__builtin_popcountll(masks[i]) == 12 && (masks[i] & 7) == 7);
+    for (size_t i = 0; i < nw; ++i) EXPECT(__builtin_popcountll(masks[i]) == VQE_HPSI_WINDOW_QUBITS && (masks[i] & 7) == 7);
     if (nw) EXPECT(vqe_hamiltonian_plan(h, &nw, masks.data(), nw - 1) == VQE_ERR_ARG);
     EXPECT(vqe_hamiltonian_free(h) == VQE_OK);
 }
@@ -159,7 +159,7 @@ static void hamiltonians() {
         z.push_back(rng() & ((1ull << 20) - 1));
         w.push_back(nd(rng));
     }
-    for (int q = 12; q < 20; ++q) {
+    for (int q = VQE_HPSI_WINDOW_QUBITS; q < 20; ++q) {
         x.push_back(1ull << q);
         z.push_back(0);
         w.push_back(0.5);
