@@ -367,7 +367,7 @@ std::vector<uint64_t> cover_windows(int n, const std::vector<uint64_t>& xs, uint
 // Window-pass plan of lam = H psi (see HwDesc): the smallest of several
 // greedy covers (cover_windows with p = 1, 2, 3, each deterministic and
 // with seeded tie perturbations, as many restarts as a fixed work budget
-// allows); each group goes to the first window holding its X mask.  Used for
+// allows); the groups spread evenly over the windows holding them.  Used for
 // lam = H psi if its (3 m - 1) S of traffic (m passes; psi read per pass, lam
 // written once and read-modify-written m - 1 times) is below the tile
 // kernel's (D + 2) S, and for the energy-only sweep if its m S (psi read per
@@ -397,13 +397,52 @@ void plan_hwin(vqe_hamiltonian* h) {
         }
         if (work > kWorkBudget) break;
     }
-    std::vector<int> win_of(G, -1);
+    // Each group goes to one of the windows holding its X mask.  A pass costs
+    // about the larger of its memory time and a fixed amount of arithmetic per
+    // group (the per-group bodies dominate; the class count matters little),
+    // so the groups are spread evenly: those only one window holds first, then
+    // the others, the most constrained first, each to the holding window where
+    // it adds the least cost, max(kHwPassGroups x passes, groups) with passes =
+    // ceil(classes / kHwMaxClasses); ties go to the window with fewer groups,
+    // then fewer classes, then the lower index.
+    constexpr size_t kHwPassGroups = 16;  // groups per pass whose arithmetic about matches its memory time
+    const size_t Wn = wins.size();
+    std::vector<std::vector<std::pair<int, size_t>>> cand(G);  // (window, classes of the group in it)
+    std::vector<uint64_t> zw;
     for (size_t g = 0; g < G; ++g)
-        for (size_t wi = 0; wi < wins.size(); ++wi)
-            if ((h->groups[g].x & ~wins[wi]) == 0) {
-                win_of[g] = (int)wi;
-                break;
+        for (size_t wi = 0; wi < Wn; ++wi) {
+            if (h->groups[g].x & ~wins[wi]) continue;
+            zw.clear();
+            for (uint32_t t = h->groups[g].begin; t < h->groups[g].end; ++t) zw.push_back(h->t64[t].z & wins[wi]);
+            std::sort(zw.begin(), zw.end());
+            cand[g].emplace_back((int)wi, (size_t)(std::unique(zw.begin(), zw.end()) - zw.begin()));
+        }
+    std::vector<size_t> order(G);
+    for (size_t g = 0; g < G; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cand[a].size() < cand[b].size(); });
+    std::vector<size_t> w_groups(Wn, 0), w_classes(Wn, 0);
+    auto w_cost = [&](size_t groups, size_t classes) {
+        const size_t passes = std::max<size_t>(1, (classes + kHwMaxClasses - 1) / kHwMaxClasses);
+        return std::max(kHwPassGroups * passes, groups);
+    };
+    std::vector<int> win_of(G, -1);
+    for (size_t g : order) {
+        int best = -1;
+        size_t best_add = 0, best_cls = 0;
+        for (const auto& [wi, cls] : cand[g]) {
+            const size_t add = w_cost(w_groups[wi] + 1, w_classes[wi] + cls) - w_cost(w_groups[wi], w_classes[wi]);
+            if (best < 0 || add < best_add ||
+                (add == best_add && (w_groups[wi] < w_groups[best] ||
+                                     (w_groups[wi] == w_groups[best] && w_classes[wi] + cls < w_classes[best] + best_cls)))) {
+                best = wi;
+                best_add = add;
+                best_cls = cls;
             }
+        }
+        win_of[g] = best;
+        w_groups[best] += 1;
+        w_classes[best] += best_cls;
+    }
     // Passes: per window its groups, the terms of a group merged into classes
     // of equal in-window z bits and sorted by them (register part first), at
     // most kHwMaxClasses classes per pass.  A window with more classes takes

@@ -487,8 +487,9 @@ def test_hamiltonian_window_plan_deterministic_and_compact():
     """The window cover is a deterministic function of the Hamiltonian (its
     restarts use a fixed seeded stream) and keeps the pass counts reached by
     the multi-start greedy: 4 for the 32-qubit Hubbard step, 4 at 28 qubits,
-    at most 21 for the 32-qubit molecule-shaped Hamiltonian slimmed at 1e-3."""
-    cases = [("hubbard4x4", None, 4), ("hubbard2x7", None, 4), ("molecule_16", 1e-3, 21)]
+    at most 20 for the 32-qubit molecule-shaped Hamiltonian slimmed at 1e-3
+    (its groups spread so that no window overflows one pass's classes)."""
+    cases = [("hubbard4x4", None, 4), ("hubbard2x7", None, 4), ("molecule_16", 1e-3, 20)]
     for name, th, most in cases:
         wl = synth.WORKLOADS[name]
         if wl.kind == "molecule":
