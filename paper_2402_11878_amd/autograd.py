@@ -1,11 +1,13 @@
 """torch.autograd.Function for the VQE energy E(theta) = <psi|H|psi>/<psi|psi>
 (eq. 7) whose backward is the adjoint gradient computed by libvqe.so.
 
-The forward call runs one fused forward sweep, lam = H psi and the reverse
-sweep, so the gradient is ready when backward is called (about three circuit
-costs in all, against 2P + 1 circuit runs for parameter shift).  State
-buffers are kept in a workspace keyed by (qubits, dtype, checkpoints) and
-reused across calls.
+When theta needs a gradient, the forward call runs one fused forward sweep,
+lam = H psi and the reverse sweep, so the gradient is ready when backward is
+called (about three circuit costs in all, against 2P + 1 circuit runs for
+parameter shift).  Otherwise (theta without requires_grad, or under
+torch.no_grad) it runs the forward sweep and the grouped energy only (eq. 7),
+about one circuit cost.  State buffers are kept in a workspace keyed by
+(qubits, dtype, checkpoints) and reused across calls.
 """
 from __future__ import annotations
 
@@ -55,6 +57,8 @@ class EnergyFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, hamiltonian, circuit, dtype="c64", n_ckpt=0, workspace=None):
         ws = workspace or default_workspace()
+        if not ctx.needs_input_grad[0]:
+            return _energy_only(theta, hamiltonian, circuit, dtype, ws)
         states = ws.get(circuit.n, dtype, n_ckpt)
         th = theta.detach().to("cpu", torch.float64).numpy()
         E, g = _lib.vqe_energy_grad(states[0].handle, states[1].handle, circuit.handle, th, hamiltonian.handle,
@@ -68,5 +72,19 @@ class EnergyFn(torch.autograd.Function):
         return grad_out * g, None, None, None, None, None
 
 
+def _energy_only(theta, hamiltonian, circuit, dtype, ws):
+    """E(theta) without the gradient: psi = U(theta)|0...0>, then the grouped
+    energy <psi|H|psi>/<psi|psi>."""
+    psi = ws.get(circuit.n, dtype, 0)[0]
+    th = theta.detach().to("cpu", torch.float64).numpy()
+    _lib.vqe_state_set_basis(psi.handle, 0)
+    _lib.vqe_apply_circuit(psi.handle, circuit.handle, th)
+    E, _ = _lib.vqe_expect_pauli(psi.handle, hamiltonian.handle, _lib.EXPECT_GROUPED)
+    return torch.tensor(E, dtype=theta.dtype, device=theta.device)
+
+
 def energy(theta, hamiltonian, circuit, dtype="c64", n_ckpt=0, workspace=None):
+    """E(theta); the adjoint sweep runs only when theta needs a gradient."""
+    if not (torch.is_grad_enabled() and theta.requires_grad):
+        return _energy_only(theta, hamiltonian, circuit, dtype, workspace or default_workspace())
     return EnergyFn.apply(theta, hamiltonian, circuit, dtype, n_ckpt, workspace)

@@ -32,17 +32,21 @@ __device__ __forceinline__ uint32_t ins0(uint32_t k, uint32_t q) {
     return ((k ^ low) << 1) | low;
 }
 
-// Fixed-tree block sum (all threads participate; returns the total to all).
+// Block sum of NT threads in a fixed order: butterflies within each wave
+// (every lane ends with the same bits, addition being commutative), then the
+// wave totals in wave order; every thread gets the total.  red holds NT / 64
+// doubles of LDS.
+template <int NT>
 __device__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int t = threadIdx.x;
-    red[t] = v;
+    __syncthreads();  // earlier readers of red are done
+    if ((t & 63) == 0) red[t >> 6] = v;
     __syncthreads();
-    for (int w = kBT / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) r += red[w];
     return r;
 }
 
@@ -164,7 +168,7 @@ batch_kernel(const BatchDesc<T>* __restrict__ items, const BatchGate* __restrict
              const Mat2<T>* __restrict__ mats, double* __restrict__ out) {
     using V = typename VecB<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kBT];
+    __shared__ double red[kBT / 64];
     const BatchDesc<T> d = items[blockIdx.x];
     const int n = d.n;
     const uint32_t dim = 1u << n;
@@ -210,8 +214,8 @@ batch_kernel(const BatchDesc<T>* __restrict__ items, const BatchGate* __restrict
         n_acc += (double)(p.x * p.x + p.y * p.y);
     }
     __syncthreads();
-    const double E = block_sum(e_acc, red);
-    const double nrm = block_sum(n_acc, red);
+    const double E = block_sum<kBT>(e_acc, red);
+    const double nrm = block_sum<kBT>(n_acc, red);
     if (t == 0) o[0] = E / nrm;
     for (uint32_t k = t; k < d.n_params; k += kBT) o[1 + k] = 0.0;
     __syncthreads();
@@ -219,7 +223,7 @@ batch_kernel(const BatchDesc<T>* __restrict__ items, const BatchGate* __restrict
     for (uint32_t gi = d.n_gates; gi-- > 0;) {
         const BatchGate g = gates[d.gate_off + gi];
         if (g.pidx >= 0) {
-            const double gsum = block_sum((double)grad_part<kBT, T>(psi, lam, n, g), red);
+            const double gsum = block_sum<kBT>((double)grad_part<kBT, T>(psi, lam, n, g), red);
             if (t == 0) o[1 + g.pidx] += gsum / nrm;
         }
         const T* m = mats[d.mat_off + g.mat].v;
@@ -243,21 +247,6 @@ constexpr int kMT = 256;                       // threads per block
 constexpr int kMidTile = 1 << kMidWin;         // amplitudes per coset
 constexpr int kMidPer = kMidTile / kMT;        // ... per thread
 static_assert(kMidPer == 4, "two register bits per thread");
-
-// Block sum in a fixed order: butterflies within each wave (every lane ends
-// with the same bits, addition being commutative), then the waves in order.
-__device__ double mid_block_sum(double v, double* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int t = threadIdx.x;
-    __syncthreads();  // earlier readers of red are done
-    if ((t & 63) == 0) red[t >> 6] = v;
-    __syncthreads();
-    double r = red[0];
-#pragma unroll
-    for (int w = 1; w < kMT / 64; ++w) r += red[w];
-    return r;
-}
 
 // Index of the descriptor that owns block b: the last one with blk_begin <= b.
 template <typename D>
@@ -327,7 +316,7 @@ mid_pass_kernel(const MidPass* __restrict__ descs, uint32_t n_desc, const BatchG
             for (uint32_t gi = d.n_gates; gi-- > 0;) {
                 const BatchGate g = gates[d.gate_off + gi];
                 if (g.pidx >= 0) {
-                    const double v = mid_block_sum((double)grad_part<kMT, T>(sp, sl, kMidWin, g), red);
+                    const double v = block_sum<kMT>((double)grad_part<kMT, T>(sp, sl, kMidWin, g), red);
                     if (t == 0) acc[s] += v;
                     ++s;
                 }
@@ -388,8 +377,8 @@ mid_hpsi_kernel(const MidHam* __restrict__ descs, uint32_t n_desc, double* __res
             n_acc += (double)(p.x * p.x + p.y * p.y);
         }
     }
-    const double e = mid_block_sum(e_acc, red);
-    const double nn = mid_block_sum(n_acc, red);
+    const double e = block_sum<kMT>(e_acc, red);
+    const double nn = block_sum<kMT>(n_acc, red);
     if (t == 0) {
         part[d.part_off + blk] = e;
         part[d.part_off + d.n_blk + blk] = nn;
@@ -402,7 +391,7 @@ mid_reduce_kernel(const MidRed* __restrict__ r, const double* __restrict__ part,
     const MidRed d = r[blockIdx.x];
     double s = 0.0;
     for (uint32_t i = threadIdx.x; i < d.count; i += kMT) s += part[d.part_off + i];
-    const double tot = mid_block_sum(s, red);
+    const double tot = block_sum<kMT>(s, red);
     if (threadIdx.x == 0) out[blockIdx.x] = tot;
 }
 

@@ -411,17 +411,21 @@ std::string jit_source(bool dbl, int K, int S, int NV, const std::vector<KOp>& o
               << g.I(v, p) << "};\n";
     o << "  }\n";
     if (NV == 2 && n_gslots) {
-        // fixed-tree block reduction, one gradient slot at a time
-        o << "  __shared__ double red[" << kBlock << "];\n"
-          << "  const double gv[" << n_gslots << "] = {";
+        // block reduction in a fixed order: butterflies within each wave (every
+        // lane ends with the same bits), then thread s adds slot s's wave totals
+        // in wave order
+        constexpr int W = kBlock / 64;
+        o << "  __shared__ double red[" << W * n_gslots << "];\n"
+          << "  double gv[" << n_gslots << "] = {";
         for (uint32_t s = 0; s < n_gslots; ++s) o << (s ? ", " : "") << "g" << s;
         o << "};\n"
           << "#pragma unroll\n  for (int s = 0; s < " << n_gslots << "; ++s) {\n"
-          << "    red[tid] = gv[s];\n    __syncthreads();\n"
-          << "    for (int w = " << kBlock / 2 << "; w > 0; w >>= 1) {\n"
-          << "      if (tid < w) red[tid] += red[tid + w];\n      __syncthreads();\n    }\n"
-          << "    if (tid == 0) gpart[(u64)blockIdx.x * " << n_gslots << " + s] = red[0];\n"
-          << "    __syncthreads();\n  }\n";
+          << "#pragma unroll\n    for (int d = 32; d > 0; d >>= 1) gv[s] += __shfl_xor(gv[s], d);\n"
+          << "    if ((tid & 63) == 0) red[s * " << W << " + (tid >> 6)] = gv[s];\n  }\n"
+          << "  __syncthreads();\n"
+          << "  if (tid < " << n_gslots << ") {\n    double r = red[tid * " << W << "];\n"
+          << "#pragma unroll\n    for (int w = 1; w < " << W << "; ++w) r += red[tid * " << W << " + w];\n"
+          << "    gpart[(u64)blockIdx.x * " << n_gslots << " + tid] = r;\n  }\n";
     }
     o << "}\n";
     return o.str();

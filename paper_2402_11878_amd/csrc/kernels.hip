@@ -730,6 +730,35 @@ window_lds_kernel(const PassArgs<T> a, const LdsMap m, uint32_t cpt, uint32_t ml
     }
 }
 
+// Sums a and b over a block of NT threads in a fixed order: butterflies
+// within each wave (every lane ends with the same bits, addition being
+// commutative), then thread 0 adds the wave totals in wave order.  wsum holds
+// 2 NT / 64 doubles of LDS that no thread reads any more; the totals are
+// valid in thread 0 only.  Every thread of the block must call it.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* wsum) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int t = threadIdx.x;
+    if ((t & 63) == 0) {
+        wsum[t >> 6] = a;
+        wsum[NT / 64 + (t >> 6)] = b;
+    }
+    __syncthreads();
+    if (t == 0) {
+        a = wsum[0];
+        b = wsum[NT / 64];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) {
+            a += wsum[w];
+            b += wsum[NT / 64 + w];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- H psi
 // Block = one tile of 2^tb amplitudes at a time (grid-stride over tiles);
 // thread t owns local indices r*TPT + t, r < R.
@@ -739,7 +768,7 @@ hpsi_kernel(int n, int tb, uint32_t tpb, const typename VecOf<T>::type* __restri
             typename VecOf<T>::type* __restrict__ lam, const GroupDesc* __restrict__ groups,
             uint32_t n_groups, const TermDesc<T>* __restrict__ terms, double* __restrict__ part) {
     using V = typename VecOf<T>::type;
-    __shared__ double red[2][kBlock];
+    __shared__ double red[2 * kBlock / 64];
     const int tid = threadIdx.x;
     const int tpt = (1 << tb) / R;  // threads per tile
     const uint64_t n_tiles = 1ull << (n - tb);
@@ -808,19 +837,10 @@ hpsi_kernel(int n, int tb, uint32_t tpb, const typename VecOf<T>::type* __restri
             n_acc += (double)n_t;
         }
     }
-    red[0][tid] = e_acc;
-    red[1][tid] = n_acc;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            red[0][tid] += red[0][tid + w];
-            red[1][tid] += red[1][tid + w];
-        }
-        __syncthreads();
-    }
+    block_sum2<kBlock>(e_acc, n_acc, red);
     if (tid == 0) {
-        part[2 * blockIdx.x + 0] = red[0][0];
-        part[2 * blockIdx.x + 1] = red[1][0];
+        part[2 * blockIdx.x + 0] = e_acc;
+        part[2 * blockIdx.x + 1] = n_acc;
     }
 }
 
@@ -960,9 +980,9 @@ __device__ __forceinline__ void hwin_body(const HwDesc& w, uint64_t n_cosets, ui
     // immediate offsets of LDS reads: the class coefficients of the current
     // coset (after the last coset, the block reduction), their thread-part z
     // bits, then the psi coset.
-    constexpr size_t kTabBytes = kHwMaxClasses * sizeof(V) > 2 * kHwThreads * sizeof(double)
+    constexpr size_t kTabBytes = kHwMaxClasses * sizeof(V) > 2 * (kHwThreads / 64) * sizeof(double)
                                      ? kHwMaxClasses * sizeof(V)
-                                     : 2 * kHwThreads * sizeof(double);
+                                     : 2 * (kHwThreads / 64) * sizeof(double);
     constexpr size_t kZtOff = kTabBytes, kSpOff = kTabBytes + kHwMaxClasses * sizeof(uint32_t);
     static_assert(kSpOff % 16 == 0, "psi coset alignment");
     __shared__ __align__(16) unsigned char lds[kSpOff + (1 << kHwBits) * sizeof(V)];
@@ -1068,19 +1088,10 @@ __device__ __forceinline__ void hwin_body(const HwDesc& w, uint64_t n_cosets, ui
         __syncthreads();  // the next coset overwrites both LDS tables
     }
     if (!EONLY && !last) return;
-    red[t] = e_acc;
-    red[kHwThreads + t] = n_acc;
-    __syncthreads();
-    for (int s2 = kHwThreads / 2; s2 > 0; s2 >>= 1) {
-        if (t < s2) {
-            red[t] += red[t + s2];
-            red[kHwThreads + t] += red[kHwThreads + t + s2];
-        }
-        __syncthreads();
-    }
+    block_sum2<kHwThreads>(e_acc, n_acc, red);  // the loop's last barrier freed the class table
     if (t == 0) {
-        *e_out = red[0];
-        *n_out = red[kHwThreads];
+        *e_out = e_acc;
+        *n_out = n_acc;
     }
 }
 
@@ -1128,7 +1139,7 @@ __global__ void __launch_bounds__(kBlock)
 expect_term_kernel(int n, uint32_t cpt, const typename VecOf<T>::type* __restrict__ psi, uint64_t x, uint64_t z,
                    uint32_t hbit, T cre, T cim, double* __restrict__ part) {
     using V = typename VecOf<T>::type;
-    __shared__ double red[2][kBlock];
+    __shared__ double red[2 * kBlock / 64];
     const int tid = threadIdx.x;
     const uint64_t count = (x == 0) ? (1ull << n) : (1ull << (n - 1));
     const uint64_t hmask = (x == 0) ? 0 : ((1ull << hbit) - 1);
@@ -1156,19 +1167,10 @@ expect_term_kernel(int n, uint32_t cpt, const typename VecOf<T>::type* __restric
             n_acc += (double)(p.x * p.x + p.y * p.y + q.x * q.x + q.y * q.y);
         }
     }
-    red[0][tid] = v_acc;
-    red[1][tid] = n_acc;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            red[0][tid] += red[0][tid + w];
-            red[1][tid] += red[1][tid + w];
-        }
-        __syncthreads();
-    }
+    block_sum2<kBlock>(v_acc, n_acc, red);
     if (tid == 0) {
-        part[2 * blockIdx.x + 0] = red[0][0];
-        part[2 * blockIdx.x + 1] = red[1][0];
+        part[2 * blockIdx.x + 0] = v_acc;
+        part[2 * blockIdx.x + 1] = n_acc;
     }
 }
 
@@ -1198,20 +1200,15 @@ __global__ void __launch_bounds__(kBlock) copy_kernel(const V* __restrict__ src,
 __global__ void __launch_bounds__(kBlock)
 reduce_kernel(const double* __restrict__ part, uint32_t nblocks, uint32_t nslots,
               const int32_t* __restrict__ map, double* __restrict__ out, int accumulate) {
-    __shared__ double red[kBlock];
+    __shared__ double red[2 * kBlock / 64];
     const int tid = threadIdx.x;
     const uint32_t s = blockIdx.x;
-    double acc = 0.0;
+    double acc = 0.0, unused = 0.0;
     for (uint32_t i = tid; i < nblocks; i += kBlock) acc += part[(uint64_t)i * nslots + s];
-    red[tid] = acc;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
+    block_sum2<kBlock>(acc, unused, red);
     if (tid == 0) {
         const int idx = map ? map[s] : (int)s;
-        out[idx] = accumulate > 0 ? out[idx] + red[0] : accumulate < 0 ? out[idx] - red[0] : red[0];
+        out[idx] = accumulate > 0 ? out[idx] + acc : accumulate < 0 ? out[idx] - acc : acc;
     }
 }
 

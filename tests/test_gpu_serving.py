@@ -39,6 +39,13 @@ def test_energy_fn_autograd():
     loss = 3.0 * EnergyFn.apply(th2, H, C, "c128", 0, ws) ** 2
     loss.backward()
     assert np.max(np.abs(th2.grad.numpy() - 6.0 * E_ref * g_ref)) <= 1e-8 * max(abs(6 * E_ref), 1)
+    # no gradient wanted: the forward sweep and the grouped energy only
+    from paper_2402_11878_amd.autograd import energy
+    with torch.no_grad():
+        E1 = energy(th, H, C, "c128", 0, ws)
+    E2 = EnergyFn.apply(th.detach(), H, C, "c128", 0, ws)
+    assert not E1.requires_grad and not E2.requires_grad
+    assert rel_err(E1.item(), E_ref) <= 1e-10 and rel_err(E2.item(), E_ref) <= 1e-10
     ws.clear()
 
 
