@@ -439,6 +439,7 @@ void plan_hwin(vqe_hamiltonian* h) {
                 best_cls = cls;
             }
         }
+        if (best < 0) return;  // cannot happen for a cover; the tile form stays
         win_of[g] = best;
         w_groups[best] += 1;
         w_classes[best] += best_cls;
