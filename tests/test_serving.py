@@ -254,3 +254,53 @@ def test_mid_batch_split_by_size():
     assert [srv.instances[i].footprint == 0 for i in range(5)] == [True, True, False, False, False]
     with pytest.raises(ValueError):
         _server(ex, 1 << 34, mid_n_max=20, mid_workers=0, mid_batch=True, mid_batch_n_max=16)
+
+
+def test_energy_fn_runs_the_adjoint_only_for_a_gradient(monkeypatch):
+    """autograd.energy / EnergyFn call the energy + gradient entry point only
+    when theta needs a gradient; otherwise the forward sweep and the grouped
+    energy (library calls stubbed: this checks the dispatch on the host)."""
+    import torch
+    from paper_2402_11878_amd import _lib, autograd
+
+    calls = []
+
+    class FakeState:
+        def __init__(self, k):
+            self.handle = k
+
+    class FakeWs:
+        def get(self, n, dtype, n_ckpt):
+            return [FakeState(k) for k in range(2 + n_ckpt)]
+
+    class FakeCircuit:
+        n, handle = 4, "C"
+
+    class FakeHamiltonian:
+        handle = "H"
+
+    def grad(psi, lam, c, th, h, ckpt=()):
+        calls.append("grad")
+        return 1.5, np.arange(len(th), dtype=np.float64)
+
+    monkeypatch.setattr(_lib, "vqe_energy_grad", grad)
+    monkeypatch.setattr(_lib, "vqe_state_set_basis", lambda s, b: calls.append("basis"))
+    monkeypatch.setattr(_lib, "vqe_apply_circuit", lambda s, c, th: calls.append("circuit"))
+    monkeypatch.setattr(_lib, "vqe_expect_pauli", lambda s, h, mode: (calls.append("energy"), (2.5, 1.0))[1])
+    ws, C, H = FakeWs(), FakeCircuit(), FakeHamiltonian()
+
+    th = torch.zeros(3, dtype=torch.float64, requires_grad=True)
+    E = autograd.energy(th, H, C, "c128", 0, ws)
+    assert calls == ["grad"] and E.item() == 1.5
+    E.backward()
+    assert th.grad.tolist() == [0.0, 1.0, 2.0]
+
+    for run in (lambda: autograd.energy(th.detach(), H, C, "c128", 0, ws),
+                lambda: autograd.EnergyFn.apply(th.detach(), H, C, "c128", 0, ws)):
+        calls.clear()
+        E = run()
+        assert calls == ["basis", "circuit", "energy"] and E.item() == 2.5 and not E.requires_grad
+    calls.clear()
+    with torch.no_grad():
+        E = autograd.energy(th, H, C, "c128", 0, ws)
+    assert calls == ["basis", "circuit", "energy"] and E.item() == 2.5
