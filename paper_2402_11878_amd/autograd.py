@@ -24,11 +24,16 @@ class Workspace:
     def __init__(self):
         self._cache = {}
 
-    def get(self, n, dtype, n_ckpt):
+    def get(self, n, dtype, n_ckpt, count=None):
+        """The first `count` (default 2 + n_ckpt: psi, lam and the
+        checkpoints) states of the entry for (n, dtype, n_ckpt) on the
+        current stream, allocated on first use."""
         key = (n, dtype, n_ckpt, torch.cuda.current_stream().cuda_stream)
-        if key not in self._cache:
-            self._cache[key] = [State(n, dtype) for _ in range(2 + n_ckpt)]
-        return self._cache[key]
+        states = self._cache.setdefault(key, [])
+        want = 2 + n_ckpt if count is None else count
+        while len(states) < want:
+            states.append(State(n, dtype))
+        return states[:want]
 
     def clear(self):
         for states in self._cache.values():
@@ -75,7 +80,7 @@ class EnergyFn(torch.autograd.Function):
 def _energy_only(theta, hamiltonian, circuit, dtype, ws):
     """E(theta) without the gradient: psi = U(theta)|0...0>, then the grouped
     energy <psi|H|psi>/<psi|psi>."""
-    psi = ws.get(circuit.n, dtype, 0)[0]
+    psi = ws.get(circuit.n, dtype, 0, count=1)[0]  # no lam: the energy needs psi only
     th = theta.detach().to("cpu", torch.float64).numpy()
     _lib.vqe_state_set_basis(psi.handle, 0)
     _lib.vqe_apply_circuit(psi.handle, circuit.handle, th)

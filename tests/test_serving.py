@@ -270,8 +270,8 @@ def test_energy_fn_runs_the_adjoint_only_for_a_gradient(monkeypatch):
             self.handle = k
 
     class FakeWs:
-        def get(self, n, dtype, n_ckpt):
-            return [FakeState(k) for k in range(2 + n_ckpt)]
+        def get(self, n, dtype, n_ckpt, count=None):
+            return [FakeState(k) for k in range(2 + n_ckpt if count is None else count)]
 
     class FakeCircuit:
         n, handle = 4, "C"
@@ -304,3 +304,33 @@ def test_energy_fn_runs_the_adjoint_only_for_a_gradient(monkeypatch):
     with torch.no_grad():
         E = autograd.energy(th, H, C, "c128", 0, ws)
     assert calls == ["basis", "circuit", "energy"] and E.item() == 2.5
+
+
+def test_workspace_grows_entries_on_demand(monkeypatch):
+    """Workspace.get allocates only the states asked for and reuses them: an
+    energy-only call takes psi alone, a later gradient call adds lam (and
+    checkpoints) to the same entry (allocation stubbed)."""
+    import types
+    import torch
+    from paper_2402_11878_amd import autograd
+
+    made = []
+
+    class FakeState:
+        def __init__(self, n, dtype):
+            made.append((n, dtype))
+
+        def free(self):
+            made.append("free")
+
+    monkeypatch.setattr(autograd, "State", FakeState)
+    monkeypatch.setattr(torch.cuda, "current_stream", lambda: types.SimpleNamespace(cuda_stream=7))
+    ws = autograd.Workspace()
+    (psi,) = ws.get(20, "c128", 0, count=1)
+    assert made == [(20, "c128")]
+    psi2, lam = ws.get(20, "c128", 0)
+    assert psi2 is psi and len(made) == 2
+    assert ws.get(20, "c128", 0, count=1)[0] is psi and len(made) == 2
+    assert len(ws.get(20, "c128", 2)) == 4 and len(made) == 6  # another entry: psi, lam, 2 checkpoints
+    ws.clear()
+    assert made.count("free") == 6
